@@ -1,0 +1,156 @@
+"""Oracle: the SQH Hamiltonian and its matrix-free product, written from Sec. II.A.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+Conventions (Sec. II.A):
+  * basis state |z> = |z_n> x ... x |z_1>, z = sum_i z_i 2^(i-1): qubit i is bit i-1
+    of the integer index (eq. (ztensor));
+  * |0> and |1> are the sigma^z eigenvectors with eigenvalues +1 and -1;
+  * sigma^y = [[0, -i], [i, 0]] (the standard matrix; the paper names it only).
+
+A Hamiltonian is H(t) = sum_terms m_l(t) * P_l with P_l a product of single-qubit
+Pauli matrices (eq. (SQH-Hamiltonian)) and m_l(t) = w_l * f_{sid_l}(s(t)) a real
+time-dependent coefficient (end of Sec. II.A).  The term's Pauli letters are read
+from two masks: bit q-1 set in ``x`` only -> sigma^x on qubit q, in ``z`` only ->
+sigma^z, in both -> sigma^y.
+
+The product H|psi> follows the paper's recipe literally: every term acts on every
+basis state |z> as a succession of single-qubit operations sigma^alpha |z_q>, which
+maps |z> to a phase times another basis state; the results are summed.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+_ONE = np.uint64(1)
+
+
+# ---------------------------------------------------------------------------
+# Path and schedules (eq. (aqc), eq. (nlpath), time-dependent m_l(t))
+# ---------------------------------------------------------------------------
+
+def path_s(path, t):
+    """Interpolation parameter s(t).  'linear': s = t/T (eq. (aqc));
+    'sin2': s = sin^2(pi t / 2T) (a smooth nonlinear speed profile)."""
+    T = path["T"]
+    if path["kind"] == "linear":
+        return t / T
+    if path["kind"] == "sin2":
+        return math.sin(math.pi * t / (2.0 * T)) ** 2
+    raise ValueError(f"unknown path {path['kind']!r}")
+
+
+def schedule_value(sched, t, path):
+    """Scalar f(t) that multiplies a term's weight."""
+    kind = sched["kind"]
+    if kind == "const":
+        return 1.0
+    if kind == "poly_s":
+        s = path_s(path, t)
+        lo, hi = sched["s_lo"], sched["s_hi"]
+        inside = (s >= lo) and ((s <= hi) if sched.get("hi_closed", False) else (s < hi))
+        if not inside:
+            return 0.0
+        val = 0.0
+        for d, c in enumerate(sched["coef"]):
+            val += c * s ** d
+        return val
+    if kind == "trig_t":
+        return sched["amp"] * math.cos(sched["omega"] * t + sched["phase"])
+    raise ValueError(f"unknown schedule {kind!r}")
+
+
+def coefficients(ham, t):
+    """m_l(t) = w_l * f_{sid_l}(t) for every term (float64 array)."""
+    f = [schedule_value(s, t, ham.path) for s in ham.scheds]
+    return np.array([ham.w[l] * f[ham.sid[l]] for l in range(len(ham.w))], dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# One Pauli string on all basis states
+# ---------------------------------------------------------------------------
+
+def pauli_letters(n, x, z):
+    """[(qubit, 'X'|'Y'|'Z'), ...] of the string encoded by the masks (x, z)."""
+    out = []
+    for q in range(1, n + 1):
+        b = 1 << (q - 1)
+        xb = bool(int(x) & b)
+        zb = bool(int(z) & b)
+        if xb and zb:
+            out.append((q, "Y"))
+        elif xb:
+            out.append((q, "X"))
+        elif zb:
+            out.append((q, "Z"))
+    return out
+
+
+def pauli_on_basis(n, letters):
+    """Image of every basis state under the string: P|z> = phase(z) |image(z)>.
+
+    Each single-qubit factor acts on bit q-1 of z:
+      sigma^x |0> = |1>,    sigma^x |1> = |0>
+      sigma^y |0> = i|1>,   sigma^y |1> = -i|0>
+      sigma^z |0> = |0>,    sigma^z |1> = -|1>
+    Returns (image, phase) as arrays over z = 0 .. 2^n - 1.
+    """
+    N = 1 << n
+    z = np.arange(N, dtype=np.uint64)
+    image = z.copy()
+    phase = np.ones(N, dtype=np.complex128)
+    for q, a in letters:
+        bit = np.uint64(q - 1)
+        zq = (z >> bit) & _ONE            # the qubit's value in the *input* state
+        if a == "X":
+            image ^= (_ONE << bit)
+        elif a == "Y":
+            image ^= (_ONE << bit)
+            phase *= np.where(zq == 0, 1j, -1j)
+        elif a == "Z":
+            phase *= np.where(zq == 0, 1.0, -1.0)
+        else:
+            raise ValueError(a)
+    return image, phase
+
+
+def apply_pauli(psi, n, x, z, coef=1.0):
+    """coef * P|psi> with P the string (x, z):  sum_z psi_z coef phase(z) |image(z)>."""
+    image, phase = pauli_on_basis(n, pauli_letters(n, x, z))
+    out = np.zeros_like(psi, dtype=np.complex128)
+    # image is a permutation of the basis, so a plain scatter is exact
+    out[image.astype(np.int64)] = coef * phase * psi
+    return out
+
+
+def apply_h(ham, t, psi, shift=0.0):
+    """(H(t) - shift) |psi>, H(t) = sum_l m_l(t) P_l (eq. (SQH-Hamiltonian))."""
+    m = coefficients(ham, t)
+    out = np.zeros(psi.shape, dtype=np.complex128)
+    for l in range(len(m)):
+        if m[l] == 0.0:
+            continue
+        out += apply_pauli(psi, ham.n, ham.x[l], ham.z[l], m[l])
+    if shift != 0.0:
+        out -= shift * psi
+    return out
+
+
+def diagonal(ham, t):
+    """Diagonal of H(t) over all basis states: sum over the terms without a flip
+    (x = 0) of m_l(t) times their sign on |z>."""
+    N = 1 << ham.n
+    m = coefficients(ham, t)
+    d = np.zeros(N, dtype=np.float64)
+    for l in range(len(m)):
+        if int(ham.x[l]) != 0 or m[l] == 0.0:
+            continue
+        _, phase = pauli_on_basis(ham.n, pauli_letters(ham.n, 0, ham.z[l]))
+        d += m[l] * phase.real
+    return d
+
+
+def is_diagonal_term(ham, l):
+    return int(ham.x[l]) == 0
