@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the time-stepped Schroedinger evolution on one MI355X.
+
+Workload: the Sherrington-Kirkpatrick annealing run with n = 30 qubits
+(2^30 amplitudes, 8 GiB per complex64 vector): H(s) = (1 - s) H_x + s H_SK,
+H_x = sum (1 - sigma^x)/2, H_SK = sum J_ij sz_i sz_j + sum h_i sz_i with
+J_ij ~ N(0, 1/n), h_i ~ N(0, 0.1), s(t) = sin^2(pi t / 2T), T = 30, psi(0) = |+>^30.
+The integrator is the one-evaluation 4th-order predictor-corrector (Sec. II.B of
+the paper) with a centred spectral shift; the step h comes from the stability
+guard h * rho <= 0.1.  Complex64 state, float32 products, float64 reductions.
+
+One benchmark step = one aqc_evolve call over the next window of `--window`
+integration steps of the path (RK4 bootstrap, predictor-corrector steps, norm
+guard, shift phase) followed by the ground-state fidelity at T.  The metric is
+amplitude updates per second: 2^n x integration steps / seconds.
+
+Prints one JSON line (rank 0, N = 1 only)."""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(seconds_target=15.0):
+    """The oracle (NumPy complex128, one thread) on the same workload family at
+    n = 16, for a bounded number of predictor-corrector steps."""
+    import numpy as np
+    from oracle import integrate, sqh
+    from paper_1311_3938_amd import instances as I
+    n = 16
+    inst = I.workload_sk_sin2(n=n, T=30.0, seed=I.seed_for(2))
+    d0 = sqh.diagonal(inst, inst.path["T"])
+    shift = 0.5 * (min(0.0, d0.min()) + max(float(n), d0.max()))
+    psi = I.plus_state(n)
+    h = 30.0 / 8000
+    t0 = time.perf_counter()
+    seg = integrate.Segment(inst, psi, 0.0, h, "pc4", shift)
+    steps = 0
+    while True:
+        seg.advance(1)
+        steps += 1
+        if steps >= 8 and time.perf_counter() - t0 > seconds_target:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": (1 << n) * steps / dt, "unit": "amp-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"SK + transverse field, sin^2 path, n={n} (same generator, 2^{n} amplitudes), "
+                      f"pc4 with shift, {steps} steps incl. 3 RK4 bootstrap steps, {dt:.1f} s, "
+                      "NumPy complex128 single thread; n=30 does not fit the oracle"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=30)
+    ap.add_argument("--window", type=int, default=200, help="integration steps per bench step")
+    ap.add_argument("--dtype", choices=["c64", "c128"], default="c64")
+    ap.add_argument("--method", choices=["pc4", "rk4"], default="pc4")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the complex128 comparison of the first window")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB copy (for scaling hardware byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1311_3938_amd import engine
+    from paper_1311_3938_amd import instances as I
+
+    n = args.n
+    N = 1 << n
+    T = 30.0
+    tdt = torch.complex64 if args.dtype == "c64" else torch.complex128
+    es = 8 if args.dtype == "c64" else 16
+    inst = I.workload_sk_sin2(n=n, T=T, seed=I.seed_for(2))
+    ctx = engine.Context(0)
+    ham = engine.Hamiltonian(ctx, inst)
+    lo, hi = ham.spectral_bounds(0.0, T)
+    rho = 0.5 * (hi - lo)
+    k_total = int(math.ceil(T * rho / 0.1))
+    h = T / k_total
+    W = args.window
+    log(f"n={n} dtype={args.dtype} method={args.method} enclosure=[{lo:.3f},{hi:.3f}] "
+        f"rho={rho:.3f} K_total={k_total} h={h:.6g} window={W}")
+
+    psi = torch.full((N,), 1.0 / math.sqrt(N), dtype=tdt, device="cuda")
+    opts = dict(method=args.method, n_steps=W, shift="center", check_every=W,
+                norm_tol=1e-2, stab_limit=0.2155)
+    o, _, _ = engine.evolve_opts(**opts)
+    ws = engine.workspace(ctx, engine.evolve_workspace_bytes(ham, engine.dtype_code(psi), o))
+    info = ham.info()
+    log(f"plan: {info}; workspace {ws.numel() / 2**30:.1f} GiB")
+
+    n_windows_total = k_total // W
+
+    def bench_step(i):
+        w = i % n_windows_total
+        if w == 0 and i > 0:
+            psi.fill_(1.0 / math.sqrt(N))
+        t_a, t_b = w * W * h, (w + 1) * W * h
+        st, _ = engine.evolve(ctx, ham, psi, t_a, t_b, ws=ws, **opts)
+        mass, emin = engine.ground_mass(ctx, ham, T, psi)
+        return st, mass
+
+    for i in range(args.warmup):
+        bench_step(i)
+        log(f"warmup step {i} done")
+    engine.profile_enable(ctx, True)
+    engine.profile_reset(ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for i in range(args.steps):
+        stats.append(bench_step(args.warmup + i))
+        log(f"step {i} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = engine.profile_read(ctx)
+    engine.profile_enable(ctx, False)
+    int_steps = sum(s[0]["steps"] for s in stats)
+    value = N * int_steps / elapsed
+    last_ms, last_n, last_bytes = prof["last_pass"]
+    high_ms, high_n, high_bytes = prof["high_pass"]
+    peak = 8.0e12
+    achieved = last_bytes / (last_ms * 1e-3) if last_ms > 0 else 0.0
+    result = {
+        "metric": "amp-updates/s",
+        "value": value,
+        "unit": "amp-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": f"SK spin glass n={n} (2^{n} amplitudes), transverse-field start, "
+                        f"sin^2 path, T={T:g}; {args.method} with centred shift, "
+                        f"{args.dtype} state, fp64 reductions",
+            "n_qubits": n, "integration_steps_per_step": W, "h": h, "k_total": k_total,
+            "tile_passes_per_matvec": info["n_passes"][0 if args.dtype == "c64" else 1],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved / 1e9,
+            "peak": peak / 1e9,
+            "unit": "GB/s",
+            "frac": achieved / peak,
+            "traffic": None,
+            "kernel": "k_pass<last> (diagonal + low flips + fused stage update)",
+            "avg_launch_ms": last_ms / max(last_n, 1),
+            "algorithmic_bytes_per_launch": last_bytes / max(last_n, 1),
+        },
+        "high_pass": {
+            "launches": high_n, "avg_launch_ms": high_ms / max(high_n, 1),
+            "achieved_GBps": (high_bytes / (high_ms * 1e-3) / 1e9) if high_ms > 0 else None,
+        },
+        "effective_frac": None,
+        "fidelity_T": stats[-1][1],
+    }
+    # whole-step traffic at the algorithmic minimum of this plan vs peak
+    step_bytes = (last_bytes + high_bytes) / max(int_steps, 1)
+    result["effective_frac"] = (step_bytes * int_steps / elapsed) / peak
+    result["bytes_per_amp_step"] = step_bytes / N
+
+    del ws
+    torch.cuda.empty_cache()
+    if args.copy_calib:
+        a = torch.empty(1 << 27, dtype=torch.complex64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        result["copy_calib_bytes"] = {"read": a.numel() * 8, "write": a.numel() * 8}
+        del a, b
+    if not args.no_accuracy and args.dtype == "c64":
+        # first window at complex64 and at complex128 from the same |+> state
+        p64 = torch.full((N,), 1.0 / math.sqrt(N), dtype=torch.complex64, device="cuda")
+        engine.evolve(ctx, ham, p64, 0.0, W * h, **opts)
+        f64, _ = engine.ground_mass(ctx, ham, T, p64)
+        p128 = torch.full((N,), 1.0 / math.sqrt(N), dtype=torch.complex128, device="cuda")
+        engine.evolve(ctx, ham, p128, 0.0, W * h, **opts)
+        f128, _ = engine.ground_mass(ctx, ham, T, p128)
+        p64c = p64.to(torch.complex128)
+        del p64
+        a2 = engine.norm2(ctx, p64c)
+        b2 = engine.norm2(ctx, p128)
+        ov = engine.overlap(ctx, p64c, p128)
+        dpsi = math.sqrt(max(a2 + b2 - 2.0 * ov.real, 0.0))
+        result["accuracy"] = {"window": [0.0, W * h], "dpsi_c64_vs_c128": dpsi,
+                              "dF_c64_vs_c128": abs(f64 - f128), "F_c128": f128}
+        del p64c, p128
+        torch.cuda.empty_cache()
+        log(f"accuracy: {result['accuracy']}")
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host")
+        result["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,253 @@
+/*
+ * aqc.h -- C ABI of the MI355X engine for the time-dependent Schroedinger
+ * equation with Hamiltonians in compact Pauli-string ("SQH") form.
+ *
+ * Method: M. Hofmann, G. Schaller, "Probing nonlinear adiabatic paths with a
+ * universal integrator", arXiv:1311.3938.
+ *   - state and basis:   Sec. II.A, eq. (ztensor), eq. (expansion)
+ *   - Hamiltonian form:  Sec. II.A, eq. (SQH-Hamiltonian), time-dependent
+ *                        coefficients m_l(t) at the end of Sec. II.A
+ *   - paths:             Sec. II.B eq. (aqc); Sec. IV.A eq. (nlpath)
+ *   - time stepping:     Sec. II.B eq. (schroedinger), the 4th-order
+ *                        predictor-corrector with one H|psi> per step
+ *   - success measures:  Sec. III.B (P_1(T) = |<psi(T)|w>|^2, energy E(T))
+ *
+ * Conventions shared by every entry point
+ *   - qubit q (1-based) is bit q-1 of the basis index z (eq. (ztensor));
+ *     |0>, |1> are the sigma^z eigenvectors (+1, -1).
+ *   - a state of n qubits is 2^n complex amplitudes, interleaved (re, im),
+ *     contiguous, in device memory: AQC_C64 = 2 x float32 (8 bytes),
+ *     AQC_C128 = 2 x float64 (16 bytes).  Pointers must be 16-byte aligned.
+ *     The caller owns every state and workspace buffer; the library never
+ *     allocates state-sized memory.
+ *   - a Pauli string is two masks: bit q-1 of x set <=> sigma^x or sigma^y on
+ *     qubit q; bit q-1 of z set <=> sigma^z or sigma^y on qubit q (sigma^y sets
+ *     both).  sigma^y = [[0,-i],[i,0]].
+ *   - hbar = 1; times and energies share one unit.
+ *   - every call returns an aqc_status; on failure aqc_last_error() gives a
+ *     message (per calling thread).  No call throws across the ABI.  All
+ *     device work is enqueued on the context's stream; calls that return host
+ *     scalars (reductions, evolve statistics) synchronise that stream.
+ *   - floating point: AQC_C64 keeps states in complex64 and forms H|psi> and
+ *     the stage updates in float32; every norm, overlap, energy, error
+ *     estimate, step-size decision and phase is computed in float64.  AQC_C128
+ *     is float64 throughout.
+ */
+#ifndef AQC_H
+#define AQC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int aqc_status;
+#define AQC_OK         0
+#define AQC_EINVAL    -1  /* bad argument (null pointer, size, mask, value)   */
+#define AQC_ENOMEM    -2  /* caller-provided workspace too small               */
+#define AQC_EDEVICE   -3  /* HIP runtime error                                 */
+#define AQC_EUNSTABLE -4  /* norm guard tripped, or step above stability limit */
+#define AQC_ENOTSUP   -5  /* unsupported size or dtype (n > 34)                */
+#define AQC_EBUSY     -6  /* no free slot or memory in a batch                 */
+
+typedef enum { AQC_C64 = 0, AQC_C128 = 1 } aqc_dtype;
+
+/* ---- schedules and paths (time dependence of the coefficients) --------- */
+typedef enum {
+  AQC_SCHED_CONST  = 0,  /* f = 1                                            */
+  AQC_SCHED_POLY_S = 1,  /* f = sum_{d<=degree} coef[d] s^d on s_lo <= s < s_hi
+                            (s <= s_hi when hi_closed), 0 outside             */
+  AQC_SCHED_TRIG_T = 2   /* f = amp * cos(omega t + phase)                   */
+} aqc_sched_kind;
+
+typedef struct {
+  int32_t kind;       /* aqc_sched_kind                                      */
+  int32_t degree;     /* POLY_S: 0..7                                         */
+  int32_t hi_closed;  /* POLY_S: 1 => the window includes s_hi               */
+  int32_t reserved;
+  double coef[8];
+  double s_lo, s_hi;  /* POLY_S window (use +-INFINITY for none)             */
+  double amp, omega, phase;
+} aqc_sched;
+
+typedef enum {
+  AQC_PATH_LINEAR = 0,  /* s(t) = t / T                 (eq. (aqc))          */
+  AQC_PATH_SIN2   = 1   /* s(t) = sin^2(pi t / (2 T))                        */
+} aqc_path_kind;
+
+typedef struct {
+  int32_t kind;
+  int32_t reserved;
+  double T;
+} aqc_path;
+
+typedef struct aqc_ctx aqc_ctx;
+typedef struct aqc_ham aqc_ham;
+
+/* ---- context ------------------------------------------------------------ */
+/* Binds a device and a HIP stream (hipStream_t passed as void*, NULL = the
+ * default stream).  The stream is borrowed, never destroyed.  The context owns
+ * small device buffers for reduction partials (a few MB).                    */
+aqc_status aqc_create(int device, void* stream, aqc_ctx** out);
+aqc_status aqc_destroy(aqc_ctx* ctx);
+aqc_status aqc_set_stream(aqc_ctx* ctx, void* stream);
+const char* aqc_last_error(void);
+const char* aqc_version(void);
+
+/* ---- Hamiltonian -------------------------------------------------------- */
+/* aqc_build_hamiltonian: H(t) = sum_l weight[l] * f_{sched_id[l]}(t) * P_l
+ * (eq. (SQH-Hamiltonian) with time-dependent coefficients), P_l the Pauli
+ * string (x_mask[l], z_mask[l]).  Inputs are host arrays of n_terms entries and
+ * are copied; the caller keeps ownership.  Terms with equal (x, z, sched_id)
+ * are merged; terms with x = 0 form the diagonal, the others are grouped by
+ * their flip pattern x.  Errors: EINVAL for n_qubits < 1, masks >= 2^n,
+ * non-finite weights, a sched_id outside [0, n_sched), n_sched > 16, bad
+ * schedule or path data; ENOTSUP for n_qubits > 34.  The compiled tables live
+ * in library-owned device memory (small: O(terms + 2^(n-13) n) entries) until
+ * aqc_ham_free.  The context's stream is used for uploads.                  */
+aqc_status aqc_build_hamiltonian(aqc_ctx* ctx, int n_qubits, int64_t n_terms,
+                                 const uint64_t* x_mask, const uint64_t* z_mask,
+                                 const double* weight, const int32_t* sched_id,
+                                 int n_sched, const aqc_sched* scheds,
+                                 const aqc_path* path, aqc_ham** out);
+aqc_status aqc_ham_free(aqc_ham* ham);
+
+typedef struct {
+  int32_t n_qubits;
+  int32_t n_terms;        /* after merging                                    */
+  int32_t n_diag_terms;
+  int32_t n_groups;       /* distinct flip patterns x != 0                    */
+  int32_t n_passes[2];    /* tile passes per H|psi>, [C64, C128]              */
+  int32_t tile_bits[2];   /* bits held on chip by the last pass, [C64, C128]  */
+  double spec_lo, spec_hi;/* spectral enclosure of H(t) over [0, T]          */
+} aqc_ham_info_t;
+aqc_status aqc_ham_info(const aqc_ham* ham, aqc_ham_info_t* out);
+
+/* Spectral enclosure [lo, hi] of H(t) on [t0, t1]: exact minimum and maximum of
+ * each schedule's diagonal part (device reduction) combined with the triangle
+ * inequality for the flip terms, over a grid of 257 times (Weyl bound).      */
+aqc_status aqc_spectral_bounds(aqc_ctx* ctx, const aqc_ham* ham, double t0, double t1,
+                               double* lo, double* hi);
+
+/* ---- H|psi> ------------------------------------------------------------ */
+/* psi_out = H(t) psi_in (the matrix-free product of Sec. II.A).  Device
+ * pointers to 2^n amplitudes of `dtype`; psi_in != psi_out (EINVAL).  When the
+ * Hamiltonian needs more than one tile pass, `workspace` must hold one state
+ * vector (aqc_apply_workspace_bytes); otherwise it may be NULL.             */
+size_t aqc_apply_workspace_bytes(const aqc_ham* ham, int dtype);
+aqc_status aqc_apply(aqc_ctx* ctx, const aqc_ham* ham, double t, const void* psi_in,
+                     void* psi_out, int dtype, void* workspace, size_t ws_bytes);
+
+/* ---- time evolution ----------------------------------------------------- */
+#define AQC_METHOD_PC4 0   /* one-evaluation 4th-order predictor-corrector   */
+#define AQC_METHOD_RK4 1   /* classical 4-stage Runge-Kutta                  */
+
+#define AQC_SHIFT_VALUE  0 /* subtract opts.shift from H                     */
+#define AQC_SHIFT_CENTER 1 /* subtract the midpoint of the spectral enclosure */
+
+typedef struct {
+  int32_t method;       /* AQC_METHOD_*                                       */
+  int32_t n_steps;      /* > 0: fixed steps h = (t1-t0)/n_steps; 0: adaptive  */
+  int32_t shift_mode;   /* AQC_SHIFT_*                                        */
+  int32_t check_every;  /* norm guard period in steps (0 = off)              */
+  double shift;         /* used with AQC_SHIFT_VALUE                          */
+  double norm_tol;      /* guard: | ||psi||^2 - ||psi0||^2 | <= norm_tol      */
+  double stab_limit;    /* pc4: refuse h*rho above this (<= 0: no check)     */
+  /* adaptive pc4 (n_steps == 0): Milne estimate per step, windows of
+   * `window` steps, reject above atol (h/2), grow below atol/64 (2h)         */
+  double atol, h0, hmin, hmax;
+  int32_t window;
+  int32_t n_replay;     /* > 0: replay these segments instead of adapting    */
+  const double* replay; /* host, n_replay x (t_start, h, n_steps)             */
+  double* record;       /* host, record_cap x (t_start, h, n_steps), or NULL  */
+  int32_t record_cap;
+  int32_t compensated;  /* AQC_C64: 1 (recommended) keeps the state as a
+                           float32 pair hi + lo updated by exact two-sums, so
+                           rounding of the stored state does not accumulate
+                           (one more vector of workspace, two more vector
+                           passes per step); 0 stores y in complex64 only.
+                           Ignored for AQC_C128.                              */
+} aqc_evolve_opts;
+
+typedef struct {
+  int64_t steps;        /* accepted steps                                     */
+  int64_t rejected;     /* steps undone by the adaptive controller            */
+  int64_t matvecs;      /* evaluations of H|psi>                              */
+  int32_t n_segments;   /* segments written to opts.record (or needed)        */
+  int32_t status_step;  /* step at which the guard tripped (-1 if none)       */
+  double t_reached;
+  double h_last;
+  double shift_used;
+  double rho;           /* half-width of the enclosure after the shift       */
+  double norm2_initial;
+  double norm2_final;
+  double max_err;       /* largest Milne estimate of accepted pc4 steps      */
+} aqc_evolve_stats;
+
+/* Bytes of device workspace aqc_evolve needs for this Hamiltonian and dtype:
+ * 5 state vectors for pc4, 2 for rk4, one more when H|psi> takes several
+ * tile passes, one more for a compensated complex64 state, and one (two when
+ * compensated) for the adaptive controller's checkpoint.                   */
+size_t aqc_evolve_workspace_bytes(const aqc_ham* ham, int dtype, const aqc_evolve_opts* opts);
+
+/* aqc_evolve: psi holds psi(t0) on entry and psi(t1) on return (in place).
+ * Solves i d psi/dt = H(t) psi (eq. (schroedinger)) on the grid
+ * t_k = t_start + k h of each segment.  pc4: three RK4 steps start every
+ * segment, then one H|psi> per step.  A constant shift c is subtracted from H
+ * and exp(-i c (t1 - t0)) is multiplied back in at the end.  Synchronous: the
+ * statistics are final on return.  EUNSTABLE: the norm guard tripped or
+ * h * rho > stab_limit; psi then holds the last state reached and
+ * stats->t_reached says when.  ENOMEM: ws_bytes too small.                  */
+aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* ham, void* psi, int dtype, double t0,
+                      double t1, const aqc_evolve_opts* opts, void* workspace,
+                      size_t ws_bytes, aqc_evolve_stats* stats);
+
+/* ---- reductions (float64) ---------------------------------------------- */
+/* sum_z |psi_z|^2 */
+aqc_status aqc_norm2(aqc_ctx* ctx, const void* psi, int dtype, int n_qubits, double* out);
+/* <phi|psi> = sum_z conj(phi_z) psi_z */
+aqc_status aqc_overlap(aqc_ctx* ctx, const void* phi, const void* psi, int dtype,
+                       int n_qubits, double* re, double* im);
+
+#define AQC_TARGET_STATE      0  /* target: device state |phi>; |<phi|psi>|^2   */
+#define AQC_TARGET_BASIS_LIST 1  /* target: host int64 list of basis states;
+                                    sum of |psi_z|^2 over the distinct entries  */
+/* Success probability P_1 (Sec. III.B). */
+aqc_status aqc_fidelity(aqc_ctx* ctx, const void* psi, int dtype, int n_qubits,
+                        int target_kind, const void* target, int64_t target_len,
+                        double* out);
+/* Mass of psi on the ground set of the diagonal part of H(t):
+ * {z : E(z) <= E_min + rel_tol * max(1, |E_min|)}; also returns E_min.  For a
+ * problem Hamiltonian with a unique solution this is P_1(T) (Sec. III.B).   */
+aqc_status aqc_ground_mass(aqc_ctx* ctx, const aqc_ham* ham, double t, const void* psi,
+                           int dtype, double rel_tol, double* mass, double* e_min);
+/* <psi|H(t)|psi> (real), the energy E(T) of Sec. III.B.  Workspace as for
+ * aqc_apply.                                                                */
+aqc_status aqc_energy(aqc_ctx* ctx, const aqc_ham* ham, double t, const void* psi,
+                      int dtype, void* workspace, size_t ws_bytes, double* out);
+
+/* ---- instrumentation ----------------------------------------------------- */
+/* Kernel timing with HIP events recorded on the context's stream around every
+ * tile-pass launch (the events add no synchronisation).  Classes:
+ *   AQC_PROF_HIGH_PASS  passes that apply high-qubit flips and write the partial
+ *                       product;
+ *   AQC_PROF_LAST_PASS  the last pass: diagonal, low flips and the fused stage
+ *                       update.
+ * aqc_profile_read synchronises the stream and returns the summed kernel time
+ * (ms), the number of launches and their algorithmic bytes (each vector a
+ * launch must read or write, counted once: the tile source, the partial
+ * product in and out, and the stage update's streamed inputs and outputs)
+ * since the last reset.                                                     */
+#define AQC_PROF_HIGH_PASS 0
+#define AQC_PROF_LAST_PASS 1
+aqc_status aqc_profile_enable(aqc_ctx* ctx, int on);
+aqc_status aqc_profile_reset(aqc_ctx* ctx);
+aqc_status aqc_profile_read(aqc_ctx* ctx, int kind, double* total_ms, int64_t* launches,
+                            double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AQC_H */

@@ -154,3 +154,47 @@ def diagonal(ham, t):
 
 def is_diagonal_term(ham, l):
     return int(ham.x[l]) == 0
+
+
+def apply_h_rows(ham, t, values_at, rows, shift=0.0):
+    """Selected entries of (H(t) - shift)|psi> without forming the whole vector.
+
+    ``values_at(idx)`` returns psi at the basis states ``idx`` (int64 array);
+    ``rows`` are the output indices y.  Every term maps |z> to phase(z)|z ^ x>
+    (the per-qubit rule of ``pauli_on_basis``), so entry y of P|psi> is
+    phase(y ^ x) psi[y ^ x]."""
+    rows = np.asarray(rows, dtype=np.uint64)
+    m = coefficients(ham, t)
+    out = np.zeros(rows.shape, dtype=np.complex128)
+    for l in range(len(m)):
+        if m[l] == 0.0:
+            continue
+        x = np.uint64(int(ham.x[l]))
+        src = rows ^ x
+        phase = np.ones(rows.shape, dtype=np.complex128)
+        for q, a in pauli_letters(ham.n, ham.x[l], ham.z[l]):
+            bit = np.uint64(q - 1)
+            zq = (src >> bit) & _ONE
+            if a == "Y":
+                phase *= np.where(zq == 0, 1j, -1j)
+            elif a == "Z":
+                phase *= np.where(zq == 0, 1.0, -1.0)
+        out += m[l] * phase * values_at(src.astype(np.int64))
+    if shift != 0.0:
+        out -= shift * values_at(rows.astype(np.int64))
+    return out
+
+
+def diagonal_rows(ham, t, rows):
+    """Entries of the diagonal of H(t) at the basis states ``rows``."""
+    rows = np.asarray(rows, dtype=np.uint64)
+    m = coefficients(ham, t)
+    d = np.zeros(rows.shape, dtype=np.float64)
+    for l in range(len(m)):
+        if int(ham.x[l]) != 0 or m[l] == 0.0:
+            continue
+        sign = np.ones(rows.shape)
+        for q, a in pauli_letters(ham.n, 0, ham.z[l]):
+            sign *= np.where(((rows >> np.uint64(q - 1)) & _ONE) == 0, 1.0, -1.0)
+        d += m[l] * sign
+    return d

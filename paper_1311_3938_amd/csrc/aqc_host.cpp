@@ -1,0 +1,1413 @@
+// Host runtime of the C ABI in include/aqc.h: Hamiltonian compiler, tile-pass
+// planner, split diagonal tables, integrator driver and reductions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/aqc.h"
+#include "aqc_internal.h"
+
+using namespace aqc;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static aqc_status fail(aqc_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(AQC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+#define STCHK(expr)                 \
+  do {                              \
+    aqc_status s_ = (expr);         \
+    if (s_ != AQC_OK) return s_;    \
+  } while (0)
+
+extern "C" const char* aqc_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char* aqc_version(void) { return "aqc 0.1 (gfx950)"; }
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+// largest dynamic LDS a workgroup may use (set by aqc_create)
+static size_t g_lds_max = 0;
+
+struct aqc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t lds_max = 0;
+  double* parts = nullptr;      // per-block partial sums
+  size_t parts_cap = 0;         // doubles
+  double* dres = nullptr;       // device results [64]
+  double* hres = nullptr;       // pinned host results [64]
+  int64_t* didx = nullptr;      // device index list for basis-list fidelity
+  size_t didx_cap = 0;
+  // instrumentation: event pairs around tile-pass launches
+  bool prof_on = false;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
+  double prof_ms[2] = {0, 0};
+  int64_t prof_n[2] = {0, 0};
+  double prof_bytes[2] = {0, 0};  // algorithmic bytes of the timed launches
+};
+
+static aqc_status prof_drain(aqc_ctx* c) {
+  if (c->prof_pending.empty()) return AQC_OK;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (auto& r : c->prof_pending) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    c->prof_ms[r.kind] += ms;
+    c->prof_n[r.kind] += 1;
+    c->prof_pool.push_back(r.a);
+    c->prof_pool.push_back(r.b);
+  }
+  c->prof_pending.clear();
+  return AQC_OK;
+}
+
+static aqc_status prof_event(aqc_ctx* c, hipEvent_t* e) {
+  if (!c->prof_pool.empty()) {
+    *e = c->prof_pool.back();
+    c->prof_pool.pop_back();
+    return AQC_OK;
+  }
+  HIPCHK(hipEventCreate(e));
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_profile_enable(aqc_ctx* c, int on) {
+  if (!c) return fail(AQC_EINVAL, "aqc_profile_enable: ctx is NULL");
+  c->prof_on = on != 0;
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_profile_reset(aqc_ctx* c) {
+  if (!c) return fail(AQC_EINVAL, "aqc_profile_reset: ctx is NULL");
+  STCHK(prof_drain(c));
+  c->prof_ms[0] = c->prof_ms[1] = 0.0;
+  c->prof_n[0] = c->prof_n[1] = 0;
+  c->prof_bytes[0] = c->prof_bytes[1] = 0.0;
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_profile_read(aqc_ctx* c, int kind, double* ms, int64_t* n,
+                                       double* bytes) {
+  if (!c || !ms || !n || !bytes) return fail(AQC_EINVAL, "aqc_profile_read: NULL argument");
+  if (kind != AQC_PROF_HIGH_PASS && kind != AQC_PROF_LAST_PASS)
+    return fail(AQC_EINVAL, "aqc_profile_read: unknown kind");
+  STCHK(prof_drain(c));
+  *ms = c->prof_ms[kind];
+  *n = c->prof_n[kind];
+  *bytes = c->prof_bytes[kind];
+  return AQC_OK;
+}
+
+static aqc_status ensure_parts(aqc_ctx* c, size_t n) {
+  if (n <= c->parts_cap) return AQC_OK;
+  if (c->parts) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipFree(c->parts));
+    c->parts = nullptr;
+  }
+  size_t cap = std::max<size_t>(n, 1 << 16);
+  HIPCHK(hipMalloc(&c->parts, cap * sizeof(double)));
+  c->parts_cap = cap;
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_create(int device, void* stream, aqc_ctx** out) {
+  if (!out) return fail(AQC_EINVAL, "aqc_create: out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(AQC_EINVAL, "aqc_create: bad device index");
+  HIPCHK(hipSetDevice(device));
+  std::unique_ptr<aqc_ctx> c(new aqc_ctx());
+  c->device = device;
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  int lds = 0;
+  HIPCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+  c->lds_max = (size_t)lds;
+  g_lds_max = (size_t)lds;
+  HIPCHK(prepare_kernels());
+  HIPCHK(hipMalloc(&c->dres, 64 * sizeof(double)));
+  HIPCHK(hipHostMalloc(&c->hres, 64 * sizeof(double), hipHostMallocDefault));
+  STCHK(ensure_parts(c.get(), 1 << 16));
+  *out = c.release();
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_destroy(aqc_ctx* c) {
+  if (!c) return AQC_OK;
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  if (c->parts) hipFree(c->parts);
+  if (c->dres) hipFree(c->dres);
+  if (c->hres) hipHostFree(c->hres);
+  if (c->didx) hipFree(c->didx);
+  prof_drain(c);
+  for (hipEvent_t e : c->prof_pool) hipEventDestroy(e);
+  delete c;
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_set_stream(aqc_ctx* c, void* stream) {
+  if (!c) return fail(AQC_EINVAL, "aqc_set_stream: ctx is NULL");
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  return AQC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// schedules (time dependence of the coefficients, end of Sec. II.A)
+// ---------------------------------------------------------------------------
+static double path_s(const aqc_path& p, double t) {
+  if (p.kind == AQC_PATH_LINEAR) return t / p.T;
+  const double v = std::sin(M_PI * t / (2.0 * p.T));
+  return v * v;
+}
+
+static double sched_value(const aqc_sched& s, const aqc_path& p, double t) {
+  switch (s.kind) {
+    case AQC_SCHED_CONST:
+      return 1.0;
+    case AQC_SCHED_POLY_S: {
+      const double x = path_s(p, t);
+      const bool inside = x >= s.s_lo && (s.hi_closed ? x <= s.s_hi : x < s.s_hi);
+      if (!inside) return 0.0;
+      double v = 0.0, pw = 1.0;
+      for (int d = 0; d <= s.degree; ++d) {
+        v += s.coef[d] * pw;
+        pw *= x;
+      }
+      return v;
+    }
+    default:
+      return s.amp * std::cos(s.omega * t + s.phase);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Hamiltonian
+// ---------------------------------------------------------------------------
+struct HTerm {
+  uint64_t x, z;
+  double w;
+  int sid;
+};
+
+struct Pass {
+  int tb = 0, lbits = 0;
+  uint64_t hmask = 0, cmask = 0;
+  bool final_pass = false;
+  std::vector<int> groups;   // indices into Ham::groups
+  DevGroup* dgroups = nullptr;
+  DevTerm* dterms = nullptr;
+  int ng = 0, nterms = 0;
+};
+
+struct Plan {
+  bool built = false;
+  int tbf = 0;               // last pass tile bits
+  std::vector<Pass> passes;  // high passes first, last pass last
+  // split diagonal tables for tile bits tbf
+  DiagDev dg{};
+  double* dCT = nullptr;
+  double* dLT = nullptr;
+  double* dTAB64 = nullptr;
+  float* dTAB32 = nullptr;
+  DevTerm* dres = nullptr;
+};
+
+struct GroupH {
+  uint64_t x;
+  std::vector<HTerm> terms;
+  bool plain;
+};
+
+struct aqc_ham {
+  int n = 0;
+  int device = 0;
+  std::vector<aqc_sched> scheds;
+  aqc_path path{};
+  std::vector<HTerm> terms;      // merged
+  std::vector<HTerm> diag;       // x == 0, z != 0
+  std::vector<HTerm> ident;      // x == 0, z == 0
+  std::vector<GroupH> groups;    // x != 0
+  Plan plans[2];
+  // diagonal minimum and maximum per schedule (spectral enclosure)
+  bool have_minmax = false;
+  std::vector<double> dmin, dmax;  // per schedule
+};
+
+static void free_plan(Plan& p) {
+  for (auto& ps : p.passes) {
+    if (ps.dgroups) hipFree(ps.dgroups);
+    if (ps.dterms) hipFree(ps.dterms);
+  }
+  p.passes.clear();
+  if (p.dCT) hipFree(p.dCT);
+  if (p.dLT) hipFree(p.dLT);
+  if (p.dTAB64) hipFree(p.dTAB64);
+  if (p.dTAB32) hipFree(p.dTAB32);
+  if (p.dres) hipFree(p.dres);
+  p = Plan();
+}
+
+extern "C" aqc_status aqc_ham_free(aqc_ham* h) {
+  if (!h) return AQC_OK;
+  hipSetDevice(h->device);
+  hipDeviceSynchronize();
+  free_plan(h->plans[0]);
+  free_plan(h->plans[1]);
+  delete h;
+  return AQC_OK;
+}
+
+static int popc(uint64_t v) { return __builtin_popcountll(v); }
+
+extern "C" aqc_status aqc_build_hamiltonian(aqc_ctx* ctx, int n, int64_t n_terms,
+                                            const uint64_t* xm, const uint64_t* zm,
+                                            const double* w, const int32_t* sid, int n_sched,
+                                            const aqc_sched* scheds, const aqc_path* path,
+                                            aqc_ham** out) {
+  if (!out) return fail(AQC_EINVAL, "aqc_build_hamiltonian: out is NULL");
+  *out = nullptr;
+  if (!ctx) return fail(AQC_EINVAL, "aqc_build_hamiltonian: ctx is NULL");
+  if (n < 1) return fail(AQC_EINVAL, "aqc_build_hamiltonian: n_qubits < 1");
+  if (n > 34) return fail(AQC_ENOTSUP, "aqc_build_hamiltonian: n_qubits > 34");
+  if (n_terms < 0) return fail(AQC_EINVAL, "aqc_build_hamiltonian: n_terms < 0");
+  if (n_terms > 0 && (!xm || !zm || !w || !sid))
+    return fail(AQC_EINVAL, "aqc_build_hamiltonian: NULL term array");
+  if (n_sched < 1 || n_sched > kMaxSched || !scheds)
+    return fail(AQC_EINVAL, "aqc_build_hamiltonian: need 1..16 schedules");
+  if (!path || !(path->T > 0.0) || !std::isfinite(path->T) ||
+      (path->kind != AQC_PATH_LINEAR && path->kind != AQC_PATH_SIN2))
+    return fail(AQC_EINVAL, "aqc_build_hamiltonian: bad path");
+  for (int s = 0; s < n_sched; ++s) {
+    const aqc_sched& sc = scheds[s];
+    if (sc.kind < 0 || sc.kind > 2) return fail(AQC_EINVAL, "aqc_build_hamiltonian: bad schedule kind");
+    if (sc.kind == AQC_SCHED_POLY_S) {
+      if (sc.degree < 0 || sc.degree > 7) return fail(AQC_EINVAL, "aqc_build_hamiltonian: poly degree");
+      for (int d = 0; d <= sc.degree; ++d)
+        if (!std::isfinite(sc.coef[d])) return fail(AQC_EINVAL, "aqc_build_hamiltonian: non-finite coef");
+      if (std::isnan(sc.s_lo) || std::isnan(sc.s_hi))
+        return fail(AQC_EINVAL, "aqc_build_hamiltonian: NaN window");
+    }
+    if (sc.kind == AQC_SCHED_TRIG_T &&
+        !(std::isfinite(sc.amp) && std::isfinite(sc.omega) && std::isfinite(sc.phase)))
+      return fail(AQC_EINVAL, "aqc_build_hamiltonian: non-finite trig schedule");
+  }
+  const uint64_t full = (n == 64) ? ~0ull : ((1ull << n) - 1ull);
+  std::map<std::tuple<uint64_t, uint64_t, int>, double> merged;
+  for (int64_t l = 0; l < n_terms; ++l) {
+    if ((xm[l] & ~full) || (zm[l] & ~full))
+      return fail(AQC_EINVAL, "aqc_build_hamiltonian: mask outside the n qubits (term " +
+                                  std::to_string(l) + ")");
+    if (!std::isfinite(w[l])) return fail(AQC_EINVAL, "aqc_build_hamiltonian: non-finite weight");
+    if (sid[l] < 0 || sid[l] >= n_sched)
+      return fail(AQC_EINVAL, "aqc_build_hamiltonian: sched_id out of range");
+    merged[std::make_tuple(xm[l], zm[l], (int)sid[l])] += w[l];
+  }
+  std::unique_ptr<aqc_ham> h(new aqc_ham());
+  h->n = n;
+  h->device = ctx->device;
+  h->scheds.assign(scheds, scheds + n_sched);
+  h->path = *path;
+  std::map<uint64_t, size_t> gidx;
+  for (auto& kv : merged) {
+    HTerm t{std::get<0>(kv.first), std::get<1>(kv.first), kv.second, std::get<2>(kv.first)};
+    if (t.w == 0.0) continue;
+    h->terms.push_back(t);
+    if (t.x == 0) {
+      if (t.z == 0) h->ident.push_back(t);
+      else h->diag.push_back(t);
+    } else {
+      auto it = gidx.find(t.x);
+      if (it == gidx.end()) {
+        gidx[t.x] = h->groups.size();
+        h->groups.push_back(GroupH{t.x, {}, true});
+        it = gidx.find(t.x);
+      }
+      GroupH& g = h->groups[it->second];
+      g.terms.push_back(t);
+      if (t.z != 0) g.plain = false;
+    }
+  }
+  *out = h.release();
+  return AQC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// planner
+// ---------------------------------------------------------------------------
+struct Tiling {
+  int tbf, tbh, lh;
+};
+
+static Tiling default_tiling(int dtype) {
+  // last pass: 2^13 (c64) / 2^12 (c128) amplitudes = 64 KiB of LDS, so two
+  // workgroups share a CU; high passes use the same tile with 128-byte chunks.
+  return dtype == 0 ? Tiling{13, 13, 4} : Tiling{12, 12, 3};
+}
+
+static int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return v ? std::atoi(v) : dflt;
+}
+
+static aqc_status upload(void** dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) {
+    *dst = nullptr;
+    return AQC_OK;
+  }
+  HIPCHK(hipMalloc(dst, bytes));
+  HIPCHK(hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return AQC_OK;
+}
+
+static uint64_t pext_host(uint64_t v, uint64_t mask) {
+  uint64_t r = 0;
+  int k = 0;
+  for (int b = 0; b < 64; ++b)
+    if (mask >> b & 1ull) r |= ((v >> b) & 1ull) << (k++);
+  return r;
+}
+
+static aqc_status build_pass_tables(Pass& ps, const aqc_ham* h, hipStream_t s) {
+  std::vector<DevGroup> dg;
+  std::vector<DevTerm> dt;
+  const uint64_t tmask = ((1ull << ps.lbits) - 1ull) | ps.hmask;
+  for (int gi : ps.groups) {
+    const GroupH& g = h->groups[gi];
+    DevGroup d{};
+    d.x = g.x;
+    d.xl = (uint32_t)pext_host(g.x, tmask);
+    d.t0 = (int)dt.size();
+    d.nt = (int)g.terms.size();
+    d.plain = g.plain ? 1 : 0;
+    for (const HTerm& t : g.terms)
+      dt.push_back(DevTerm{t.z, t.w, t.sid, popc(t.x & t.z) & 3});
+    dg.push_back(d);
+  }
+  ps.ng = (int)dg.size();
+  ps.nterms = (int)dt.size();
+  STCHK(upload((void**)&ps.dgroups, dg.data(), dg.size() * sizeof(DevGroup), s));
+  STCHK(upload((void**)&ps.dterms, dt.data(), dt.size() * sizeof(DevTerm), s));
+  return AQC_OK;
+}
+
+// Split the diagonal terms for tile bits tb: see DiagDev.
+static aqc_status build_diag_tables(Plan& p, const aqc_ham* h, hipStream_t s) {
+  const int n = h->n, tb = p.tbf;
+  const uint64_t lomask = (1ull << tb) - 1ull;
+  const int64_t nhi = (int64_t)1 << (n - tb);
+  const int64_t ntile = (int64_t)1 << tb;
+  std::vector<int> sd, ts;
+  std::vector<HTerm> ct_terms, lt_terms, tab_terms, res;
+  auto slot = [](std::vector<int>& v, int sid, int cap) -> int {
+    for (size_t i = 0; i < v.size(); ++i)
+      if (v[i] == sid) return (int)i;
+    if ((int)v.size() >= cap) return -1;
+    v.push_back(sid);
+    return (int)v.size() - 1;
+  };
+  for (const HTerm& t : h->diag) {
+    const uint64_t u = t.z & lomask;
+    const uint64_t zh = t.z >> tb;
+    const int pu = popc(u);
+    if (pu <= 1) {
+      if (slot(sd, t.sid, kMaxDiagSched) < 0) {
+        res.push_back(t);
+        continue;
+      }
+      (pu == 0 ? ct_terms : lt_terms).push_back(t);
+    } else if (zh == 0) {
+      if (slot(ts, t.sid, kMaxTabSched) < 0) {
+        res.push_back(t);
+        continue;
+      }
+      tab_terms.push_back(t);
+    } else {
+      res.push_back(t);
+    }
+  }
+  const int nsd = (int)sd.size(), ntab = (int)ts.size();
+  std::vector<double> CT((size_t)std::max(nsd, 1) * nhi, 0.0);
+  std::vector<double> LT((size_t)std::max(nsd, 1) * nhi * tb, 0.0);
+  std::vector<double> TAB((size_t)std::max(ntab, 1) * ntile, 0.0);
+  auto sidx = [&](const std::vector<int>& v, int sid) {
+    return (int)(std::find(v.begin(), v.end(), sid) - v.begin());
+  };
+  for (const HTerm& t : ct_terms) {
+    const int k = sidx(sd, t.sid);
+    const uint64_t zh = t.z >> tb;
+    for (int64_t hi = 0; hi < nhi; ++hi)
+      CT[(size_t)k * nhi + hi] += (popc((uint64_t)hi & zh) & 1) ? -t.w : t.w;
+  }
+  for (const HTerm& t : lt_terms) {
+    const int k = sidx(sd, t.sid);
+    const uint64_t zh = t.z >> tb;
+    const int i = __builtin_ctzll(t.z & lomask);
+    for (int64_t hi = 0; hi < nhi; ++hi)
+      LT[((size_t)k * nhi + hi) * tb + i] += (popc((uint64_t)hi & zh) & 1) ? -t.w : t.w;
+  }
+  for (const HTerm& t : tab_terms) {
+    const int k = sidx(ts, t.sid);
+    const uint64_t u = t.z & lomask;
+    for (int64_t lo = 0; lo < ntile; ++lo)
+      TAB[(size_t)k * ntile + lo] += (popc((uint64_t)lo & u) & 1) ? -t.w : t.w;
+  }
+  std::vector<float> TAB32(TAB.begin(), TAB.end());
+  std::vector<DevTerm> dres;
+  for (const HTerm& t : res) dres.push_back(DevTerm{t.z, t.w, t.sid, 0});
+  STCHK(upload((void**)&p.dCT, CT.data(), CT.size() * sizeof(double), s));
+  STCHK(upload((void**)&p.dLT, LT.data(), LT.size() * sizeof(double), s));
+  STCHK(upload((void**)&p.dTAB64, TAB.data(), TAB.size() * sizeof(double), s));
+  STCHK(upload((void**)&p.dTAB32, TAB32.data(), TAB32.size() * sizeof(float), s));
+  STCHK(upload((void**)&p.dres, dres.data(), dres.size() * sizeof(DevTerm), s));
+  DiagDev& d = p.dg;
+  d = DiagDev{};
+  d.nsd = nsd;
+  for (int i = 0; i < nsd; ++i) d.sd_sid[i] = sd[i];
+  d.ntab = ntab;
+  for (int i = 0; i < ntab; ++i) d.tab_sid[i] = ts[i];
+  d.nres = (int)dres.size();
+  d.CT = p.dCT;
+  d.LT = p.dLT;
+  d.TAB64 = p.dTAB64;
+  d.TAB32 = p.dTAB32;
+  d.res = p.dres;
+  return AQC_OK;
+}
+
+// Pass layout (host only): the last pass tiles the low tbf bits; every other
+// flip pattern goes to a high pass whose tile is [0, lh) plus at most tbh - lh
+// further bits.
+static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& out, int* tbf_out) {
+  Tiling tl = default_tiling(dtype);
+  tl.tbf = env_int(dtype == 0 ? "AQC_TBF_C64" : "AQC_TBF_C128", tl.tbf);
+  tl.tbh = env_int(dtype == 0 ? "AQC_TBH_C64" : "AQC_TBH_C128", tl.tbh);
+  tl.lh = env_int(dtype == 0 ? "AQC_LH_C64" : "AQC_LH_C128", tl.lh);
+  const int maxtb = dtype == 0 ? 14 : 13;
+  if (tl.tbf < 1 || tl.tbf > maxtb || tl.tbh < 2 || tl.tbh > maxtb || tl.lh < 1 || tl.lh >= tl.tbh)
+    return fail(AQC_EINVAL, "tiling parameters out of range");
+  if (g_lds_max > 0) {
+    while (tl.tbf > 1 && pass_lds_bytes(tl.tbf, dtype) > g_lds_max) --tl.tbf;
+    while (tl.tbh > tl.lh + 1 && pass_lds_bytes(tl.tbh, dtype) > g_lds_max) --tl.tbh;
+  }
+  const int n = h->n;
+  const uint64_t full = (1ull << n) - 1ull;
+  const int tbf = std::min(n, tl.tbf);
+  const int lh = std::min(tl.lh, tbf);
+  const int tbh = std::min(n, tl.tbh);
+  const int cap = std::max(0, tbh - lh);  // high bits per pass
+  const uint64_t fmask = (1ull << tbf) - 1ull;
+  const uint64_t lowh = (1ull << lh) - 1ull;
+
+  Pass last;
+  last.final_pass = true;
+  last.tb = tbf;
+  last.lbits = tbf;
+  last.hmask = 0;
+  last.cmask = full & ~fmask;
+  std::vector<int> rest;
+  int lterms = 0;
+  for (size_t gi = 0; gi < h->groups.size(); ++gi) {
+    const GroupH& g = h->groups[gi];
+    if ((g.x & ~fmask) == 0 && (int)last.groups.size() < kMaxPassGroups &&
+        lterms + (int)g.terms.size() <= kMaxPassTerms) {
+      last.groups.push_back((int)gi);
+      lterms += (int)g.terms.size();
+    } else {
+      rest.push_back((int)gi);
+    }
+  }
+  std::sort(rest.begin(), rest.end(), [&](int a, int b) {
+    const uint64_t xa = h->groups[a].x, xb = h->groups[b].x;
+    const int ha = 63 - __builtin_clzll(xa), hb = 63 - __builtin_clzll(xb);
+    if (ha != hb) return ha < hb;
+    return xa < xb;
+  });
+  std::vector<Pass> high;
+  std::vector<int> hterms;
+  for (int gi : rest) {
+    const GroupH& g = h->groups[gi];
+    if ((int)g.terms.size() > kMaxPassTerms)
+      return fail(AQC_ENOTSUP, "a flip pattern has more terms than a pass holds");
+    const uint64_t need = g.x & ~lowh;
+    if (popc(need) > cap)
+      return fail(AQC_ENOTSUP, "a flip pattern spans more bits than a high-pass tile holds");
+    bool placed = false;
+    for (size_t p2 = 0; p2 < high.size() && !placed; ++p2) {
+      Pass& ps = high[p2];
+      if (popc(ps.hmask | need) <= cap && (int)ps.groups.size() < kMaxPassGroups &&
+          hterms[p2] + (int)g.terms.size() <= kMaxPassTerms) {
+        ps.hmask |= need;
+        ps.groups.push_back(gi);
+        hterms[p2] += (int)g.terms.size();
+        placed = true;
+      }
+    }
+    if (!placed) {
+      Pass ps;
+      ps.final_pass = false;
+      ps.lbits = lh;
+      ps.hmask = need;
+      ps.groups.push_back(gi);
+      high.push_back(ps);
+      hterms.push_back((int)g.terms.size());
+    }
+  }
+  // fill every high tile to its full width with unused bits, lowest first
+  for (Pass& ps : high) {
+    for (int b = lh; b < n && popc(ps.hmask) < cap; ++b)
+      if (!(ps.hmask >> b & 1ull)) ps.hmask |= 1ull << b;
+    ps.tb = lh + popc(ps.hmask);
+    ps.cmask = full & ~(lowh | ps.hmask);
+  }
+  out.clear();
+  for (Pass& ps : high) out.push_back(ps);
+  out.push_back(last);
+  *tbf_out = tbf;
+  return AQC_OK;
+}
+
+static aqc_status build_plan(aqc_ham* h, int dtype, hipStream_t s) {
+  Plan& p = h->plans[dtype];
+  if (p.built) return AQC_OK;
+  HIPCHK(hipSetDevice(h->device));
+  std::vector<Pass> passes;
+  int tbf = 0;
+  STCHK(layout_passes(h, dtype, passes, &tbf));
+  p.tbf = tbf;
+  p.passes = passes;
+  for (Pass& ps : p.passes) STCHK(build_pass_tables(ps, h, s));
+  STCHK(build_diag_tables(p, h, s));
+  p.built = true;
+  return AQC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// pass execution
+// ---------------------------------------------------------------------------
+struct Coefs {
+  double f[kMaxSched];
+  double ident;  // identity terms at t
+};
+
+static Coefs coefs_at(const aqc_ham* h, double t) {
+  Coefs c{};
+  for (size_t s = 0; s < h->scheds.size(); ++s) c.f[s] = sched_value(h->scheds[s], h->path, t);
+  c.ident = 0.0;
+  for (const HTerm& it : h->ident) c.ident += it.w * c.f[it.sid];
+  return c;
+}
+
+static void fill_common(PassArgs& a, const aqc_ham* h, const Plan& p, const Pass& ps,
+                        const Coefs& c, double shift) {
+  std::memset(&a, 0, sizeof(a));
+  a.n = h->n;
+  a.tb = ps.tb;
+  a.lbits = ps.lbits;
+  a.final_pass = ps.final_pass ? 1 : 0;
+  a.hmask = ps.hmask;
+  a.cmask = ps.cmask;
+  a.groups = ps.dgroups;
+  a.terms = ps.dterms;
+  a.ng = ps.ng;
+  a.nterms = ps.nterms;
+  for (int i = 0; i < kMaxSched; ++i) a.f[i] = c.f[i];
+  a.dconst = c.ident - shift;
+  a.dg = p.dg;
+}
+
+// (H(t) - shift) u, with the last pass's epilogue `epi`.  hbuf: one vector when
+// the plan has high passes.
+static aqc_status run_matvec(aqc_ctx* ctx, const aqc_ham* h, int dtype, double t, double shift,
+                             const void* u, void* hbuf, const EpiDesc& epi) {
+  const Plan& p = h->plans[dtype];
+  const Coefs c = coefs_at(h, t);
+  const int np = (int)p.passes.size();
+  if (np > 1 && !hbuf) return fail(AQC_ENOMEM, "workspace for the partial product missing");
+  for (int k = 0; k < np; ++k) {
+    const Pass& ps = p.passes[k];
+    PassArgs a;
+    fill_common(a, h, p, ps, c, shift);
+    a.src = u;
+    if (!ps.final_pass) {
+      a.acc_in = k > 0 ? hbuf : nullptr;
+      a.acc_out = hbuf;
+    } else {
+      a.acc_in = np > 1 ? hbuf : nullptr;
+      a.epi = epi;
+    }
+    const int64_t nb = (int64_t)1 << (h->n - ps.tb);
+    if (ctx->prof_on) {
+      aqc_ctx::Rec r;
+      r.kind = ps.final_pass ? AQC_PROF_LAST_PASS : AQC_PROF_HIGH_PASS;
+      STCHK(prof_event(ctx, &r.a));
+      STCHK(prof_event(ctx, &r.b));
+      HIPCHK(hipEventRecord(r.a, ctx->stream));
+      HIPCHK(launch_pass(a, dtype, nb, ctx->stream));
+      HIPCHK(hipEventRecord(r.b, ctx->stream));
+      ctx->prof_pending.push_back(r);
+      // algorithmic traffic: the tile source once, each streamed input and
+      // output once, the partial product in and out
+      int nvec = 1 + (a.acc_in ? 1 : 0) + (a.acc_out ? 1 : 0);
+      if (ps.final_pass) {
+        for (int i = 0; i < 4; ++i) nvec += a.epi.in[i] ? 1 : 0;
+        for (int i = 0; i < 3; ++i) nvec += a.epi.out[i] ? 1 : 0;
+      }
+      ctx->prof_bytes[r.kind] += (double)nvec * (double)((size_t)1 << h->n) * (dtype == 0 ? 8.0 : 16.0);
+      if (ctx->prof_pending.size() >= 4096) STCHK(prof_drain(ctx));
+    } else {
+      HIPCHK(launch_pass(a, dtype, nb, ctx->stream));
+    }
+  }
+  return AQC_OK;
+}
+
+static int64_t last_nblocks(const aqc_ham* h, int dtype) {
+  return (int64_t)1 << (h->n - h->plans[dtype].tbf);
+}
+
+static aqc_status read_results(aqc_ctx* ctx, int k, double* out) {
+  HIPCHK(hipMemcpyAsync(ctx->hres, ctx->dres, k * sizeof(double), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < k; ++i) out[i] = ctx->hres[i];
+  return AQC_OK;
+}
+
+static EpiDesc epi_zero() {
+  EpiDesc e;
+  std::memset(&e, 0, sizeof(e));
+  return e;
+}
+
+static aqc_status check_common(aqc_ctx* ctx, const aqc_ham* h, int dtype) {
+  if (!ctx) return fail(AQC_EINVAL, "ctx is NULL");
+  if (!h) return fail(AQC_EINVAL, "ham is NULL");
+  if (dtype != AQC_C64 && dtype != AQC_C128) return fail(AQC_ENOTSUP, "dtype must be C64 or C128");
+  if (h->device != ctx->device) return fail(AQC_EINVAL, "ham built for another device");
+  HIPCHK(hipSetDevice(ctx->device));
+  return build_plan(const_cast<aqc_ham*>(h), dtype, ctx->stream);
+}
+
+static size_t vec_bytes(const aqc_ham* h, int dtype) {
+  return ((size_t)1 << h->n) * (dtype == AQC_C64 ? 8 : 16);
+}
+
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+extern "C" aqc_status aqc_ham_info(const aqc_ham* h, aqc_ham_info_t* out) {
+  if (!h || !out) return fail(AQC_EINVAL, "aqc_ham_info: NULL argument");
+  std::memset(out, 0, sizeof(*out));
+  out->n_qubits = h->n;
+  out->n_terms = (int)h->terms.size();
+  out->n_diag_terms = (int)(h->diag.size() + h->ident.size());
+  out->n_groups = (int)h->groups.size();
+  for (int d = 0; d < 2; ++d) {
+    out->n_passes[d] = h->plans[d].built ? (int)h->plans[d].passes.size() : 0;
+    out->tile_bits[d] = h->plans[d].built ? h->plans[d].tbf : 0;
+  }
+  out->spec_lo = NAN;
+  out->spec_hi = NAN;
+  return AQC_OK;
+}
+
+extern "C" size_t aqc_apply_workspace_bytes(const aqc_ham* h, int dtype) {
+  if (!h || (dtype != 0 && dtype != 1)) return 0;
+  const Plan& p = h->plans[dtype];
+  size_t np = p.passes.size();
+  if (!p.built) {
+    std::vector<Pass> passes;
+    int tbf = 0;
+    if (layout_passes(h, dtype, passes, &tbf) != AQC_OK) return 0;
+    np = passes.size();
+  }
+  return np > 1 ? vec_bytes(h, dtype) : 0;
+}
+
+extern "C" aqc_status aqc_apply(aqc_ctx* ctx, const aqc_ham* h, double t, const void* in,
+                                void* out, int dtype, void* ws, size_t ws_bytes) {
+  STCHK(check_common(ctx, h, dtype));
+  if (!in || !out) return fail(AQC_EINVAL, "aqc_apply: NULL state pointer");
+  if (in == out) return fail(AQC_EINVAL, "aqc_apply: psi_in and psi_out must differ");
+  if (!aligned16(in) || !aligned16(out)) return fail(AQC_EINVAL, "aqc_apply: pointers must be 16-byte aligned");
+  if (!std::isfinite(t)) return fail(AQC_EINVAL, "aqc_apply: t not finite");
+  const Plan& p = h->plans[dtype];
+  void* hbuf = nullptr;
+  if (p.passes.size() > 1) {
+    if (!ws || ws_bytes < vec_bytes(h, dtype)) return fail(AQC_ENOMEM, "aqc_apply: workspace too small");
+    hbuf = ws;
+  }
+  EpiDesc e = epi_zero();
+  e.out[0] = out;
+  e.scale[0] = 1.0;
+  e.br[0] = 1.0;
+  return run_matvec(ctx, h, dtype, t, 0.0, in, hbuf, e);
+}
+
+extern "C" aqc_status aqc_energy(aqc_ctx* ctx, const aqc_ham* h, double t, const void* psi,
+                                 int dtype, void* ws, size_t ws_bytes, double* out) {
+  STCHK(check_common(ctx, h, dtype));
+  if (!psi || !out) return fail(AQC_EINVAL, "aqc_energy: NULL pointer");
+  if (!aligned16(psi)) return fail(AQC_EINVAL, "aqc_energy: psi must be 16-byte aligned");
+  const Plan& p = h->plans[dtype];
+  void* hbuf = nullptr;
+  if (p.passes.size() > 1) {
+    if (!ws || ws_bytes < vec_bytes(h, dtype)) return fail(AQC_ENOMEM, "aqc_energy: workspace too small");
+    hbuf = ws;
+  }
+  const int64_t nb = last_nblocks(h, dtype);
+  STCHK(ensure_parts(ctx, 3 * (size_t)nb));
+  EpiDesc e = epi_zero();
+  e.red = ctx->parts;
+  e.red_flags = 4;
+  STCHK(run_matvec(ctx, h, dtype, t, 0.0, psi, hbuf, e));
+  HIPCHK(launch_reduce_sum(ctx->parts + 2 * nb, nb, 1, ctx->dres, ctx->stream));
+  return read_results(ctx, 1, out);
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+static aqc_status check_state(aqc_ctx* ctx, const void* psi, int dtype, int n) {
+  if (!ctx) return fail(AQC_EINVAL, "ctx is NULL");
+  if (!psi) return fail(AQC_EINVAL, "state pointer is NULL");
+  if (dtype != 0 && dtype != 1) return fail(AQC_ENOTSUP, "dtype must be C64 or C128");
+  if (n < 1 || n > 34) return fail(AQC_EINVAL, "n_qubits outside 1..34");
+  if (!aligned16(psi)) return fail(AQC_EINVAL, "state must be 16-byte aligned");
+  HIPCHK(hipSetDevice(ctx->device));
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_norm2(aqc_ctx* ctx, const void* psi, int dtype, int n, double* out) {
+  STCHK(check_state(ctx, psi, dtype, n));
+  if (!out) return fail(AQC_EINVAL, "aqc_norm2: out is NULL");
+  STCHK(ensure_parts(ctx, 16384));
+  int64_t nb = 0;
+  HIPCHK(launch_norm2(psi, dtype, (int64_t)1 << n, ctx->parts, &nb, ctx->stream));
+  HIPCHK(launch_reduce_sum(ctx->parts, nb, 1, ctx->dres, ctx->stream));
+  return read_results(ctx, 1, out);
+}
+
+extern "C" aqc_status aqc_overlap(aqc_ctx* ctx, const void* phi, const void* psi, int dtype, int n,
+                                  double* re, double* im) {
+  STCHK(check_state(ctx, psi, dtype, n));
+  STCHK(check_state(ctx, phi, dtype, n));
+  if (!re || !im) return fail(AQC_EINVAL, "aqc_overlap: NULL output");
+  STCHK(ensure_parts(ctx, 2 * 16384));
+  int64_t nb = 0;
+  HIPCHK(launch_overlap(phi, psi, dtype, (int64_t)1 << n, ctx->parts, &nb, ctx->stream));
+  HIPCHK(launch_reduce_sum(ctx->parts, nb, 2, ctx->dres, ctx->stream));
+  double r[2];
+  STCHK(read_results(ctx, 2, r));
+  *re = r[0];
+  *im = r[1];
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_fidelity(aqc_ctx* ctx, const void* psi, int dtype, int n, int kind,
+                                   const void* target, int64_t len, double* out) {
+  STCHK(check_state(ctx, psi, dtype, n));
+  if (!out || !target) return fail(AQC_EINVAL, "aqc_fidelity: NULL argument");
+  if (kind == AQC_TARGET_STATE) {
+    double re, im;
+    STCHK(aqc_overlap(ctx, target, psi, dtype, n, &re, &im));
+    *out = re * re + im * im;
+    return AQC_OK;
+  }
+  if (kind != AQC_TARGET_BASIS_LIST) return fail(AQC_EINVAL, "aqc_fidelity: unknown target kind");
+  if (len < 0) return fail(AQC_EINVAL, "aqc_fidelity: negative list length");
+  const int64_t* li = reinterpret_cast<const int64_t*>(target);
+  std::vector<int64_t> idx(li, li + len);
+  std::sort(idx.begin(), idx.end());
+  idx.erase(std::unique(idx.begin(), idx.end()), idx.end());
+  for (int64_t v : idx)
+    if (v < 0 || v >= ((int64_t)1 << n)) return fail(AQC_EINVAL, "aqc_fidelity: basis index out of range");
+  if (idx.empty()) {
+    *out = 0.0;
+    return AQC_OK;
+  }
+  if (idx.size() > ctx->didx_cap) {
+    if (ctx->didx) {
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      HIPCHK(hipFree(ctx->didx));
+    }
+    ctx->didx = nullptr;
+    HIPCHK(hipMalloc(&ctx->didx, idx.size() * sizeof(int64_t)));
+    ctx->didx_cap = idx.size();
+  }
+  HIPCHK(hipMemcpyAsync(ctx->didx, idx.data(), idx.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                        ctx->stream));
+  STCHK(ensure_parts(ctx, 16384));
+  int64_t nb = 0;
+  HIPCHK(launch_gather_mass(psi, dtype, ctx->didx, (int64_t)idx.size(), ctx->parts, &nb, ctx->stream));
+  HIPCHK(launch_reduce_sum(ctx->parts, nb, 1, ctx->dres, ctx->stream));
+  return read_results(ctx, 1, out);
+}
+
+// diagonal of H(t) restricted to schedule weights f (float64 tables)
+static void diag_args(PassArgs& a, const aqc_ham* h, const Plan& p, const double* f, double dconst) {
+  std::memset(&a, 0, sizeof(a));
+  a.n = h->n;
+  a.tb = p.tbf;
+  a.lbits = p.tbf;
+  a.final_pass = 1;
+  for (int i = 0; i < kMaxSched; ++i) a.f[i] = f[i];
+  a.dconst = dconst;
+  a.dg = p.dg;
+}
+
+static aqc_status diag_minmax(aqc_ctx* ctx, const aqc_ham* h, const Plan& p, const double* f,
+                              double dconst, double* mn, double* mx) {
+  PassArgs a;
+  diag_args(a, h, p, f, dconst);
+  const int64_t nb = (int64_t)1 << (h->n - p.tbf);
+  STCHK(ensure_parts(ctx, 2 * (size_t)nb));
+  HIPCHK(launch_diag_minmax(a, nb, ctx->parts, ctx->stream));
+  std::vector<double> host(2 * nb);
+  HIPCHK(hipMemcpyAsync(host.data(), ctx->parts, 2 * nb * sizeof(double), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  double a0 = INFINITY, b0 = -INFINITY;
+  for (int64_t i = 0; i < nb; ++i) {
+    a0 = std::min(a0, host[i]);
+    b0 = std::max(b0, host[nb + i]);
+  }
+  *mn = a0;
+  *mx = b0;
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_ground_mass(aqc_ctx* ctx, const aqc_ham* h, double t, const void* psi,
+                                      int dtype, double rel_tol, double* mass, double* e_min) {
+  STCHK(check_common(ctx, h, dtype));
+  if (!psi || !mass || !e_min) return fail(AQC_EINVAL, "aqc_ground_mass: NULL argument");
+  if (!aligned16(psi)) return fail(AQC_EINVAL, "aqc_ground_mass: psi must be 16-byte aligned");
+  if (!(rel_tol >= 0.0)) return fail(AQC_EINVAL, "aqc_ground_mass: rel_tol < 0");
+  // float64 tables of the same geometry as this dtype's last pass
+  const Plan& p = h->plans[dtype];
+  const Coefs c = coefs_at(h, t);
+  double mn, mx;
+  STCHK(diag_minmax(ctx, h, p, c.f, c.ident, &mn, &mx));
+  const double thr = mn + rel_tol * std::max(1.0, std::fabs(mn));
+  PassArgs a;
+  diag_args(a, h, p, c.f, c.ident);
+  a.src = psi;
+  const int64_t nb = (int64_t)1 << (h->n - p.tbf);
+  STCHK(ensure_parts(ctx, (size_t)nb));
+  HIPCHK(launch_diag_mass(a, dtype, nb, thr, ctx->parts, ctx->stream));
+  HIPCHK(launch_reduce_sum(ctx->parts, nb, 1, ctx->dres, ctx->stream));
+  STCHK(read_results(ctx, 1, mass));
+  *e_min = mn;
+  return AQC_OK;
+}
+
+static aqc_status ensure_minmax(aqc_ctx* ctx, aqc_ham* h) {
+  if (h->have_minmax) return AQC_OK;
+  STCHK(build_plan(h, 1, ctx->stream));
+  const Plan& p = h->plans[1];
+  const int ns = (int)h->scheds.size();
+  h->dmin.assign(ns, 0.0);
+  h->dmax.assign(ns, 0.0);
+  for (int s = 0; s < ns; ++s) {
+    bool any = false;
+    for (const HTerm& t : h->diag) any |= (t.sid == s);
+    double idc = 0.0;
+    for (const HTerm& t : h->ident)
+      if (t.sid == s) idc += t.w;
+    if (!any) {
+      h->dmin[s] = h->dmax[s] = idc;
+      continue;
+    }
+    double f[kMaxSched] = {0};
+    f[s] = 1.0;
+    double mn, mx;
+    STCHK(diag_minmax(ctx, h, p, f, idc, &mn, &mx));
+    h->dmin[s] = mn;
+    h->dmax[s] = mx;
+  }
+  h->have_minmax = true;
+  return AQC_OK;
+}
+
+static void enclosure_at(const aqc_ham* h, double t, double* lo, double* hi) {
+  const Coefs c = coefs_at(h, t);
+  double a = 0.0, b = 0.0;
+  for (size_t s = 0; s < h->scheds.size(); ++s) {
+    const double f = c.f[s];
+    if (f >= 0) {
+      a += f * h->dmin[s];
+      b += f * h->dmax[s];
+    } else {
+      a += f * h->dmax[s];
+      b += f * h->dmin[s];
+    }
+  }
+  double off = 0.0;
+  for (const GroupH& g : h->groups)
+    for (const HTerm& t : g.terms) off += std::fabs(t.w * c.f[t.sid]);
+  *lo = a - off;
+  *hi = b + off;
+}
+
+extern "C" aqc_status aqc_spectral_bounds(aqc_ctx* ctx, const aqc_ham* hc, double t0, double t1,
+                                          double* lo, double* hi) {
+  if (!ctx || !hc || !lo || !hi) return fail(AQC_EINVAL, "aqc_spectral_bounds: NULL argument");
+  aqc_ham* h = const_cast<aqc_ham*>(hc);
+  HIPCHK(hipSetDevice(ctx->device));
+  STCHK(ensure_minmax(ctx, h));
+  double a = INFINITY, b = -INFINITY;
+  const int K = 256;
+  for (int k = 0; k <= K; ++k) {
+    const double t = t0 + (t1 - t0) * k / K;
+    double l, u;
+    enclosure_at(h, t, &l, &u);
+    a = std::min(a, l);
+    b = std::max(b, u);
+  }
+  *lo = a;
+  *hi = b;
+  return AQC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// time evolution (Sec. II.B)
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr double kMilne = 19.0 / 270.0;
+
+struct Evolver {
+  aqc_ctx* ctx;
+  const aqc_ham* h;
+  int dtype;
+  double shift;
+  int64_t N;
+  size_t vb;
+  int method;
+  void* y;           // the caller's state
+  void* yp;          // predictor (pc4) or RK4 stage input u
+  void* B[4];        // f history (pc4); B[0] is the RK4 accumulator
+  void* hbuf;        // partial product of the high passes
+  void* ckpt;        // adaptive: state at the window start
+  void* ycomp;       // complex64 compensated state: low part of y (or nullptr)
+  void* ckpt_lo;     // adaptive: low part at the window start
+  int64_t nb_last;
+  aqc_evolve_stats* st;
+  int check_every;
+  double norm_tol;
+  int64_t steps_since_check = 0;
+  double* errbuf;    // device, per-step Milne sums of a window
+
+  // one RK4 step on (t, h); when fk != nullptr the first stage's F = f(t, y)
+  // is written there (the predictor-corrector bootstrap keeps it).  With a
+  // compensated state the stage inputs u = y + c h F include y_lo and the
+  // final update is a two-sum into (y, y_lo).
+  aqc_status rk4_step(double t, double hh, void* fk, void* acc, bool want_norm) {
+    const int lo_in = ycomp ? 1 : 0;
+    // stage 1: acc (or f_k) = F, u = y + h/2 F
+    EpiDesc e = epi_zero();
+    e.out[0] = fk ? fk : acc;
+    e.scale[0] = 1.0;
+    e.bi[0] = -1.0;
+    e.out[1] = yp;
+    e.cu[1] = 1.0;
+    e.scale[1] = 0.5 * hh;
+    e.bi[1] = -1.0;
+    e.comp = ycomp;
+    e.comp_flags = lo_in << 1;
+    STCHK(run_matvec(ctx, h, dtype, t, shift, y, hbuf, e));
+    // stages 2, 3: acc = acc_in + 2F, u = y + c h F (u updated in place)
+    for (int sg = 2; sg <= 3; ++sg) {
+      e = epi_zero();
+      e.in[0] = y;
+      e.in[1] = (sg == 2 && fk) ? fk : acc;
+      e.out[0] = acc;
+      e.scale[0] = 1.0;
+      e.a[0][0] = 1.0;
+      e.bi[0] = -2.0;
+      e.out[1] = yp;
+      e.c0[1] = 1.0;
+      e.scale[1] = sg == 2 ? 0.5 * hh : hh;
+      e.bi[1] = -1.0;
+      e.comp = ycomp;
+      e.comp_flags = lo_in << 1;
+      STCHK(run_matvec(ctx, h, dtype, t + 0.5 * hh, shift, yp, hbuf, e));
+    }
+    // stage 4: y = y + h/6 (acc + F)
+    e = epi_zero();
+    e.in[0] = y;
+    e.in[1] = acc;
+    e.out[0] = y;
+    e.c0[0] = 1.0;
+    e.scale[0] = hh / 6.0;
+    e.a[0][0] = 1.0;
+    e.bi[0] = -1.0;
+    e.comp = ycomp;
+    e.comp_flags = ycomp ? (1 | 8) : 0;
+    if (want_norm) {
+      e.red = ctx->parts;
+      e.red_flags = 1;
+    }
+    STCHK(run_matvec(ctx, h, dtype, t + hh, shift, yp, hbuf, e));
+    st->matvecs += 4;
+    return AQC_OK;
+  }
+
+  aqc_status norm_check(double t_now, int64_t k_global) {
+    HIPCHK(launch_reduce_sum(ctx->parts, nb_last, 1, ctx->dres, ctx->stream));
+    double v;
+    STCHK(read_results(ctx, 1, &v));
+    if (!std::isfinite(v) || std::fabs(v - st->norm2_initial) > norm_tol) {
+      st->status_step = (int32_t)k_global;
+      st->t_reached = t_now;
+      char buf[160];
+      snprintf(buf, sizeof buf, "norm guard: |psi|^2 = %.6g at t = %.6g (initial %.6g)", v, t_now,
+               st->norm2_initial);
+      return fail(AQC_EUNSTABLE, buf);
+    }
+    return AQC_OK;
+  }
+
+  bool due_check() {
+    if (check_every <= 0) return false;
+    return (++steps_since_check % check_every) == 0;
+  }
+
+  // Segment state: k steps done on the grid t_s + k h.
+  struct Seg {
+    double ts, h;
+    int64_t k;
+  };
+
+  // Advance a segment by nsteps; Milne sums of pc4 steps go to errbuf[0..]
+  // (when errs != nullptr, the count is returned in *nerr).
+  aqc_status advance(Seg& sg, int64_t nsteps, bool want_err, int* nerr, bool last_segment_end) {
+    const double hh = sg.h;
+    int ne = 0;
+    for (int64_t i = 0; i < nsteps; ++i) {
+      const int64_t k = sg.k;
+      const double tk = sg.ts + (double)k * hh;
+      const bool chk = due_check();
+      if (method == AQC_METHOD_RK4) {
+        STCHK(rk4_step(tk, hh, nullptr, B[0], chk));
+      } else if (k < 3) {
+        STCHK(rk4_step(tk, hh, B[k & 3], B[3], chk));
+        if (k == 2) {
+          // f_3 at the end of the bootstrap, then the first prediction
+          const double t3 = sg.ts + 3.0 * hh;
+          EpiDesc e = epi_zero();
+          e.out[0] = B[3];
+          e.scale[0] = 1.0;
+          e.bi[0] = -1.0;
+          // only when the segment continues past the bootstrap
+          if (i + 1 < nsteps || !last_segment_end) {
+            STCHK(run_matvec(ctx, h, dtype, t3, shift, y, hbuf, e));
+            st->matvecs += 1;
+            const double c4[4] = {55.0 * hh / 24.0, -59.0 * hh / 24.0, 37.0 * hh / 24.0,
+                                  -9.0 * hh / 24.0};
+            HIPCHK(launch_ab4(yp, y, B[3], B[2], B[1], B[0], c4, dtype, N, ctx->stream));
+          }
+        }
+      } else {
+        // predictor-corrector step k -> k+1: one H|psi> at t_{k+1} on y^p_{k+1}
+        void* fk = B[k & 3];
+        void* fk1 = B[(k - 1) & 3];
+        void* fk2 = B[(k - 2) & 3];
+        void* fnew = B[(k + 1) & 3];  // holds f_{k-3}, no longer needed
+        const bool more = (i + 1 < nsteps) || !last_segment_end;
+        const double c = hh / 24.0;
+        EpiDesc e = epi_zero();
+        e.in[0] = y;
+        e.in[1] = fk;
+        e.in[2] = fk1;
+        e.in[3] = fk2;
+        e.out[0] = y;  // y_{k+1} = y_k + h/24 (9 F + 19 f_k - 5 f_{k-1} + f_{k-2})
+        e.c0[0] = 1.0;
+        e.scale[0] = c;
+        e.a[0][0] = 19.0;
+        e.a[0][1] = -5.0;
+        e.a[0][2] = 1.0;
+        e.bi[0] = -9.0;
+        e.out[1] = fnew;  // f_{k+1} = F
+        e.scale[1] = 1.0;
+        e.bi[1] = -1.0;
+        if (more) {
+          e.out[2] = yp;  // y^p_{k+2} = y_k + h/24 (64 F - 40 f_k + 32 f_{k-1} - 8 f_{k-2})
+          e.c0[2] = 1.0;
+          e.scale[2] = c;
+          e.a[2][0] = -40.0;
+          e.a[2][1] = 32.0;
+          e.a[2][2] = -8.0;
+          e.bi[2] = -64.0;
+        }
+        e.comp = ycomp;
+        e.comp_flags = ycomp ? (1 | 8 | 4) : 0;
+        e.red = ctx->parts;
+        e.red_flags = (chk ? 1 : 0) | (want_err ? 2 : 0);
+        STCHK(run_matvec(ctx, h, dtype, sg.ts + (double)(k + 1) * hh, shift, yp, hbuf, e));
+        st->matvecs += 1;
+        if (want_err) {
+          HIPCHK(launch_reduce_sum(ctx->parts + nb_last, nb_last, 1, errbuf + ne, ctx->stream));
+          ++ne;
+        }
+      }
+      sg.k = k + 1;
+      st->steps += 1;
+      if (chk) STCHK(norm_check(sg.ts + (double)sg.k * hh, st->steps));
+    }
+    if (nerr) *nerr = ne;
+    return AQC_OK;
+  }
+};
+
+}  // namespace
+
+extern "C" size_t aqc_evolve_workspace_bytes(const aqc_ham* h, int dtype, const aqc_evolve_opts* o) {
+  if (!h || (dtype != 0 && dtype != 1)) return 0;
+  const size_t vb = vec_bytes(h, dtype);
+  const int method = o ? o->method : AQC_METHOD_PC4;
+  size_t nv = method == AQC_METHOD_RK4 ? 2 : 5;
+  if (aqc_apply_workspace_bytes(h, dtype) > 0) nv += 1;
+  const bool adaptive = o && o->n_steps == 0 && o->n_replay <= 0 && method == AQC_METHOD_PC4;
+  const bool comp = dtype == AQC_C64 && (!o || o->compensated != 0);
+  if (comp) nv += 1;
+  if (adaptive) nv += comp ? 2 : 1;
+  return nv * vb + 256;
+}
+
+extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int dtype, double t0,
+                                 double t1, const aqc_evolve_opts* o, void* ws, size_t ws_bytes,
+                                 aqc_evolve_stats* stats) {
+  STCHK(check_common(ctx, h, dtype));
+  if (!psi || !o || !stats) return fail(AQC_EINVAL, "aqc_evolve: NULL argument");
+  if (!aligned16(psi)) return fail(AQC_EINVAL, "aqc_evolve: psi must be 16-byte aligned");
+  if (!std::isfinite(t0) || !std::isfinite(t1) || !(t1 >= t0))
+    return fail(AQC_EINVAL, "aqc_evolve: need finite t0 <= t1");
+  if (o->method != AQC_METHOD_PC4 && o->method != AQC_METHOD_RK4)
+    return fail(AQC_EINVAL, "aqc_evolve: unknown method");
+  if (o->n_steps < 0) return fail(AQC_EINVAL, "aqc_evolve: n_steps < 0");
+  const bool replay = o->n_replay > 0;
+  if (replay && (!o->replay || o->method != AQC_METHOD_PC4))
+    return fail(AQC_EINVAL, "aqc_evolve: replay needs a segment list and method PC4");
+  const bool adaptive = o->n_steps == 0 && !replay;
+  if (adaptive && o->method != AQC_METHOD_PC4)
+    return fail(AQC_EINVAL, "aqc_evolve: adaptive stepping uses PC4");
+  if (adaptive && (!(o->atol > 0.0) || !(o->h0 > 0.0) || o->window < 1))
+    return fail(AQC_EINVAL, "aqc_evolve: adaptive stepping needs atol > 0, h0 > 0, window >= 1");
+  const size_t need = aqc_evolve_workspace_bytes(h, dtype, o);
+  if (!ws || ws_bytes < need)
+    return fail(AQC_ENOMEM, "aqc_evolve: workspace needs " + std::to_string(need) + " bytes");
+  if (!aligned16(ws)) return fail(AQC_EINVAL, "aqc_evolve: workspace must be 16-byte aligned");
+
+  std::memset(stats, 0, sizeof(*stats));
+  stats->status_step = -1;
+  stats->t_reached = t0;
+  aqc_ham* hm = const_cast<aqc_ham*>(h);
+  // shift and stability guard
+  double lo = 0, hi = 0;
+  const bool need_enc = o->shift_mode == AQC_SHIFT_CENTER || o->stab_limit > 0.0;
+  if (need_enc) STCHK(aqc_spectral_bounds(ctx, hm, t0, t1, &lo, &hi));
+  double shift = o->shift_mode == AQC_SHIFT_CENTER ? 0.5 * (lo + hi) : o->shift;
+  if (!std::isfinite(shift)) return fail(AQC_EINVAL, "aqc_evolve: shift not finite");
+  stats->shift_used = shift;
+  stats->rho = need_enc ? std::max(hi - shift, shift - lo) : NAN;
+
+  Evolver ev;
+  ev.ctx = ctx;
+  ev.h = h;
+  ev.dtype = dtype;
+  ev.shift = shift;
+  ev.N = (int64_t)1 << h->n;
+  ev.vb = vec_bytes(h, dtype);
+  ev.method = o->method;
+  ev.y = psi;
+  char* w = reinterpret_cast<char*>(ws);
+  ev.yp = w;
+  w += ev.vb;
+  if (o->method == AQC_METHOD_RK4) {
+    ev.B[0] = w;
+    w += ev.vb;
+    ev.B[1] = ev.B[2] = ev.B[3] = nullptr;
+  } else {
+    for (int i = 0; i < 4; ++i) {
+      ev.B[i] = w;
+      w += ev.vb;
+    }
+  }
+  ev.hbuf = nullptr;
+  if (h->plans[dtype].passes.size() > 1) {
+    ev.hbuf = w;
+    w += ev.vb;
+  }
+  ev.ycomp = nullptr;
+  ev.ckpt = nullptr;
+  ev.ckpt_lo = nullptr;
+  const bool comp = dtype == AQC_C64 && o->compensated != 0;
+  if (comp) {
+    ev.ycomp = w;
+    w += ev.vb;
+    HIPCHK(launch_zero(ev.ycomp, ev.vb, ctx->stream));
+  }
+  if (adaptive) {
+    ev.ckpt = w;
+    w += ev.vb;
+    if (comp) {
+      ev.ckpt_lo = w;
+      w += ev.vb;
+    }
+  }
+  ev.nb_last = last_nblocks(h, dtype);
+  ev.st = stats;
+  ev.check_every = o->check_every;
+  ev.norm_tol = o->norm_tol > 0 ? o->norm_tol : 1e-3;
+  STCHK(ensure_parts(ctx, 3 * (size_t)ev.nb_last + 64));
+  ev.errbuf = ctx->dres + 8;  // up to 56 per-step estimates per window
+  if (adaptive && o->window > 56) return fail(AQC_EINVAL, "aqc_evolve: window must be <= 56");
+
+  STCHK(aqc_norm2(ctx, psi, dtype, h->n, &stats->norm2_initial));
+  std::vector<double> segs;  // recorded (t_s, h, k)
+  auto record = [&](const Evolver::Seg& s) {
+    if (s.k <= 0) return;
+    segs.push_back(s.ts);
+    segs.push_back(s.h);
+    segs.push_back((double)s.k);
+  };
+  auto guard = [&](double hh) -> aqc_status {
+    if (o->method == AQC_METHOD_PC4 && o->stab_limit > 0.0 && hh * stats->rho > o->stab_limit) {
+      char buf[200];
+      snprintf(buf, sizeof buf,
+               "stability guard: h*rho = %.4g exceeds %.4g (h = %.4g, rho = %.4g after shift %.4g)",
+               hh * stats->rho, o->stab_limit, hh, stats->rho, shift);
+      return fail(AQC_EUNSTABLE, buf);
+    }
+    return AQC_OK;
+  };
+
+  aqc_status rc = AQC_OK;
+  if (!adaptive) {
+    std::vector<Evolver::Seg> list;
+    if (replay) {
+      for (int i = 0; i < o->n_replay; ++i) {
+        const double* r = o->replay + 3 * i;
+        if (!(r[1] > 0) || !(r[2] >= 1) || !std::isfinite(r[0]))
+          return fail(AQC_EINVAL, "aqc_evolve: bad replay segment");
+        list.push_back(Evolver::Seg{r[0], r[1], (int64_t)r[2]});
+      }
+    } else {
+      list.push_back(Evolver::Seg{t0, (t1 - t0) / o->n_steps, (int64_t)o->n_steps});
+    }
+    for (auto& s : list) STCHK(guard(s.h));
+    for (size_t i = 0; i < list.size() && rc == AQC_OK; ++i) {
+      Evolver::Seg s{list[i].ts, list[i].h, 0};
+      rc = ev.advance(s, list[i].k, false, nullptr, true);
+      stats->h_last = s.h;
+      record(s);
+      stats->t_reached = s.ts + (double)s.k * s.h;
+    }
+  } else {
+    // adaptive predictor-corrector (windows of W steps, Milne estimates)
+    const int W = o->window;
+    const double hmax = o->hmax > 0 ? o->hmax : INFINITY;
+    Evolver::Seg sg{t0, std::min(o->h0, hmax), 0};
+    int windows_at_h = 0;
+    std::vector<double> errs(W);
+    while (rc == AQC_OK) {
+      const double t_now = sg.ts + (double)sg.k * sg.h;
+      const double left = t1 - t_now;
+      if (left <= 0.0) break;
+      const bool fin = left <= W * sg.h * (1.0 + 1e-12);
+      int64_t nsteps = W;
+      if (fin) {
+        nsteps = std::max<int64_t>(1, (int64_t)std::ceil(left / sg.h - 1e-9));
+        const double hf = left / (double)nsteps;
+        if (hf != sg.h) {
+          record(sg);
+          sg = Evolver::Seg{t_now, hf, 0};
+          windows_at_h = 0;
+        }
+      }
+      rc = guard(sg.h);
+      if (rc != AQC_OK) break;
+      HIPCHK(launch_copy(ev.ckpt, ev.y, dtype, ev.N, ctx->stream));
+      if (ev.ckpt_lo) HIPCHK(launch_copy(ev.ckpt_lo, ev.ycomp, dtype, ev.N, ctx->stream));
+      const int64_t k_before = sg.k;
+      const int64_t steps_before = stats->steps;
+      int ne = 0;
+      rc = ev.advance(sg, nsteps, true, &ne, fin);
+      if (rc != AQC_OK) break;
+      double emax = 0.0;
+      if (ne > 0) {
+        std::vector<double> tmp(8 + ne);
+        STCHK(read_results(ctx, 8 + ne, tmp.data()));
+        for (int i = 0; i < ne; ++i) emax = std::max(emax, kMilne * std::sqrt(tmp[8 + i]));
+      }
+      if (emax > o->atol && sg.h / 2.0 >= o->hmin) {
+        stats->rejected += (stats->steps - steps_before);
+        stats->steps = steps_before;
+        HIPCHK(launch_copy(ev.y, ev.ckpt, dtype, ev.N, ctx->stream));
+        if (ev.ckpt_lo) HIPCHK(launch_copy(ev.ycomp, ev.ckpt_lo, dtype, ev.N, ctx->stream));
+        Evolver::Seg old{sg.ts, sg.h, k_before};
+        record(old);
+        sg = Evolver::Seg{sg.ts + (double)k_before * sg.h, sg.h / 2.0, 0};
+        windows_at_h = 0;
+        continue;
+      }
+      stats->max_err = std::max(stats->max_err, emax);
+      ++windows_at_h;
+      if (fin) {
+        record(sg);
+        stats->t_reached = sg.ts + (double)sg.k * sg.h;
+        stats->h_last = sg.h;
+        break;
+      }
+      if (emax < o->atol / 64.0 && windows_at_h >= 2 && 2.0 * sg.h <= hmax) {
+        record(sg);
+        sg = Evolver::Seg{sg.ts + (double)sg.k * sg.h, 2.0 * sg.h, 0};
+        windows_at_h = 0;
+      }
+      stats->h_last = sg.h;
+      stats->t_reached = sg.ts + (double)sg.k * sg.h;
+    }
+  }
+  stats->n_segments = (int32_t)(segs.size() / 3);
+  if (o->record && o->record_cap > 0) {
+    const size_t m = std::min<size_t>(segs.size(), (size_t)o->record_cap * 3);
+    std::memcpy(o->record, segs.data(), m * sizeof(double));
+  }
+  if (rc != AQC_OK) return rc;
+  if (shift != 0.0) {
+    const double ph = -shift * (t1 - t0);
+    HIPCHK(launch_scale(psi, dtype, ev.N, std::cos(ph), std::sin(ph), ctx->stream));
+  }
+  STCHK(aqc_norm2(ctx, psi, dtype, h->n, &stats->norm2_final));
+  stats->t_reached = t1;
+  return AQC_OK;
+}

@@ -1,0 +1,133 @@
+// Internal interface between the host runtime (aqc_host.cpp) and the HIP
+// kernels (aqc_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace aqc {
+
+constexpr int kMaxSched = 16;       // schedules per Hamiltonian
+constexpr int kMaxDiagSched = 4;    // schedules with split diagonal tables
+constexpr int kMaxTabSched = 4;     // schedules with a low-bit diagonal table
+constexpr int kMaxPassGroups = 256;
+constexpr int kMaxPassTerms = 512;
+constexpr int kThreads = 512;       // threads per tile workgroup
+constexpr int kRedThreads = 256;    // threads per reduction workgroup
+
+// One Pauli term inside a flip group or the residual diagonal list.
+// The operator is w * f_sid(t) * i^p * X^x Z^z with p = popc(x & z) mod 4
+// (sigma^y = i sigma^x sigma^z on each qubit that carries it).
+struct DevTerm {
+  uint64_t z;
+  double w;
+  int32_t sid;
+  int32_t p;
+};
+
+// All terms sharing one flip pattern x.  (H psi)[g] gets
+// c_x(g) psi[g ^ x] with c_x(g) = sum_t m_t i^{p_t} (-1)^{popc((g ^ x) & z_t)}.
+struct DevGroup {
+  uint64_t x;      // global flip mask
+  uint32_t xl;     // the same mask in tile-local coordinates
+  int32_t t0;      // first term (index into the pass's term array)
+  int32_t nt;      // number of terms
+  int32_t plain;   // 1: all z_t = 0 and p_t = 0, so c_x is one real number
+};
+
+// Diagonal part split for a tile of `tb` low bits ("lo") and the remaining
+// high bits ("hi"): E_s(g) = CT_s[hi] + sum_{i<tb} LT_s[hi][i] (-1)^{lo_i}
+//                           + TAB_s[lo] + (residual terms, evaluated directly).
+struct DiagDev {
+  int32_t nsd;                  // schedules with CT/LT tables
+  int32_t sd_sid[kMaxDiagSched];
+  int32_t ntab;                 // schedules with a TAB table
+  int32_t tab_sid[kMaxTabSched];
+  int32_t nres;                 // residual terms
+  int32_t pad;
+  const double* CT;             // [nsd][2^(n-tb)]
+  const double* LT;             // [nsd][2^(n-tb)][tb]
+  const double* TAB64;          // [ntab][2^tb]
+  const float* TAB32;           // [ntab][2^tb]
+  const DevTerm* res;           // [nres]
+};
+
+// Epilogue of the last pass.  With Hv = ((H - c) u)[g], u the tile value and
+// in_1..in_3 streamed inputs, output j is
+//   out_j = c0_j in_0 + cu_j u + scale_j (sum_i a_j[i] in_{i+1} + (br_j + i bi_j) Hv)
+// The weights c0, cu, a, br, bi are small integers (exact in float32); the
+// step-size factor scale_j is applied as a float-float pair in complex64
+// kernels, so the integrator's weights carry no float32 rounding.
+// Compensated state (complex64): `comp` holds the low part y_lo of in_0 = y.
+// Bit j of comp_flags (j < 3) adds y_lo to out_j's increment; bit 3 makes
+// out_0 = in_0 + increment an exact two-sum whose error is written back to
+// comp.  Reductions (float64, per workgroup):
+//   red0 = sum |out_0|^2, red1 = sum |out_0 - u|^2, red2 = sum Re(conj(u) Hv).
+struct EpiDesc {
+  const void* in[4];
+  void* out[3];
+  void* comp;
+  double c0[3];
+  double cu[3];
+  double a[3][3];
+  double br[3];
+  double bi[3];
+  double scale[3];
+  double* red;        // [3][nblocks] partial sums or nullptr
+  int32_t red_flags;  // bit0 red0, bit1 red1, bit2 red2
+  int32_t comp_flags;
+};
+
+struct PassArgs {
+  int32_t n;          // qubits
+  int32_t tb;         // tile bits
+  int32_t lbits;      // contiguous low bits of the tile
+  int32_t final_pass; // 1: add the diagonal, read acc_in, run the epilogue
+  uint64_t hmask;     // high bits of the tile (outside [0, lbits))
+  uint64_t cmask;     // bits outside the tile (enumerate the workgroups)
+  const void* src;    // tile source vector u
+  const DevGroup* groups;
+  const DevTerm* terms;
+  int32_t ng;
+  int32_t nterms;
+  double f[kMaxSched];   // schedule values at this time
+  double dconst;         // constant added to the diagonal (identity terms - shift)
+  DiagDev dg;
+  const void* acc_in;    // partial H u from earlier passes (or nullptr)
+  void* acc_out;         // high passes: partial H u written here
+  EpiDesc epi;
+};
+
+// ---- launchers (aqc_kernels.hip) -------------------------------------------
+hipError_t launch_pass(const PassArgs& a, int dtype, int64_t nblocks, hipStream_t s);
+size_t pass_lds_bytes(int tb, int dtype);
+hipError_t prepare_kernels();
+
+// red: per-block partials [k][nblocks] -> out[k] (k < nk), fixed-order sum
+hipError_t launch_reduce_sum(const double* parts, int64_t nblocks, int nk, double* out,
+                             hipStream_t s);
+// sum |psi|^2 -> parts[nblocks]; returns nblocks via *nb
+hipError_t launch_norm2(const void* psi, int dtype, int64_t N, double* parts, int64_t* nb,
+                        hipStream_t s);
+// sum conj(phi) psi -> parts[2][nb]
+hipError_t launch_overlap(const void* phi, const void* psi, int dtype, int64_t N, double* parts,
+                          int64_t* nb, hipStream_t s);
+// sum of |psi_z|^2 over a device list of indices -> parts[nb]
+hipError_t launch_gather_mass(const void* psi, int dtype, const int64_t* idx, int64_t m,
+                              double* parts, int64_t* nb, hipStream_t s);
+// per tile minimum and maximum of the diagonal part (float64 tables):
+// minmax[2][nblocks]; each schedule separately when sid_only >= 0
+hipError_t launch_diag_minmax(const PassArgs& a, int64_t nblocks, double* parts, hipStream_t s);
+// mass of psi where diag(g) <= thr -> parts[nblocks]
+hipError_t launch_diag_mass(const PassArgs& a, int dtype, int64_t nblocks, double thr,
+                            double* parts, hipStream_t s);
+// y *= (re + i im)
+hipError_t launch_scale(void* y, int dtype, int64_t N, double re, double im, hipStream_t s);
+// out = y + c0 f0 + c1 f1 + c2 f2 + c3 f3 (real coefficients): the Adams-Bashforth predictor
+hipError_t launch_ab4(void* out, const void* y, const void* f0, const void* f1, const void* f2,
+                      const void* f3, const double c[4], int dtype, int64_t N, hipStream_t s);
+hipError_t launch_copy(void* dst, const void* src, int dtype, int64_t N, hipStream_t s);
+// zero `bytes` (a multiple of 16) with a fill kernel
+hipError_t launch_zero(void* dst, size_t bytes, hipStream_t s);
+
+}  // namespace aqc

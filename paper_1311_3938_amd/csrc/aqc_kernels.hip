@@ -1,0 +1,645 @@
+// HIP kernels (gfx950) for the matrix-free product H(t)|psi> of Sec. II.A and
+// the integrator stages of Sec. II.B, with float64 reductions.
+//
+// Tile passes.  A workgroup holds a tile of 2^tb amplitudes of the source
+// vector u in LDS: `lbits` contiguous low bits (coalesced 16-byte loads) plus
+// the high bits in `hmask`.  Every flip pattern x whose bits all lie in the
+// tile is applied from LDS: (H u)[g] += c_x(g) u[g ^ x].  Flip patterns with
+// bits above the last pass's tile are handled by earlier passes whose tiles
+// include those bits; they write a partial product that the last pass reads.
+// The last pass tiles the low tb bits contiguously, adds the diagonal from
+// split tables (popcount parity folded per tile), and fuses the integrator's
+// stage update (a fixed linear combination of H u with up to four streamed
+// vectors and u itself).
+#include <hip/hip_runtime.h>
+
+#include "aqc_internal.h"
+
+namespace aqc {
+
+template <typename R> struct CT2;
+template <> struct CT2<float> { using V = float2; };
+template <> struct CT2<double> { using V = double2; };
+
+// Deposit the low bits of v into the set bits of mask (ascending order).
+__device__ __forceinline__ uint64_t pdep64(uint64_t v, uint64_t mask) {
+  uint64_t r = 0;
+  while (mask) {
+    const uint64_t low = mask & (~mask + 1ull);
+    if (v & 1ull) r |= low;
+    v >>= 1;
+    mask &= mask - 1ull;
+  }
+  return r;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Fixed-order block reduction of up to 3 values; thread 0 writes parts.
+template <int NT>
+__device__ __forceinline__ void block_reduce3(double r0, double r1, double r2, int flags,
+                                              double* sbuf, double* parts, int64_t nblocks,
+                                              int64_t bid) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  constexpr int NW = NT / 64;
+  if (flags & 1) r0 = wave_sum(r0);
+  if (flags & 2) r1 = wave_sum(r1);
+  if (flags & 4) r2 = wave_sum(r2);
+  if (lane == 0) {
+    sbuf[0 * NW + wv] = r0;
+    sbuf[1 * NW + wv] = r1;
+    sbuf[2 * NW + wv] = r2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      s0 += sbuf[0 * NW + w];
+      s1 += sbuf[1 * NW + w];
+      s2 += sbuf[2 * NW + w];
+    }
+    if (flags & 1) parts[0 * nblocks + bid] = s0;
+    if (flags & 2) parts[1 * nblocks + bid] = s1;
+    if (flags & 4) parts[2 * nblocks + bid] = s2;
+  }
+}
+
+// LDS layout of a tile workgroup (offsets in bytes, 16-byte aligned pieces).
+struct Lds {
+  static constexpr int kF = 0;                                   // double f[16]
+  static constexpr int kLin = kF + 8 * kMaxSched;                // double lin[16]
+  static constexpr int kC = kLin + 8 * 16;                       // double C'
+  static constexpr int kRed = kC + 16;                           // double [3][NW]
+  static constexpr int kLA = kRed + 8 * 3 * (kThreads / 64);     // R LA[128]
+  static constexpr int kLB = kLA + 8 * 128;                      // R LB[128]
+  static constexpr int kGco = kLB + 8 * 128;                     // R gco[kMaxPassGroups]
+  static constexpr int kTm = kGco + 8 * kMaxPassGroups;          // R tm[kMaxPassTerms]
+  static constexpr int kTile = kTm + 8 * kMaxPassTerms;          // V tile[2^tb]
+};
+
+size_t pass_lds_bytes(int tb, int dtype) {
+  const size_t es = dtype == 0 ? 8 : 16;
+  return (size_t)Lds::kTile + (es << tb);
+}
+
+// Per-tile diagonal set-up (hi = the tile's high bits): C' and the linear
+// coefficients, then the two sign tables LA (bits 0..6) and LB (bits 7..tb-1).
+template <typename R>
+__device__ __forceinline__ void diag_setup_a(const PassArgs& a, uint64_t hi, const double* fsh,
+                                             double* lin, double* cp) {
+  const int tid = threadIdx.x;
+  const int tb = a.tb;
+  const int64_t nhi = (int64_t)1 << (a.n - tb);
+  if (tid < tb) {
+    double v = 0.0;
+#pragma unroll
+    for (int s = 0; s < kMaxDiagSched; ++s) {
+      if (s < a.dg.nsd) v += fsh[a.dg.sd_sid[s]] * a.dg.LT[((int64_t)s * nhi + (int64_t)hi) * tb + tid];
+    }
+    lin[tid] = v;
+  }
+  if (tid == 64) {
+    double c = a.dconst;
+#pragma unroll
+    for (int s = 0; s < kMaxDiagSched; ++s) {
+      if (s < a.dg.nsd) c += fsh[a.dg.sd_sid[s]] * a.dg.CT[(int64_t)s * nhi + (int64_t)hi];
+    }
+    *cp = c;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void diag_setup_b(const PassArgs& a, const double* lin, R* LA, R* LB) {
+  const int tid = threadIdx.x;
+  const int tb = a.tb;
+  const int na = tb < 7 ? tb : 7;
+  const int nb = tb > 7 ? tb - 7 : 0;
+  if (tid < 128) {
+    double v = 0.0;
+    if (tid < (1 << na)) {
+      for (int i = 0; i < na; ++i) v += ((tid >> i) & 1) ? -lin[i] : lin[i];
+    }
+    LA[tid] = (R)v;
+  } else if (tid < 256) {
+    const int b = tid - 128;
+    double v = 0.0;
+    if (b < (1 << nb)) {
+      for (int i = 0; i < nb; ++i) v += ((b >> i) & 1) ? -lin[7 + i] : lin[7 + i];
+    }
+    LB[b] = (R)v;
+  }
+}
+
+// Diagonal energy of the tile element with low bits lo and global index g.
+template <typename R>
+__device__ __forceinline__ R diag_value(const PassArgs& a, uint32_t lo, uint64_t g, R cprime,
+                                        const R* LA, const R* LB, const double* fsh) {
+  R d = cprime + LA[lo & 127u] + LB[lo >> 7];
+  const int64_t ntile = (int64_t)1 << a.tb;
+#pragma unroll
+  for (int s = 0; s < kMaxTabSched; ++s) {
+    if (s < a.dg.ntab) {
+      // the product is formed in float64 and rounded once, so the float32
+      // kernel carries no fixed rounding of the table entries
+      d += (R)(fsh[a.dg.tab_sid[s]] * a.dg.TAB64[(int64_t)s * ntile + lo]);
+    }
+  }
+  for (int k = 0; k < a.dg.nres; ++k) {
+    const DevTerm t = a.dg.res[k];
+    const R m = (R)(t.w * fsh[t.sid]);
+    d += (__popcll(g & t.z) & 1) ? -m : m;
+  }
+  return d;
+}
+
+template <typename R, bool FINAL>
+__global__ __launch_bounds__(kThreads) void k_pass(const PassArgs a) {
+  using V = typename CT2<R>::V;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* fsh = reinterpret_cast<double*>(smem + Lds::kF);
+  double* lin = reinterpret_cast<double*>(smem + Lds::kLin);
+  double* cps = reinterpret_cast<double*>(smem + Lds::kC);
+  double* rbuf = reinterpret_cast<double*>(smem + Lds::kRed);
+  R* LA = reinterpret_cast<R*>(smem + Lds::kLA);
+  R* LB = reinterpret_cast<R*>(smem + Lds::kLB);
+  R* gco = reinterpret_cast<R*>(smem + Lds::kGco);
+  R* tm = reinterpret_cast<R*>(smem + Lds::kTm);
+  V* tile = reinterpret_cast<V*>(smem + Lds::kTile);
+
+  const int tid = threadIdx.x;
+  const int tb = a.tb;
+  const uint32_t ntile = 1u << tb;
+  const int64_t bid = blockIdx.x;
+  const int64_t nblocks = gridDim.x;
+  const uint64_t lowmask = (1ull << a.lbits) - 1ull;
+  const uint64_t tmask = lowmask | a.hmask;
+  const uint64_t base = FINAL ? ((uint64_t)bid << tb) : pdep64((uint64_t)bid, a.cmask);
+
+  // ---- 1. issue the tile loads (16 bytes per chunk) ----------------------
+  constexpr int VEC = 16 / (int)sizeof(V);            // elements per chunk
+  constexpr int LOGV = VEC == 2 ? 1 : 0;
+  constexpr int kMaxChunks = 16;                       // per thread (tile <= 128 KiB)
+  const uint32_t nchunks = ntile / VEC;
+  const V* src = reinterpret_cast<const V*>(a.src);
+  // local element l = q*VEC with q = tid + kThreads*j: the tid part and the j
+  // part occupy disjoint bits of l, so their deposits can be OR-ed.
+  const uint64_t dep_tid = FINAL ? ((uint64_t)tid << LOGV) : pdep64((uint64_t)tid << LOGV, tmask);
+#pragma unroll
+  for (int j = 0; j < kMaxChunks; ++j) {
+    const uint32_t q = tid + kThreads * j;
+    if (q < nchunks) {
+      const uint64_t jpart = (uint64_t)(kThreads * j) << LOGV;
+      const uint64_t g = base | dep_tid | (FINAL ? jpart : pdep64(jpart, tmask));
+      *reinterpret_cast<uint4*>(tile + q * VEC) = *reinterpret_cast<const uint4*>(src + g);
+    }
+  }
+
+  // ---- 2. per-workgroup coefficients --------------------------------------
+  if (tid < kMaxSched) fsh[tid] = a.f[tid];
+  __syncthreads();
+  if (FINAL) diag_setup_a<R>(a, (uint64_t)bid, fsh, lin, cps);
+  for (int g = tid; g < a.ng; g += kThreads) {
+    const DevGroup gr = a.groups[g];
+    double c = 0.0;
+    if (gr.plain) {
+      for (int t = 0; t < gr.nt; ++t) {
+        const DevTerm tt = a.terms[gr.t0 + t];
+        c += tt.w * fsh[tt.sid];
+      }
+    }
+    gco[g] = (R)c;
+  }
+  for (int t = tid; t < a.nterms; t += kThreads) {
+    const DevTerm tt = a.terms[t];
+    tm[t] = (R)(tt.w * fsh[tt.sid]);
+  }
+  __syncthreads();
+  if (FINAL) diag_setup_b<R>(a, lin, LA, LB);
+  __syncthreads();
+
+  // ---- 3. products and epilogue --------------------------------------------
+  const R cprime = FINAL ? (R)cps[0] : (R)0;
+  const V* accin = reinterpret_cast<const V*>(a.acc_in);
+  V* accout = reinterpret_cast<V*>(a.acc_out);
+  const EpiDesc& e = a.epi;
+  R c0[3], cu[3], ca[3][3], br[3], bi[3], sh[3], sl[3];
+#pragma unroll
+  for (int o = 0; o < 3; ++o) {
+    c0[o] = (R)e.c0[o];
+    cu[o] = (R)e.cu[o];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) ca[o][i] = (R)e.a[o][i];
+    br[o] = (R)e.br[o];
+    bi[o] = (R)e.bi[o];
+    sh[o] = (R)e.scale[o];
+    sl[o] = (R)(e.scale[o] - (double)sh[o]);   // zero in float64 kernels
+  }
+  const bool has_comp = FINAL && e.comp != nullptr;
+  V* compv = reinterpret_cast<V*>(e.comp);
+  double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+  const uint32_t E = ntile >= (uint32_t)kThreads ? ntile / kThreads : 1u;
+  const uint64_t edep_tid = FINAL ? (uint64_t)tid : pdep64((uint64_t)tid, tmask);
+  constexpr int U = sizeof(R) == 4 ? 4 : 2;
+  for (uint32_t j0 = 0; j0 < E; j0 += U) {
+    V ain[U], xin[U][4], lo[U];
+    uint64_t gidx[U];
+    uint32_t lidx[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t j = j0 + u;
+      const uint32_t l = tid + kThreads * j;
+      ok[u] = (j < E) && (l < ntile);
+      lidx[u] = l;
+      const uint64_t jpart = (uint64_t)kThreads * j;
+      gidx[u] = base | edep_tid | (FINAL ? jpart : pdep64(jpart, tmask));
+      ain[u] = V{0, 0};
+      if (ok[u] && accin) ain[u] = accin[gidx[u]];
+      if (FINAL) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          xin[u][i] = V{0, 0};
+          if (ok[u] && e.in[i]) xin[u][i] = reinterpret_cast<const V*>(e.in[i])[gidx[u]];
+        }
+        lo[u] = V{0, 0};
+        if (ok[u] && has_comp) lo[u] = compv[gidx[u]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!ok[u]) continue;
+      const uint32_t l = lidx[u];
+      const uint64_t g = gidx[u];
+      const V uv = tile[l];
+      R hr = ain[u].x, hi = ain[u].y;
+      if (FINAL) {
+        const R d = diag_value<R>(a, l, g, cprime, LA, LB, fsh);
+        hr += d * uv.x;
+        hi += d * uv.y;
+      }
+      for (int k = 0; k < a.ng; ++k) {
+        const DevGroup gr = a.groups[k];
+        const V v = tile[l ^ gr.xl];
+        if (gr.plain) {
+          const R c = gco[k];
+          hr += c * v.x;
+          hi += c * v.y;
+        } else {
+          const uint64_t src_idx = g ^ gr.x;
+          R cr = 0, ci = 0;
+          for (int t = 0; t < gr.nt; ++t) {
+            const DevTerm tt = a.terms[gr.t0 + t];
+            R m = tm[gr.t0 + t];
+            if (__popcll(src_idx & tt.z) & 1) m = -m;
+            switch (tt.p & 3) {
+              case 0: cr += m; break;
+              case 1: ci += m; break;
+              case 2: cr -= m; break;
+              default: ci -= m; break;
+            }
+          }
+          hr += cr * v.x - ci * v.y;
+          hi += cr * v.y + ci * v.x;
+        }
+      }
+      if (!FINAL) {
+        accout[g] = V{hr, hi};
+        continue;
+      }
+#pragma unroll
+      for (int o = 0; o < 3; ++o) {
+        if (!e.out[o]) continue;
+        // increment: scale * (sum a x + b Hv), scale as a float-float pair
+        R ir = br[o] * hr - bi[o] * hi;
+        R ii = br[o] * hi + bi[o] * hr;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          ir += ca[o][i] * xin[u][i + 1].x;
+          ii += ca[o][i] * xin[u][i + 1].y;
+        }
+        R vr = sh[o] * ir + sl[o] * ir;
+        R vi = sh[o] * ii + sl[o] * ii;
+        if (e.comp_flags & (1 << o)) {
+          vr += lo[u].x;
+          vi += lo[u].y;
+        }
+        const R bre = c0[o] * xin[u][0].x + cu[o] * uv.x;
+        const R bim = c0[o] * xin[u][0].y + cu[o] * uv.y;
+        R sr = bre + vr, si = bim + vi;
+        if (o == 0 && (e.comp_flags & 8)) {
+          // two-sum: the rounding error of bre + vr goes to the low part
+          const R tr = sr - bre, ti = si - bim;
+          const R er = (bre - (sr - tr)) + (vr - tr);
+          const R ei = (bim - (si - ti)) + (vi - ti);
+          compv[g] = V{er, ei};
+        }
+        reinterpret_cast<V*>(e.out[o])[g] = V{sr, si};
+        if (o == 0) {
+          if (e.red_flags & 1) r0 += (double)sr * (double)sr + (double)si * (double)si;
+          if (e.red_flags & 2) {
+            const double dr = (double)sr - (double)uv.x, di = (double)si - (double)uv.y;
+            r1 += dr * dr + di * di;
+          }
+        }
+      }
+      if (e.red_flags & 4) r2 += (double)uv.x * (double)hr + (double)uv.y * (double)hi;
+    }
+  }
+  if (FINAL && e.red_flags) block_reduce3<kThreads>(r0, r1, r2, e.red_flags, rbuf, e.red, nblocks, bid);
+}
+
+template <typename R, bool FINAL>
+static hipError_t set_lds_attr() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass<R, FINAL>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)pass_lds_bytes(sizeof(R) == 4 ? 14 : 13, sizeof(R) == 4 ? 0 : 1));
+}
+
+hipError_t prepare_kernels() {
+  hipError_t e;
+  if ((e = set_lds_attr<float, false>()) != hipSuccess) return e;
+  if ((e = set_lds_attr<float, true>()) != hipSuccess) return e;
+  if ((e = set_lds_attr<double, false>()) != hipSuccess) return e;
+  if ((e = set_lds_attr<double, true>()) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+hipError_t launch_pass(const PassArgs& a, int dtype, int64_t nblocks, hipStream_t s) {
+  const size_t lds = pass_lds_bytes(a.tb, dtype);
+  dim3 grid((unsigned)nblocks), block(kThreads);
+  if (dtype == 0) {
+    if (a.final_pass) hipLaunchKernelGGL((k_pass<float, true>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((k_pass<float, false>), grid, block, lds, s, a);
+  } else {
+    if (a.final_pass) hipLaunchKernelGGL((k_pass<double, true>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((k_pass<double, false>), grid, block, lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Reductions
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_sum(const double* parts, int64_t nb, int nk,
+                                                            double* out) {
+  __shared__ double sb[kRedThreads];
+  for (int k = 0; k < nk; ++k) {
+    double v = 0.0;
+    for (int64_t i = threadIdx.x; i < nb; i += kRedThreads) v += parts[k * nb + i];
+    sb[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) sb[threadIdx.x] += sb[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = sb[0];
+    __syncthreads();
+  }
+}
+
+hipError_t launch_reduce_sum(const double* parts, int64_t nblocks, int nk, double* out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(kRedThreads), 0, s, parts, nblocks, nk, out);
+  return hipGetLastError();
+}
+
+static int64_t red_blocks(int64_t N) {
+  int64_t nb = (N + (int64_t)kRedThreads * 16 - 1) / ((int64_t)kRedThreads * 16);
+  if (nb > 16384) nb = 16384;
+  if (nb < 1) nb = 1;
+  return nb;
+}
+
+template <typename V>
+__global__ __launch_bounds__(kRedThreads) void k_norm2(const V* psi, int64_t N, double* parts) {
+  __shared__ double sb[3 * (kRedThreads / 64)];
+  double r = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    const V v = psi[i];
+    r += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+  }
+  block_reduce3<kRedThreads>(r, 0.0, 0.0, 1, sb, parts, gridDim.x, blockIdx.x);
+}
+
+hipError_t launch_norm2(const void* psi, int dtype, int64_t N, double* parts, int64_t* nb,
+                        hipStream_t s) {
+  *nb = red_blocks(N);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_norm2<float2>, dim3((unsigned)*nb), dim3(kRedThreads), 0, s,
+                       (const float2*)psi, N, parts);
+  else
+    hipLaunchKernelGGL(k_norm2<double2>, dim3((unsigned)*nb), dim3(kRedThreads), 0, s,
+                       (const double2*)psi, N, parts);
+  return hipGetLastError();
+}
+
+template <typename V>
+__global__ __launch_bounds__(kRedThreads) void k_overlap(const V* phi, const V* psi, int64_t N,
+                                                         double* parts) {
+  __shared__ double sb[3 * (kRedThreads / 64)];
+  double re = 0.0, im = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    const V a = phi[i], b = psi[i];
+    re += (double)a.x * (double)b.x + (double)a.y * (double)b.y;
+    im += (double)a.x * (double)b.y - (double)a.y * (double)b.x;
+  }
+  block_reduce3<kRedThreads>(re, im, 0.0, 3, sb, parts, gridDim.x, blockIdx.x);
+}
+
+hipError_t launch_overlap(const void* phi, const void* psi, int dtype, int64_t N, double* parts,
+                          int64_t* nb, hipStream_t s) {
+  *nb = red_blocks(N);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_overlap<float2>, dim3((unsigned)*nb), dim3(kRedThreads), 0, s,
+                       (const float2*)phi, (const float2*)psi, N, parts);
+  else
+    hipLaunchKernelGGL(k_overlap<double2>, dim3((unsigned)*nb), dim3(kRedThreads), 0, s,
+                       (const double2*)phi, (const double2*)psi, N, parts);
+  return hipGetLastError();
+}
+
+template <typename V>
+__global__ __launch_bounds__(kRedThreads) void k_gather_mass(const V* psi, const int64_t* idx,
+                                                             int64_t m, double* parts) {
+  __shared__ double sb[3 * (kRedThreads / 64)];
+  double r = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    const V v = psi[idx[i]];
+    r += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+  }
+  block_reduce3<kRedThreads>(r, 0.0, 0.0, 1, sb, parts, gridDim.x, blockIdx.x);
+}
+
+hipError_t launch_gather_mass(const void* psi, int dtype, const int64_t* idx, int64_t m,
+                              double* parts, int64_t* nb, hipStream_t s) {
+  *nb = red_blocks(m);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_gather_mass<float2>, dim3((unsigned)*nb), dim3(kRedThreads), 0, s,
+                       (const float2*)psi, idx, m, parts);
+  else
+    hipLaunchKernelGGL(k_gather_mass<double2>, dim3((unsigned)*nb), dim3(kRedThreads), 0, s,
+                       (const double2*)psi, idx, m, parts);
+  return hipGetLastError();
+}
+
+// Diagonal over one tile of the last pass's geometry (always float64).
+__device__ __forceinline__ void diag_tile_setup(const PassArgs& a, double* fsh, double* lin,
+                                                double* cps, double* LA, double* LB) {
+  if (threadIdx.x < kMaxSched) fsh[threadIdx.x] = a.f[threadIdx.x];
+  __syncthreads();
+  diag_setup_a<double>(a, (uint64_t)blockIdx.x, fsh, lin, cps);
+  __syncthreads();
+  diag_setup_b<double>(a, lin, LA, LB);
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kThreads) void k_diag_minmax(const PassArgs a, double* parts) {
+  __shared__ double fsh[kMaxSched], lin[16], cps[1], LA[128], LB[128];
+  __shared__ double sb[2 * (kThreads / 64)];
+  diag_tile_setup(a, fsh, lin, cps, LA, LB);
+  const uint32_t ntile = 1u << a.tb;
+  const uint64_t base = (uint64_t)blockIdx.x << a.tb;
+  double mn = INFINITY, mx = -INFINITY;
+  for (uint32_t l = threadIdx.x; l < ntile; l += kThreads) {
+    const double d = diag_value<double>(a, l, base + l, cps[0], LA, LB, fsh);
+    mn = fmin(mn, d);
+    mx = fmax(mx, d);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mn = fmin(mn, __shfl_xor(mn, o, 64));
+    mx = fmax(mx, __shfl_xor(mx, o, 64));
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sb[wv] = mn;
+    sb[kThreads / 64 + wv] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kThreads / 64; ++w) {
+      mn = fmin(mn, sb[w]);
+      mx = fmax(mx, sb[kThreads / 64 + w]);
+    }
+    mn = fmin(mn, sb[0]);
+    mx = fmax(mx, sb[kThreads / 64]);
+    parts[blockIdx.x] = mn;
+    parts[gridDim.x + blockIdx.x] = mx;
+  }
+}
+
+hipError_t launch_diag_minmax(const PassArgs& a, int64_t nblocks, double* parts, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_minmax, dim3((unsigned)nblocks), dim3(kThreads), 0, s, a, parts);
+  return hipGetLastError();
+}
+
+template <typename V>
+__global__ __launch_bounds__(kThreads) void k_diag_mass(const PassArgs a, const V* psi, double thr,
+                                                        double* parts) {
+  __shared__ double fsh[kMaxSched], lin[16], cps[1], LA[128], LB[128];
+  __shared__ double sb[3 * (kThreads / 64)];
+  diag_tile_setup(a, fsh, lin, cps, LA, LB);
+  const uint32_t ntile = 1u << a.tb;
+  const uint64_t base = (uint64_t)blockIdx.x << a.tb;
+  double r = 0.0;
+  for (uint32_t l = threadIdx.x; l < ntile; l += kThreads) {
+    const double d = diag_value<double>(a, l, base + l, cps[0], LA, LB, fsh);
+    if (d <= thr) {
+      const V v = psi[base + l];
+      r += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+    }
+  }
+  block_reduce3<kThreads>(r, 0.0, 0.0, 1, sb, parts, gridDim.x, blockIdx.x);
+}
+
+hipError_t launch_diag_mass(const PassArgs& a, int dtype, int64_t nblocks, double thr,
+                            double* parts, hipStream_t s) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_diag_mass<float2>, dim3((unsigned)nblocks), dim3(kThreads), 0, s, a,
+                       (const float2*)a.src, thr, parts);
+  else
+    hipLaunchKernelGGL(k_diag_mass<double2>, dim3((unsigned)nblocks), dim3(kThreads), 0, s, a,
+                       (const double2*)a.src, thr, parts);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise
+// ---------------------------------------------------------------------------
+
+static unsigned ew_blocks(int64_t N) {
+  int64_t nb = (N + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  return (unsigned)(nb < 1 ? 1 : nb);
+}
+
+template <typename V, typename R>
+__global__ void k_scale(V* y, int64_t N, R re, R im) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const V v = y[i];
+    y[i] = V{re * v.x - im * v.y, re * v.y + im * v.x};
+  }
+}
+
+hipError_t launch_scale(void* y, int dtype, int64_t N, double re, double im, hipStream_t s) {
+  if (dtype == 0)
+    hipLaunchKernelGGL((k_scale<float2, float>), dim3(ew_blocks(N)), dim3(256), 0, s, (float2*)y, N,
+                       (float)re, (float)im);
+  else
+    hipLaunchKernelGGL((k_scale<double2, double>), dim3(ew_blocks(N)), dim3(256), 0, s,
+                       (double2*)y, N, re, im);
+  return hipGetLastError();
+}
+
+template <typename V, typename R>
+__global__ void k_ab4(V* out, const V* y, const V* f0, const V* f1, const V* f2, const V* f3, R c0,
+                      R c1, R c2, R c3, int64_t N) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const V a = y[i], b0 = f0[i], b1 = f1[i], b2 = f2[i], b3 = f3[i];
+    out[i] = V{a.x + c0 * b0.x + c1 * b1.x + c2 * b2.x + c3 * b3.x,
+               a.y + c0 * b0.y + c1 * b1.y + c2 * b2.y + c3 * b3.y};
+  }
+}
+
+hipError_t launch_ab4(void* out, const void* y, const void* f0, const void* f1, const void* f2,
+                      const void* f3, const double c[4], int dtype, int64_t N, hipStream_t s) {
+  if (dtype == 0)
+    hipLaunchKernelGGL((k_ab4<float2, float>), dim3(ew_blocks(N)), dim3(256), 0, s, (float2*)out,
+                       (const float2*)y, (const float2*)f0, (const float2*)f1, (const float2*)f2,
+                       (const float2*)f3, (float)c[0], (float)c[1], (float)c[2], (float)c[3], N);
+  else
+    hipLaunchKernelGGL((k_ab4<double2, double>), dim3(ew_blocks(N)), dim3(256), 0, s,
+                       (double2*)out, (const double2*)y, (const double2*)f0, (const double2*)f1,
+                       (const double2*)f2, (const double2*)f3, c[0], c[1], c[2], c[3], N);
+  return hipGetLastError();
+}
+
+__global__ void k_zero(uint4* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = uint4{0u, 0u, 0u, 0u};
+}
+
+hipError_t launch_zero(void* dst, size_t bytes, hipStream_t s) {
+  const int64_t n = (int64_t)(bytes / 16);
+  hipLaunchKernelGGL(k_zero, dim3(ew_blocks(n)), dim3(256), 0, s, (uint4*)dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(void* dst, const void* src, int dtype, int64_t N, hipStream_t s) {
+  return hipMemcpyAsync(dst, src, (size_t)N * (dtype == 0 ? 8 : 16), hipMemcpyDeviceToDevice, s);
+}
+
+}  // namespace aqc

@@ -1,0 +1,260 @@
+"""Python front end of the HIP library: contexts, Hamiltonians, H|psi>,
+time evolution and float64 reductions on torch device tensors.
+
+torch provides the device memory and the stream; every computation is a call
+into libaqc.so (include/aqc.h)."""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import check, lib
+
+
+def dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.complex64:
+        return L.C64
+    if t.dtype == torch.complex128:
+        return L.C128
+    raise TypeError(f"state must be complex64 or complex128, got {t.dtype}")
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A device plus a HIP stream (torch's current stream by default)."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the engine runs on the HIP device only")
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        check(lib().aqc_create(device, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        self.stream = stream
+        check(lib().aqc_set_stream(self._h, C.c_void_p(stream.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().aqc_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Hamiltonian:
+    """Compiled form of an ``instances.Instance`` (terms, schedules, path)."""
+
+    def __init__(self, ctx: Context, inst):
+        self.ctx = ctx
+        self.n = int(inst.n)
+        x = np.ascontiguousarray(inst.x, dtype=np.uint64)
+        z = np.ascontiguousarray(inst.z, dtype=np.uint64)
+        w = np.ascontiguousarray(inst.w, dtype=np.float64)
+        sid = np.ascontiguousarray(inst.sid, dtype=np.int32)
+        ns = len(inst.scheds)
+        sch = (L.Sched * ns)(*[L.make_sched(s) for s in inst.scheds])
+        path = L.make_path(inst.path)
+        h = C.c_void_p()
+        u64p = C.POINTER(C.c_uint64)
+        check(lib().aqc_build_hamiltonian(
+            ctx.handle, self.n, len(w), x.ctypes.data_as(u64p), z.ctypes.data_as(u64p),
+            w.ctypes.data_as(C.POINTER(C.c_double)), sid.ctypes.data_as(C.POINTER(C.c_int32)),
+            ns, sch, C.byref(path), C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        i = L.HamInfo()
+        check(lib().aqc_ham_info(self._h, C.byref(i)))
+        return {"n_qubits": i.n_qubits, "n_terms": i.n_terms, "n_diag_terms": i.n_diag_terms,
+                "n_groups": i.n_groups, "n_passes": list(i.n_passes),
+                "tile_bits": list(i.tile_bits)}
+
+    def spectral_bounds(self, t0, t1):
+        lo, hi = C.c_double(), C.c_double()
+        check(lib().aqc_spectral_bounds(self.ctx.handle, self._h, t0, t1, C.byref(lo), C.byref(hi)))
+        return lo.value, hi.value
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().aqc_ham_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _check_state(ctx, ham_n, psi):
+    if psi.device != ctx.device:
+        raise ValueError("state is not on the context's device")
+    if not psi.is_contiguous():
+        raise ValueError("state must be contiguous")
+    if psi.numel() != (1 << ham_n):
+        raise ValueError(f"state has {psi.numel()} amplitudes, expected 2^{ham_n}")
+    return dtype_code(psi)
+
+
+def workspace(ctx, nbytes):
+    if nbytes == 0:
+        return None
+    return torch.empty(nbytes, dtype=torch.uint8, device=ctx.device)
+
+
+def apply(ctx: Context, ham: Hamiltonian, t: float, psi: torch.Tensor, out=None, ws=None):
+    """out = H(t) psi."""
+    dt = _check_state(ctx, ham.n, psi)
+    if out is None:
+        out = torch.empty_like(psi)
+    need = lib().aqc_apply_workspace_bytes(ham.handle, dt)
+    if need and ws is None:
+        ws = workspace(ctx, need)
+    check(lib().aqc_apply(ctx.handle, ham.handle, float(t), _ptr(psi), _ptr(out), dt,
+                          _ptr(ws) if ws is not None else None, ws.numel() if ws is not None else 0))
+    return out
+
+
+def evolve_opts(method="pc4", n_steps=1000, shift=0.0, check_every=0, norm_tol=1e-3,
+                stab_limit=0.0, atol=1e-9, h0=0.0, hmin=0.0, hmax=0.0, window=8, replay=None,
+                record_cap=0, compensated=True):
+    o = L.EvolveOpts()
+    o.method = {"pc4": L.METHOD_PC4, "rk4": L.METHOD_RK4}[method]
+    o.n_steps = int(n_steps)
+    if isinstance(shift, str):
+        if shift != "center":
+            raise ValueError(shift)
+        o.shift_mode = L.SHIFT_CENTER
+    else:
+        o.shift_mode = L.SHIFT_VALUE
+        o.shift = float(shift)
+    o.check_every = int(check_every)
+    o.norm_tol = float(norm_tol)
+    o.stab_limit = float(stab_limit)
+    o.atol, o.h0, o.hmin, o.hmax = float(atol), float(h0), float(hmin), float(hmax)
+    o.window = int(window)
+    o.compensated = 1 if compensated else 0
+    keep = []
+    if replay is not None:
+        arr = np.ascontiguousarray(np.asarray(replay, dtype=np.float64).reshape(-1, 3))
+        keep.append(arr)
+        o.n_replay = arr.shape[0]
+        o.replay = arr.ctypes.data_as(C.POINTER(C.c_double))
+    rec = None
+    if record_cap:
+        rec = np.zeros((record_cap, 3), dtype=np.float64)
+        keep.append(rec)
+        o.record = rec.ctypes.data_as(C.POINTER(C.c_double))
+        o.record_cap = record_cap
+    return o, keep, rec
+
+
+def evolve_workspace_bytes(ham, dtype, opts):
+    return lib().aqc_evolve_workspace_bytes(ham.handle, dtype, C.byref(opts))
+
+
+def evolve(ctx: Context, ham: Hamiltonian, psi: torch.Tensor, t0: float, t1: float, ws=None,
+           **kw):
+    """Evolve psi in place from t0 to t1.  Returns (stats dict, recorded segments)."""
+    dt = _check_state(ctx, ham.n, psi)
+    opts, keep, rec = evolve_opts(**kw)
+    need = evolve_workspace_bytes(ham, dt, opts)
+    if ws is None or ws.numel() < need:
+        ws = workspace(ctx, need)
+    st = L.EvolveStats()
+    status = lib().aqc_evolve(ctx.handle, ham.handle, _ptr(psi), dt, float(t0), float(t1),
+                              C.byref(opts), _ptr(ws), ws.numel(), C.byref(st))
+    check(status)
+    segs = None
+    if rec is not None:
+        segs = [tuple(r) for r in rec[:min(st.n_segments, rec.shape[0])]]
+    return st.as_dict(), segs
+
+
+def norm2(ctx, psi):
+    out = C.c_double()
+    check(lib().aqc_norm2(ctx.handle, _ptr(psi), dtype_code(psi), int(math.log2(psi.numel())),
+                          C.byref(out)))
+    return out.value
+
+
+def overlap(ctx, phi, psi):
+    re, im = C.c_double(), C.c_double()
+    check(lib().aqc_overlap(ctx.handle, _ptr(phi), _ptr(psi), dtype_code(psi),
+                            int(math.log2(psi.numel())), C.byref(re), C.byref(im)))
+    return complex(re.value, im.value)
+
+
+def fidelity_state(ctx, psi, phi):
+    out = C.c_double()
+    check(lib().aqc_fidelity(ctx.handle, _ptr(psi), dtype_code(psi), int(math.log2(psi.numel())),
+                             L.TARGET_STATE, _ptr(phi), 0, C.byref(out)))
+    return out.value
+
+
+def fidelity_basis(ctx, psi, indices):
+    idx = np.ascontiguousarray(np.asarray(indices, dtype=np.int64))
+    out = C.c_double()
+    check(lib().aqc_fidelity(ctx.handle, _ptr(psi), dtype_code(psi), int(math.log2(psi.numel())),
+                             L.TARGET_BASIS_LIST, idx.ctypes.data_as(C.c_void_p), len(idx),
+                             C.byref(out)))
+    return out.value
+
+
+def ground_mass(ctx, ham, t, psi, rel_tol=1e-9):
+    mass, emin = C.c_double(), C.c_double()
+    check(lib().aqc_ground_mass(ctx.handle, ham.handle, float(t), _ptr(psi), dtype_code(psi),
+                                float(rel_tol), C.byref(mass), C.byref(emin)))
+    return mass.value, emin.value
+
+
+def energy(ctx, ham, t, psi, ws=None):
+    dt = dtype_code(psi)
+    need = lib().aqc_apply_workspace_bytes(ham.handle, dt)
+    if need and ws is None:
+        ws = workspace(ctx, need)
+    out = C.c_double()
+    check(lib().aqc_energy(ctx.handle, ham.handle, float(t), _ptr(psi), dt,
+                           _ptr(ws) if ws is not None else None, ws.numel() if ws is not None else 0,
+                           C.byref(out)))
+    return out.value
+
+
+def profile_enable(ctx, on=True):
+    check(lib().aqc_profile_enable(ctx.handle, 1 if on else 0))
+
+
+def profile_reset(ctx):
+    check(lib().aqc_profile_reset(ctx.handle))
+
+
+def profile_read(ctx):
+    """{"high_pass": (ms, launches, bytes), "last_pass": (...)} since the last reset."""
+    out = {}
+    for name, kind in (("high_pass", L.PROF_HIGH_PASS), ("last_pass", L.PROF_LAST_PASS)):
+        ms, n, b = C.c_double(), C.c_int64(), C.c_double()
+        check(lib().aqc_profile_read(ctx.handle, kind, C.byref(ms), C.byref(n), C.byref(b)))
+        out[name] = (ms.value, n.value, b.value)
+    return out

@@ -1,0 +1,144 @@
+"""GPU parity of H(t)|psi> (aqc_apply through the C ABI) against the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import sqh, observables
+from paper_1311_3938_amd import instances as I
+from tests._gpu import to_dev, to_host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+# float32 products: a sum of ~n terms of relative error 2^-24 each
+APPLY_TOL = {"c64": 5e-6, "c128": 1e-12}
+
+
+@pytest.fixture(scope="module")
+def eng():
+    from paper_1311_3938_amd import engine
+    ctx = engine.Context(0)
+    yield engine, ctx
+    ctx.close()
+
+
+def _cases():
+    rng = np.random.default_rng(1234)
+    out = []
+    out.append(("sk_diag_only", I.sk_terms(9, *I.sk_couplings(9, rng)).instance(
+        [I.SCHED_S], I.sin2_path(2.0))))
+    tx, tz = I.tfim_terms(11)
+    t = I.TermList(11)
+    t.extend(tx, sid=0)
+    t.extend(tz, sid=1)
+    out.append(("tfim", t.instance([I.SCHED_ONE_MINUS_S, I.SCHED_S], I.linear_path(3.0))))
+    out.append(("random_mixed", I.random_terms(10, 60, rng, n_sched=3).instance(
+        [I.SCHED_ONE_MINUS_S, I.trig_t(0.9, 1.7, 0.1), I.poly_s([0.2, 1.0, -1.3])],
+        I.linear_path(2.0))))
+    cl = I.ec3_random_clauses(10, 8, rng)
+    out.append(("xy_path", I.interpolated(10, I.xy_initial_terms(10, cl), I.ec3_terms(10, cl),
+                                          I.linear_path(5.0))))
+    out.append(("ec3_catalyst_16", I.workload_ec3_catalyst(n=16, m=13, n_pairs=16, T=5.0, seed=7)))
+    out.append(("sk_sin2_18", I.workload_sk_sin2(n=18, T=5.0, seed=8)))
+    out.append(("random_high_17", I.random_terms(17, 50, rng, max_weight_ops=3, n_sched=2).instance(
+        [I.SCHED_S, I.trig_t(1.0, 0.5)], I.linear_path(2.0))))
+    out.append(("one_qubit", _one_qubit()))
+    out.append(("two_qubit", I.random_terms(2, 12, rng, n_sched=1).instance(
+        [I.SCHED_CONST], I.linear_path(1.0))))
+    return out
+
+
+def _one_qubit():
+    t = I.TermList(1)
+    t.add({1: "Z"}, 0.7, 0)
+    t.add({1: "X"}, 1.0, 1)
+    t.add({1: "Y"}, 1.0, 2)
+    t.add({}, 0.25, 0)
+    return t.instance([I.SCHED_CONST, I.trig_t(0.4, 0.8), I.trig_t(0.4, 0.8, -math.pi / 2)],
+                      I.linear_path(1.0))
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("name,inst", CASES, ids=[c[0] for c in CASES])
+def test_apply_matches_oracle(eng, name, inst, dt):
+    engine, ctx = eng
+    ham = engine.Hamiltonian(ctx, inst)
+    rng = np.random.default_rng(5)
+    psi = I.random_state(inst.n, rng)
+    T = inst.path["T"]
+    for t in (0.31 * T, 0.77 * T):
+        want = sqh.apply_h(inst, t, psi)
+        got = to_host(engine.apply(ctx, ham, t, to_dev(psi, dt)))
+        assert rel_err(got, want) < APPLY_TOL[dt], (name, dt, t)
+    ham.free()
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_apply_with_small_tiles_many_passes(eng, dt, monkeypatch):
+    """Force tiny tiles so that flip patterns spread over many high passes."""
+    engine, ctx = eng
+    key = "C64" if dt == "c64" else "C128"
+    monkeypatch.setenv(f"AQC_TBF_{key}", "5")
+    monkeypatch.setenv(f"AQC_TBH_{key}", "6")
+    monkeypatch.setenv(f"AQC_LH_{key}", "2")
+    rng = np.random.default_rng(77)
+    inst = I.random_terms(12, 80, rng, max_weight_ops=3, n_sched=2).instance(
+        [I.SCHED_S, I.SCHED_ONE_MINUS_S], I.linear_path(1.0))
+    ham = engine.Hamiltonian(ctx, inst)
+    psi = I.random_state(12, rng)
+    want = sqh.apply_h(inst, 0.4, psi)
+    got = to_host(engine.apply(ctx, ham, 0.4, to_dev(psi, dt)))
+    assert ham.info()["n_passes"][0 if dt == "c64" else 1] > 3
+    assert rel_err(got, want) < APPLY_TOL[dt]
+    ham.free()
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_reductions_match_oracle(eng, dt):
+    engine, ctx = eng
+    rng = np.random.default_rng(11)
+    inst = I.workload_ec3_catalyst(n=15, m=12, n_pairs=15, T=4.0, seed=3)
+    ham = engine.Hamiltonian(ctx, inst)
+    psi = I.random_state(15, rng)
+    phi = I.random_state(15, rng)
+    dpsi, dphi = to_dev(psi, dt), to_dev(phi, dt)
+    psi_r = to_host(dpsi)     # the values the device holds (rounded for c64)
+    phi_r = to_host(dphi)
+    tol = 1e-12
+    assert engine.norm2(ctx, dpsi) == pytest.approx(observables.norm2(psi_r), abs=tol)
+    ov = engine.overlap(ctx, dphi, dpsi)
+    want = observables.overlap(phi_r, psi_r)
+    assert abs(ov - want) < tol
+    assert engine.fidelity_state(ctx, dpsi, dphi) == pytest.approx(abs(want) ** 2, abs=tol)
+    idx = [0, 5, 5, 77, (1 << 15) - 1]
+    assert engine.fidelity_basis(ctx, dpsi, idx) == pytest.approx(
+        observables.basis_mass(psi_r, idx), abs=tol)
+    for t in (4.0, 1.3):
+        m, emin = engine.ground_mass(ctx, ham, t, dpsi)
+        m_want, e_want = observables.ground_mass(inst, t, psi_r)
+        assert emin == pytest.approx(e_want, abs=1e-12)
+        assert m == pytest.approx(m_want, abs=tol)
+        e = engine.energy(ctx, ham, t, dpsi)
+        e_ref = observables.energy(inst, t, psi_r)
+        assert abs(e - e_ref) < (1e-11 if dt == "c128" else 1e-5 * max(1.0, abs(e_ref)))
+    ham.free()
+
+
+def test_errors_are_reported(eng):
+    engine, ctx = eng
+    from paper_1311_3938_amd import _lib
+    inst = I.workload_ec3_linear(n=6, m=4, T=2.0, seed=1)
+    ham = engine.Hamiltonian(ctx, inst)
+    import torch
+    psi = to_dev(I.plus_state(6), "c64")
+    with pytest.raises(_lib.AqcError) as ei:
+        engine.apply(ctx, ham, 0.0, psi, out=psi)
+    assert ei.value.status == _lib.AQC_EINVAL
+    bad = I.TermList(3)
+    bad.add_masks(1 << 5, 0, 1.0, 0)
+    with pytest.raises(_lib.AqcError):
+        engine.Hamiltonian(ctx, bad.instance([I.SCHED_CONST], I.linear_path(1.0)))
+    ham.free()

@@ -1,0 +1,101 @@
+"""Checks at the benchmark's full size (n = 30, 2^30 amplitudes, complex64, the
+three-pass plan the benchmark times): sampled outputs against the oracle's
+row-wise product, and closed forms that hold at any size."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import sqh
+from paper_1311_3938_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+N_FULL = 30
+
+
+@pytest.fixture(scope="module")
+def eng():
+    import torch
+    from paper_1311_3938_amd import engine
+    ctx = engine.Context(0)
+    yield engine, ctx, torch
+    ctx.close()
+    torch.cuda.empty_cache()
+
+
+def _rows(rng, n, k=300):
+    r = rng.integers(0, 1 << n, size=k, dtype=np.int64)
+    return np.unique(np.concatenate([r, [0, (1 << n) - 1, 1 << (n - 1), (1 << 13) - 1]]))
+
+
+def test_apply_sampled_rows_full_size(eng):
+    engine, ctx, torch = eng
+    inst = I.workload_sk_sin2(n=N_FULL, T=30.0, seed=I.seed_for(2))
+    ham = engine.Hamiltonian(ctx, inst)
+    g = torch.Generator(device="cuda").manual_seed(3)
+    psi = torch.randn(1 << N_FULL, dtype=torch.complex64, device="cuda", generator=g)
+    out = engine.apply(ctx, ham, 11.0, psi)
+    assert ham.info()["n_passes"][0] == 3
+    rows = _rows(np.random.default_rng(4), N_FULL)
+
+    def values_at(idx):
+        t = torch.from_numpy(np.ascontiguousarray(idx)).to("cuda")
+        return psi.index_select(0, t).cpu().to(torch.complex128).numpy()
+
+    want = sqh.apply_h_rows(inst, 11.0, values_at, rows)
+    got = out.index_select(0, torch.from_numpy(rows).to("cuda")).cpu().to(torch.complex128).numpy()
+    scale = np.abs(want).max()
+    assert np.max(np.abs(got - want)) / scale < 5e-6
+    del out, psi
+    ham.free()
+    torch.cuda.empty_cache()
+
+
+def test_transverse_field_only_full_size_closed_form(eng):
+    """H(t) = (1 - s) sum (1 - sx_q)/2 from |0...0>: each qubit turns by
+    exp(-i A sx) with A = -(1/2) int (1 - s) dt; identity terms give a phase."""
+    engine, ctx, torch = eng
+    n, T, t1, K = N_FULL, 30.0, 0.3, 60
+    inst = I.interpolated(n, I.transverse_terms(n), I.TermList(n), I.linear_path(T))
+    ham = engine.Hamiltonian(ctx, inst)
+    psi = torch.zeros(1 << n, dtype=torch.complex64, device="cuda")
+    psi[0] = 1.0
+    st, _ = engine.evolve(ctx, ham, psi, 0.0, t1, method="pc4", n_steps=K, shift=n / 2.0)
+    assert ham.info()["n_passes"][0] == 3
+    F = t1 - t1 * t1 / (2 * T)                    # int_0^t1 (1 - t/T) dt
+    A = -0.5 * F
+    ph = np.exp(-1j * (n / 2.0) * F)
+    rows = _rows(np.random.default_rng(5), n)
+    pop = np.array([bin(int(r)).count("1") for r in rows])
+    exact = ph * np.cos(A) ** (n - pop) * (-1j * np.sin(A)) ** pop
+    got = psi.index_select(0, torch.from_numpy(rows).to("cuda")).cpu().to(torch.complex128).numpy()
+    # float32 rounding plus the method's truncation error, t1 C h^4 lam^5 with
+    # |lam| <= n/2 after the shift (about 4e-6 of the largest amplitude)
+    assert np.max(np.abs(got - exact)) / np.max(np.abs(exact)) < 2e-5
+    assert abs(st["norm2_final"] - 1.0) < 1e-5
+    del psi
+    ham.free()
+    torch.cuda.empty_cache()
+
+
+def test_sk_diagonal_full_size_exact_phases(eng):
+    """Diagonal-only H(t) = s(t) H_SK: psi_T(z) = exp(-i E(z) int s dt) psi_0(z)."""
+    engine, ctx, torch = eng
+    n, T, t1, K = N_FULL, 30.0, 3.0, 60
+    J, h = I.sk_couplings(n, np.random.default_rng(I.seed_for(2)))
+    inst = I.sk_terms(n, J, h).instance([I.SCHED_S], I.sin2_path(T))
+    ham = engine.Hamiltonian(ctx, inst)
+    N = 1 << n
+    psi = torch.full((N,), 1.0 / math.sqrt(N), dtype=torch.complex64, device="cuda")
+    engine.evolve(ctx, ham, psi, 0.0, t1, method="pc4", n_steps=K, shift="center")
+    # int_0^t1 sin^2(pi t / 2T) dt = t1/2 - (T/(2 pi)) sin(pi t1 / T)
+    S = t1 / 2 - T / (2 * math.pi) * math.sin(math.pi * t1 / T)
+    rows = _rows(np.random.default_rng(6), n)
+    E = sqh.diagonal_rows(I.sk_terms(n, J, h).instance([I.SCHED_CONST], I.sin2_path(T)), 0.0, rows)
+    exact = np.exp(-1j * E * S) / math.sqrt(N)
+    got = psi.index_select(0, torch.from_numpy(rows).to("cuda")).cpu().to(torch.complex128).numpy()
+    assert np.max(np.abs(got - exact)) * math.sqrt(N) < 2e-5
+    del psi
+    ham.free()
+    torch.cuda.empty_cache()

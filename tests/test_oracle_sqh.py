@@ -99,3 +99,17 @@ def test_schedules_closed_forms():
     assert sqh.schedule_value(w, 2.0, p) == 0.0      # s = 0.5: outside, open high end
     wc = I.poly_s([1.0], 0.25, 0.5, hi_closed=True)
     assert sqh.schedule_value(wc, 2.0, p) == 1.0
+
+
+def test_row_wise_product_matches_full_product():
+    rng = np.random.default_rng(9)
+    n = 6
+    inst = I.random_terms(n, 30, rng, n_sched=2).instance(
+        [I.SCHED_S, I.trig_t(1.0, 0.7)], I.linear_path(2.0))
+    psi = I.random_state(n, rng)
+    full = sqh.apply_h(inst, 0.8, psi, shift=0.3)
+    rows = rng.choice(1 << n, 20, replace=False)
+    got = sqh.apply_h_rows(inst, 0.8, lambda idx: psi[idx], rows, shift=0.3)
+    np.testing.assert_allclose(got, full[rows], atol=1e-13)
+    np.testing.assert_allclose(sqh.diagonal_rows(inst, 0.8, rows), sqh.diagonal(inst, 0.8)[rows],
+                               atol=1e-13)
