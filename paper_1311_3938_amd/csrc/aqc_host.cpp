@@ -218,6 +218,9 @@ struct HTerm {
 };
 
 struct Pass {
+  int kind = 0;              // 0: LDS tile pass, 1: register hypercube pass
+  int hb = 0;                // kind 1: hypercube bits [hb, hb + RB)
+  int bit_group[8] = {-1, -1, -1, -1, -1, -1, -1, -1};  // kind 1: group per bit
   int tb = 0, lbits = 0;
   uint64_t hmask = 0, cmask = 0;
   bool final_pass = false;
@@ -545,6 +548,38 @@ static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& 
       rest.push_back((int)gi);
     }
   }
+  // single-qubit flips with real coefficients above the last pass's tile go to
+  // register hypercube passes over contiguous ranges of RB bits
+  std::vector<Pass> regp;
+  const int rb = dtype == 0 ? kRegBitsC64 : kRegBitsC128;
+  if (env_int("AQC_REGPASS", 1) && n - 6 - rb >= 2) {
+    std::map<int, int> single;  // bit -> group
+    std::vector<int> keep;
+    for (int gi : rest) {
+      const GroupH& g = h->groups[gi];
+      const int b = __builtin_ctzll(g.x);
+      if (popc(g.x) == 1 && g.plain && b >= 6) single[b] = gi;
+      else keep.push_back(gi);
+    }
+    while (!single.empty()) {
+      const int b0 = single.begin()->first;
+      const int hb = std::max(6, std::min(b0, n - rb));
+      Pass ps;
+      ps.kind = 1;
+      ps.hb = hb;
+      for (int b = 0; b < rb; ++b) {
+        auto it = single.find(hb + b);
+        if (it != single.end()) {
+          ps.bit_group[b] = it->second;
+          ps.groups.push_back(it->second);
+          single.erase(it);
+        }
+      }
+      ps.tb = rb;
+      regp.push_back(ps);
+    }
+    rest.swap(keep);
+  }
   std::sort(rest.begin(), rest.end(), [&](int a, int b) {
     const uint64_t xa = h->groups[a].x, xb = h->groups[b].x;
     const int ha = 63 - __builtin_clzll(xa), hb = 63 - __builtin_clzll(xb);
@@ -589,6 +624,7 @@ static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& 
     ps.cmask = full & ~(lowh | ps.hmask);
   }
   out.clear();
+  for (Pass& ps : regp) out.push_back(ps);
   for (Pass& ps : high) out.push_back(ps);
   out.push_back(last);
   *tbf_out = tbf;
@@ -604,7 +640,8 @@ static aqc_status build_plan(aqc_ham* h, int dtype, hipStream_t s) {
   STCHK(layout_passes(h, dtype, passes, &tbf));
   p.tbf = tbf;
   p.passes = passes;
-  for (Pass& ps : p.passes) STCHK(build_pass_tables(ps, h, s));
+  for (Pass& ps : p.passes)
+    if (ps.kind == 0) STCHK(build_pass_tables(ps, h, s));
   STCHK(build_diag_tables(p, h, s));
   p.built = true;
   return AQC_OK;
@@ -654,6 +691,37 @@ static aqc_status run_matvec(aqc_ctx* ctx, const aqc_ham* h, int dtype, double t
   if (np > 1 && !hbuf) return fail(AQC_ENOMEM, "workspace for the partial product missing");
   for (int k = 0; k < np; ++k) {
     const Pass& ps = p.passes[k];
+    if (ps.kind == 1) {
+      RegPassArgs ra;
+      std::memset(&ra, 0, sizeof(ra));
+      ra.n = h->n;
+      ra.hb = ps.hb;
+      ra.src = u;
+      ra.acc_in = k > 0 ? hbuf : nullptr;
+      ra.acc_out = hbuf;
+      for (int b = 0; b < 8; ++b) {
+        double cb = 0.0;
+        if (ps.bit_group[b] >= 0)
+          for (const HTerm& t : h->groups[ps.bit_group[b]].terms) cb += t.w * c.f[t.sid];
+        ra.cb[b] = cb;
+      }
+      if (ctx->prof_on) {
+        aqc_ctx::Rec r;
+        r.kind = AQC_PROF_HIGH_PASS;
+        STCHK(prof_event(ctx, &r.a));
+        STCHK(prof_event(ctx, &r.b));
+        HIPCHK(hipEventRecord(r.a, ctx->stream));
+        HIPCHK(launch_regpass(ra, dtype, ctx->stream));
+        HIPCHK(hipEventRecord(r.b, ctx->stream));
+        ctx->prof_pending.push_back(r);
+        ctx->prof_bytes[r.kind] += (double)(2 + (ra.acc_in ? 1 : 0)) * (double)((size_t)1 << h->n) *
+                                   (dtype == 0 ? 8.0 : 16.0);
+        if (ctx->prof_pending.size() >= 4096) STCHK(prof_drain(ctx));
+      } else {
+        HIPCHK(launch_regpass(ra, dtype, ctx->stream));
+      }
+      continue;
+    }
     PassArgs a;
     fill_common(a, h, p, ps, c, shift);
     a.src = u;
@@ -680,6 +748,7 @@ static aqc_status run_matvec(aqc_ctx* ctx, const aqc_ham* h, int dtype, double t
       if (ps.final_pass) {
         for (int i = 0; i < 4; ++i) nvec += a.epi.in[i] ? 1 : 0;
         for (int i = 0; i < 3; ++i) nvec += a.epi.out[i] ? 1 : 0;
+        if (a.epi.comp) nvec += (a.epi.comp_flags & 8) ? 2 : 1;  // y_lo read (and written)
       }
       ctx->prof_bytes[r.kind] += (double)nvec * (double)((size_t)1 << h->n) * (dtype == 0 ? 8.0 : 16.0);
       if (ctx->prof_pending.size() >= 4096) STCHK(prof_drain(ctx));

@@ -98,7 +98,22 @@ struct PassArgs {
   EpiDesc epi;
 };
 
+// Register hypercube pass: single-qubit flips (real coefficients) on the bits
+// [hb, hb + RB), with RB = kRegBitsC64 / kRegBitsC128.  A wave owns 64
+// contiguous amplitudes (one per lane) at each vertex of the hypercube.
+constexpr int kRegBitsC64 = 6;
+constexpr int kRegBitsC128 = 5;
+struct RegPassArgs {
+  int32_t n;
+  int32_t hb;
+  const void* src;
+  const void* acc_in;
+  void* acc_out;
+  double cb[8];       // coefficient of the flip of bit hb + b
+};
+
 // ---- launchers (aqc_kernels.hip) -------------------------------------------
+hipError_t launch_regpass(const RegPassArgs& a, int dtype, hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, int dtype, int64_t nblocks, hipStream_t s);
 size_t pass_lds_bytes(int tb, int dtype);
 hipError_t prepare_kernels();

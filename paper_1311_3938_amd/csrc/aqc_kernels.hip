@@ -17,6 +17,8 @@
 
 namespace aqc {
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 template <typename R> struct CT2;
 template <> struct CT2<float> { using V = float2; };
 template <> struct CT2<double> { using V = double2; };
@@ -79,7 +81,8 @@ struct Lds {
   static constexpr int kLA = kRed + 8 * 3 * (kThreads / 64);     // R LA[128]
   static constexpr int kLB = kLA + 8 * 128;                      // R LB[128]
   static constexpr int kGco = kLB + 8 * 128;                     // R gco[kMaxPassGroups]
-  static constexpr int kTm = kGco + 8 * kMaxPassGroups;          // R tm[kMaxPassTerms]
+  static constexpr int kGxl = kGco + 8 * kMaxPassGroups;         // u32 gxl[kMaxPassGroups]
+  static constexpr int kTm = kGxl + 4 * kMaxPassGroups;          // R tm[kMaxPassTerms]
   static constexpr int kTile = kTm + 8 * kMaxPassTerms;          // V tile[2^tb]
 };
 
@@ -158,6 +161,28 @@ __device__ __forceinline__ R diag_value(const PassArgs& a, uint32_t lo, uint64_t
   return d;
 }
 
+// Load CPT 16-byte chunks per thread of a tile into LDS: chunk q = tid +
+// kThreads*j holds local elements q*VEC ...; all loads are issued before the
+// first LDS write so their latencies overlap.
+template <int CPT, bool FINAL, typename V>
+__device__ __forceinline__ void load_tile(const V* src, V* tile, uint64_t base, uint64_t dep_tid,
+                                          uint64_t tmask, int logv) {
+  constexpr int VEC = 16 / (int)sizeof(V);
+  uint64_t g[CPT];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    const uint64_t jpart = (uint64_t)(kThreads * j) << logv;
+    g[j] = base | dep_tid | (FINAL ? jpart : pdep64(jpart, tmask));
+  }
+  u32x4 v[CPT];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j)
+    v[j] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src + g[j]));
+#pragma unroll
+  for (int j = 0; j < CPT; ++j)
+    *reinterpret_cast<u32x4*>(tile + (threadIdx.x + kThreads * j) * VEC) = v[j];
+}
+
 template <typename R, bool FINAL>
 __global__ __launch_bounds__(kThreads) void k_pass(const PassArgs a) {
   using V = typename CT2<R>::V;
@@ -169,6 +194,7 @@ __global__ __launch_bounds__(kThreads) void k_pass(const PassArgs a) {
   R* LA = reinterpret_cast<R*>(smem + Lds::kLA);
   R* LB = reinterpret_cast<R*>(smem + Lds::kLB);
   R* gco = reinterpret_cast<R*>(smem + Lds::kGco);
+  uint32_t* gxl = reinterpret_cast<uint32_t*>(smem + Lds::kGxl);
   R* tm = reinterpret_cast<R*>(smem + Lds::kTm);
   V* tile = reinterpret_cast<V*>(smem + Lds::kTile);
 
@@ -181,23 +207,26 @@ __global__ __launch_bounds__(kThreads) void k_pass(const PassArgs a) {
   const uint64_t tmask = lowmask | a.hmask;
   const uint64_t base = FINAL ? ((uint64_t)bid << tb) : pdep64((uint64_t)bid, a.cmask);
 
-  // ---- 1. issue the tile loads (16 bytes per chunk) ----------------------
+  // ---- 1. the tile: every 16-byte chunk is loaded before any LDS write ------
   constexpr int VEC = 16 / (int)sizeof(V);            // elements per chunk
   constexpr int LOGV = VEC == 2 ? 1 : 0;
-  constexpr int kMaxChunks = 16;                       // per thread (tile <= 128 KiB)
   const uint32_t nchunks = ntile / VEC;
   const V* src = reinterpret_cast<const V*>(a.src);
   // local element l = q*VEC with q = tid + kThreads*j: the tid part and the j
   // part occupy disjoint bits of l, so their deposits can be OR-ed.
   const uint64_t dep_tid = FINAL ? ((uint64_t)tid << LOGV) : pdep64((uint64_t)tid << LOGV, tmask);
-#pragma unroll
-  for (int j = 0; j < kMaxChunks; ++j) {
-    const uint32_t q = tid + kThreads * j;
-    if (q < nchunks) {
-      const uint64_t jpart = (uint64_t)(kThreads * j) << LOGV;
-      const uint64_t g = base | dep_tid | (FINAL ? jpart : pdep64(jpart, tmask));
-      *reinterpret_cast<uint4*>(tile + q * VEC) = *reinterpret_cast<const uint4*>(src + g);
-    }
+  switch (nchunks / kThreads) {
+    case 16: load_tile<16, FINAL, V>(src, tile, base, dep_tid, tmask, LOGV); break;
+    case 8: load_tile<8, FINAL, V>(src, tile, base, dep_tid, tmask, LOGV); break;
+    case 4: load_tile<4, FINAL, V>(src, tile, base, dep_tid, tmask, LOGV); break;
+    case 2: load_tile<2, FINAL, V>(src, tile, base, dep_tid, tmask, LOGV); break;
+    case 1: load_tile<1, FINAL, V>(src, tile, base, dep_tid, tmask, LOGV); break;
+    default:
+      // tiles smaller than one chunk per thread
+      if ((uint32_t)tid < nchunks)
+        *reinterpret_cast<uint4*>(tile + tid * VEC) =
+            *reinterpret_cast<const uint4*>(src + (base | dep_tid));
+      break;
   }
 
   // ---- 2. per-workgroup coefficients --------------------------------------
@@ -214,6 +243,8 @@ __global__ __launch_bounds__(kThreads) void k_pass(const PassArgs a) {
       }
     }
     gco[g] = (R)c;
+    // tile-local flip mask; bit 31 marks a group whose coefficient depends on g
+    gxl[g] = gr.xl | (gr.plain ? 0u : 0x80000000u);
   }
   for (int t = tid; t < a.nterms; t += kThreads) {
     const DevTerm tt = a.terms[t];
@@ -245,53 +276,61 @@ __global__ __launch_bounds__(kThreads) void k_pass(const PassArgs a) {
   double r0 = 0.0, r1 = 0.0, r2 = 0.0;
   const uint32_t E = ntile >= (uint32_t)kThreads ? ntile / kThreads : 1u;
   const uint64_t edep_tid = FINAL ? (uint64_t)tid : pdep64((uint64_t)tid, tmask);
+  // Elements are processed in blocks of EB: H u for the whole block is kept in
+  // registers while the flip groups are walked once (group-outer order), then
+  // the stage update streams the block's other vectors in batches of U.
+  constexpr int EB = FINAL ? 4 : 8;
   constexpr int U = sizeof(R) == 4 ? 4 : 2;
-  for (uint32_t j0 = 0; j0 < E; j0 += U) {
-    V ain[U], xin[U][4], lo[U];
-    uint64_t gidx[U];
-    uint32_t lidx[U];
-    bool ok[U];
+  for (uint32_t jb = 0; jb < E; jb += EB) {
+    R hr[EB], hi[EB];
+    V uv[EB];
+    uint64_t gidx[EB];
+    bool ok[EB];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t j = j0 + u;
+    for (int u = 0; u < EB; ++u) {
+      const uint32_t j = jb + u;
       const uint32_t l = tid + kThreads * j;
       ok[u] = (j < E) && (l < ntile);
-      lidx[u] = l;
       const uint64_t jpart = (uint64_t)kThreads * j;
       gidx[u] = base | edep_tid | (FINAL ? jpart : pdep64(jpart, tmask));
-      ain[u] = V{0, 0};
-      if (ok[u] && accin) ain[u] = accin[gidx[u]];
-      if (FINAL) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          xin[u][i] = V{0, 0};
-          if (ok[u] && e.in[i]) xin[u][i] = reinterpret_cast<const V*>(e.in[i])[gidx[u]];
-        }
-        lo[u] = V{0, 0};
-        if (ok[u] && has_comp) lo[u] = compv[gidx[u]];
+      uv[u] = ok[u] ? tile[l] : V{0, 0};
+      hr[u] = 0;
+      hi[u] = 0;
+      if (!FINAL && ok[u] && accin) {
+        const V av = accin[gidx[u]];
+        hr[u] = av.x;
+        hi[u] = av.y;
       }
     }
+    if (FINAL) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (!ok[u]) continue;
-      const uint32_t l = lidx[u];
-      const uint64_t g = gidx[u];
-      const V uv = tile[l];
-      R hr = ain[u].x, hi = ain[u].y;
-      if (FINAL) {
-        const R d = diag_value<R>(a, l, g, cprime, LA, LB, fsh);
-        hr += d * uv.x;
-        hi += d * uv.y;
+      for (int u = 0; u < EB; ++u) {
+        if (!ok[u]) continue;
+        const uint32_t l = tid + kThreads * (jb + u);
+        const R d = diag_value<R>(a, l, gidx[u], cprime, LA, LB, fsh);
+        hr[u] = d * uv[u].x;
+        hi[u] = d * uv[u].y;
       }
-      for (int k = 0; k < a.ng; ++k) {
+    }
+    for (int k = 0; k < a.ng; ++k) {
+      const uint32_t gx = gxl[k];
+      if (!(gx >> 31)) {
+        const R c = gco[k];
+#pragma unroll
+        for (int u = 0; u < EB; ++u) {
+          if (!ok[u]) continue;
+          const uint32_t l = tid + kThreads * (jb + u);
+          const V v = tile[l ^ gx];
+          hr[u] += c * v.x;
+          hi[u] += c * v.y;
+        }
+      } else {
         const DevGroup gr = a.groups[k];
-        const V v = tile[l ^ gr.xl];
-        if (gr.plain) {
-          const R c = gco[k];
-          hr += c * v.x;
-          hi += c * v.y;
-        } else {
-          const uint64_t src_idx = g ^ gr.x;
+#pragma unroll
+        for (int u = 0; u < EB; ++u) {
+          if (!ok[u]) continue;
+          const uint32_t l = tid + kThreads * (jb + u);
+          const uint64_t src_idx = gidx[u] ^ gr.x;
           R cr = 0, ci = 0;
           for (int t = 0; t < gr.nt; ++t) {
             const DevTerm tt = a.terms[gr.t0 + t];
@@ -304,54 +343,138 @@ __global__ __launch_bounds__(kThreads) void k_pass(const PassArgs a) {
               default: ci -= m; break;
             }
           }
-          hr += cr * v.x - ci * v.y;
-          hi += cr * v.y + ci * v.x;
+          const V v = tile[l ^ gr.xl];
+          hr[u] += cr * v.x - ci * v.y;
+          hi[u] += cr * v.y + ci * v.x;
         }
       }
-      if (!FINAL) {
-        accout[g] = V{hr, hi};
-        continue;
+    }
+    if (!FINAL) {
+#pragma unroll
+      for (int u = 0; u < EB; ++u)
+        if (ok[u]) accout[gidx[u]] = V{hr[u], hi[u]};
+      continue;
+    }
+#pragma unroll
+    for (int u0 = 0; u0 < EB; u0 += U) {
+      V ain[U], xin[U][4], lo[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = u0 + u;
+        ain[u] = V{0, 0};
+        lo[u] = V{0, 0};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) xin[u][i] = V{0, 0};
+        if (!ok[q]) continue;
+        if (accin) ain[u] = accin[gidx[q]];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (e.in[i]) xin[u][i] = reinterpret_cast<const V*>(e.in[i])[gidx[q]];
+        if (has_comp) lo[u] = compv[gidx[q]];
       }
 #pragma unroll
-      for (int o = 0; o < 3; ++o) {
-        if (!e.out[o]) continue;
-        // increment: scale * (sum a x + b Hv), scale as a float-float pair
-        R ir = br[o] * hr - bi[o] * hi;
-        R ii = br[o] * hi + bi[o] * hr;
+      for (int u = 0; u < U; ++u) {
+        const int q = u0 + u;
+        if (!ok[q]) continue;
+        const uint64_t g = gidx[q];
+        const R hrr = hr[q] + ain[u].x, hii = hi[q] + ain[u].y;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          ir += ca[o][i] * xin[u][i + 1].x;
-          ii += ca[o][i] * xin[u][i + 1].y;
-        }
-        R vr = sh[o] * ir + sl[o] * ir;
-        R vi = sh[o] * ii + sl[o] * ii;
-        if (e.comp_flags & (1 << o)) {
-          vr += lo[u].x;
-          vi += lo[u].y;
-        }
-        const R bre = c0[o] * xin[u][0].x + cu[o] * uv.x;
-        const R bim = c0[o] * xin[u][0].y + cu[o] * uv.y;
-        R sr = bre + vr, si = bim + vi;
-        if (o == 0 && (e.comp_flags & 8)) {
-          // two-sum: the rounding error of bre + vr goes to the low part
-          const R tr = sr - bre, ti = si - bim;
-          const R er = (bre - (sr - tr)) + (vr - tr);
-          const R ei = (bim - (si - ti)) + (vi - ti);
-          compv[g] = V{er, ei};
-        }
-        reinterpret_cast<V*>(e.out[o])[g] = V{sr, si};
-        if (o == 0) {
-          if (e.red_flags & 1) r0 += (double)sr * (double)sr + (double)si * (double)si;
-          if (e.red_flags & 2) {
-            const double dr = (double)sr - (double)uv.x, di = (double)si - (double)uv.y;
-            r1 += dr * dr + di * di;
+        for (int o = 0; o < 3; ++o) {
+          if (!e.out[o]) continue;
+          // increment: scale * (sum a x + b Hv), scale as a float-float pair
+          R ir = br[o] * hrr - bi[o] * hii;
+          R ii = br[o] * hii + bi[o] * hrr;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) {
+            ir += ca[o][i] * xin[u][i + 1].x;
+            ii += ca[o][i] * xin[u][i + 1].y;
+          }
+          R vr = sh[o] * ir + sl[o] * ir;
+          R vi = sh[o] * ii + sl[o] * ii;
+          if (e.comp_flags & (1 << o)) {
+            vr += lo[u].x;
+            vi += lo[u].y;
+          }
+          const R bre = c0[o] * xin[u][0].x + cu[o] * uv[q].x;
+          const R bim = c0[o] * xin[u][0].y + cu[o] * uv[q].y;
+          const R sr = bre + vr, si = bim + vi;
+          if (o == 0 && (e.comp_flags & 8)) {
+            // two-sum: the rounding error of bre + vr goes to the low part
+            const R tr = sr - bre, ti = si - bim;
+            const R er = (bre - (sr - tr)) + (vr - tr);
+            const R ei = (bim - (si - ti)) + (vi - ti);
+            compv[g] = V{er, ei};
+          }
+          reinterpret_cast<V*>(e.out[o])[g] = V{sr, si};
+          if (o == 0) {
+            if (e.red_flags & 1) r0 += (double)sr * (double)sr + (double)si * (double)si;
+            if (e.red_flags & 2) {
+              const double dr = (double)sr - (double)uv[q].x, di = (double)si - (double)uv[q].y;
+              r1 += dr * dr + di * di;
+            }
           }
         }
+        if (e.red_flags & 4) r2 += (double)uv[q].x * (double)hrr + (double)uv[q].y * (double)hii;
       }
-      if (e.red_flags & 4) r2 += (double)uv.x * (double)hr + (double)uv.y * (double)hi;
     }
   }
   if (FINAL && e.red_flags) block_reduce3<kThreads>(r0, r1, r2, e.red_flags, rbuf, e.red, nblocks, bid);
+}
+
+// High-qubit flips without LDS: lane = bits 0..5 (64 contiguous amplitudes per
+// load instruction), registers = the 2^RB vertices of the hypercube over bits
+// [hb, hb + RB), waves = all remaining bits.  A flip of bit hb + b pairs
+// vertex v with v ^ 2^b inside the same lane's registers.
+template <typename R, int RB>
+__global__ __launch_bounds__(256) void k_regpass(const RegPassArgs a) {
+  using V = typename CT2<R>::V;
+  constexpr int NV = 1 << RB;
+  const int lane = threadIdx.x & 63;
+  // the wave index is uniform: keep the row bases in scalar registers and add
+  // only the lane offset per thread
+  const uint64_t wave =
+      (uint64_t)blockIdx.x * 4 + (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int hb = a.hb;
+  if (wave >= (1ull << (a.n - 6 - RB))) return;
+  const int lowcnt = hb - 6;
+  const uint64_t ubase = ((wave & ((1ull << lowcnt) - 1ull)) << 6) | ((wave >> lowcnt) << (hb + RB));
+  const V* src = reinterpret_cast<const V*>(a.src);
+  const V* accin = reinterpret_cast<const V*>(a.acc_in);
+  V* accout = reinterpret_cast<V*>(a.acc_out);
+  V x[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) x[v] = (src + (ubase + ((uint64_t)v << hb)))[lane];
+  R c[RB];
+#pragma unroll
+  for (int b = 0; b < RB; ++b) c[b] = (R)a.cb[b];
+  constexpr int VB = 8;
+#pragma unroll
+  for (int v0 = 0; v0 < NV; v0 += VB) {
+    V ain[VB];
+#pragma unroll
+    for (int u = 0; u < VB; ++u)
+      ain[u] = accin ? (accin + (ubase + ((uint64_t)(v0 + u) << hb)))[lane] : V{0, 0};
+#pragma unroll
+    for (int u = 0; u < VB; ++u) {
+      const int v = v0 + u;
+      R hr = 0, hi = 0;
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        hr += c[b] * x[v ^ (1 << b)].x;
+        hi += c[b] * x[v ^ (1 << b)].y;
+      }
+      (accout + (ubase + ((uint64_t)v << hb)))[lane] = V{hr + ain[u].x, hi + ain[u].y};
+    }
+  }
+}
+
+hipError_t launch_regpass(const RegPassArgs& a, int dtype, hipStream_t s) {
+  const int rb = dtype == 0 ? kRegBitsC64 : kRegBitsC128;
+  const int64_t nwaves = (int64_t)1 << (a.n - 6 - rb);
+  const unsigned blocks = (unsigned)((nwaves + 3) / 4);
+  if (dtype == 0) hipLaunchKernelGGL((k_regpass<float, kRegBitsC64>), dim3(blocks), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_regpass<double, kRegBitsC128>), dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 template <typename R, bool FINAL>

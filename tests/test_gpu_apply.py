@@ -142,3 +142,30 @@ def test_errors_are_reported(eng):
     with pytest.raises(_lib.AqcError):
         engine.Hamiltonian(ctx, bad.instance([I.SCHED_CONST], I.linear_path(1.0)))
     ham.free()
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("regpass", ["1", "0"])
+def test_apply_register_hypercube_pass(eng, dt, regpass, monkeypatch):
+    """20 qubits: single-qubit flips above the last tile run in register
+    hypercube passes (or, switched off, in tile passes); pairs and Y/Z mixes
+    that straddle the tile stay in tile passes."""
+    engine, ctx = eng
+    monkeypatch.setenv("AQC_REGPASS", regpass)
+    rng = np.random.default_rng(2020)
+    n = 20
+    t = I.TermList(n)
+    for q in range(1, n + 1):
+        t.add({q: "X"}, rng.normal(), 0)
+        t.add({q: "Z"}, rng.normal(), 1)
+    for _ in range(12):
+        i, j = sorted(int(v) + 1 for v in rng.choice(n, 2, replace=False))
+        t.add({i: "X", j: "X"}, rng.normal(), 2)
+        t.add({i: "Y", j: "Z"}, rng.normal(), 0)
+    inst = t.instance([I.SCHED_ONE_MINUS_S, I.SCHED_S, I.SCHED_S_ONE_MINUS_S], I.linear_path(1.0))
+    ham = engine.Hamiltonian(ctx, inst)
+    psi = I.random_state(n, rng)
+    want = sqh.apply_h(inst, 0.37, psi)
+    got = to_host(engine.apply(ctx, ham, 0.37, to_dev(psi, dt)))
+    assert rel_err(got, want) < APPLY_TOL[dt]
+    ham.free()
