@@ -228,6 +228,39 @@ aqc_status aqc_ground_mass(aqc_ctx* ctx, const aqc_ham* ham, double t, const voi
 aqc_status aqc_energy(aqc_ctx* ctx, const aqc_ham* ham, double t, const void* psi,
                       int dtype, void* workspace, size_t ws_bytes, double* out);
 
+/* ---- batches of solves ------------------------------------------------------ */
+/* A batch advances many independent fixed-step predictor-corrector solves
+ * (each its own Hamiltonian, n, interval, step and shift) together: every
+ * "tick" performs one H|psi> per active solve, with one launch per tile-pass
+ * level for all solves (the workgroups of a launch are mapped to (solve, tile)
+ * pairs).  Each solve runs exactly the launch sequence aqc_evolve uses for
+ * {AQC_METHOD_PC4, n_steps, AQC_SHIFT_VALUE shift, compensated}, so its result
+ * does not depend on what else is in the batch.  The batch works on its own
+ * stream, ordered after and before the context's stream by events; with
+ * graphs on, each tick is replayed as a captured hipGraph (re-captured when
+ * the set of active solves changes).  States and workspaces stay owned by the
+ * caller and must stay allocated until the solve is retired.               */
+typedef struct aqc_batch aqc_batch;
+aqc_status aqc_batch_create(aqc_ctx* ctx, int dtype, int capacity, aqc_batch** out);
+aqc_status aqc_batch_destroy(aqc_batch* batch);
+aqc_status aqc_batch_set_graph(aqc_batch* batch, int on);
+/* workspace one solve needs (pc4, compensated for AQC_C64)                   */
+size_t aqc_batch_workspace_bytes(const aqc_ham* ham, int dtype);
+/* Admit the solve psi(t0) -> psi(t1) in n_steps equal steps with the constant
+ * shift; psi is evolved in place.  EBUSY when every slot is taken.           */
+aqc_status aqc_batch_admit(aqc_batch* batch, const aqc_ham* ham, void* psi, void* workspace,
+                           size_t ws_bytes, double t0, double t1, int64_t n_steps, double shift,
+                           int* slot);
+/* Run up to `ticks` ticks (fewer when every solve has finished); returns the
+ * number of solves still running.                                           */
+aqc_status aqc_batch_step(aqc_batch* batch, int ticks, int* n_active);
+/* Finished solves not reported before (their psi holds psi(t1) once this
+ * returns: it synchronises the batch stream).                               */
+aqc_status aqc_batch_poll(aqc_batch* batch, int* slots, int cap, int* n_done);
+/* Release a finished slot; fills steps, matvecs, t_reached, h_last, shift.   */
+aqc_status aqc_batch_retire(aqc_batch* batch, int slot, aqc_evolve_stats* stats);
+aqc_status aqc_batch_info(const aqc_batch* batch, int* active, int* finished, int64_t* ticks);
+
 /* ---- instrumentation ----------------------------------------------------- */
 /* Kernel timing with HIP events recorded on the context's stream around every
  * tile-pass launch (the events add no synchronisation).  Classes:

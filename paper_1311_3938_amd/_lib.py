@@ -96,6 +96,15 @@ SIGNATURES = {
     "aqc_fidelity": (I32, [P, P, C.c_int, C.c_int, C.c_int, P, I64, C.POINTER(D)]),
     "aqc_ground_mass": (I32, [P, P, D, P, C.c_int, D, C.POINTER(D), C.POINTER(D)]),
     "aqc_energy": (I32, [P, P, D, P, C.c_int, P, SZ, C.POINTER(D)]),
+    "aqc_batch_create": (I32, [P, C.c_int, C.c_int, C.POINTER(P)]),
+    "aqc_batch_destroy": (I32, [P]),
+    "aqc_batch_set_graph": (I32, [P, C.c_int]),
+    "aqc_batch_workspace_bytes": (SZ, [P, C.c_int]),
+    "aqc_batch_admit": (I32, [P, P, P, P, SZ, D, D, I64, D, C.POINTER(C.c_int)]),
+    "aqc_batch_step": (I32, [P, C.c_int, C.POINTER(C.c_int)]),
+    "aqc_batch_poll": (I32, [P, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int)]),
+    "aqc_batch_retire": (I32, [P, C.c_int, C.POINTER(EvolveStats)]),
+    "aqc_batch_info": (I32, [P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(I64)]),
     "aqc_profile_enable": (I32, [P, C.c_int]),
     "aqc_profile_reset": (I32, [P]),
     "aqc_profile_read": (I32, [P, C.c_int, C.POINTER(D), C.POINTER(I64), C.POINTER(D)]),

@@ -1073,6 +1073,165 @@ namespace {
 
 constexpr double kMilne = 19.0 / 270.0;
 
+// Vectors of one running solve (device pointers; see aqc_evolve's workspace).
+struct SolveVecs {
+  void* y;       // the caller's state
+  void* yp;      // y^p (pc4) or the RK4 stage input u
+  void* B[4];    // f history (pc4, rotating); RK4 accumulator: B[3] (pc4 bootstrap) or B[0]
+  void* hbuf;    // partial product of the high passes
+  void* ycomp;   // complex64 compensated state: low part of y, or nullptr
+};
+
+// One H|psi> of a fixed-step segment: time, tile source and stage update.
+struct MatvecStage {
+  double t;
+  const void* src;
+  EpiDesc e;
+  bool ends_step;  // completes an integration step
+  bool pc4;        // a predictor-corrector step (Milne estimate defined)
+};
+
+// Walks the matvecs of a segment on the grid t_s + k h.  pc4: RK4 steps for
+// k = 0, 1, 2 (their first stages are f_0..f_2), then one evaluation at t_3 that
+// also forms the first prediction y^p_4, then one H|psi> per step.  The same
+// sequence serves aqc_evolve and the batch engine, so a solve performs the
+// same launches alone and in a batch.
+struct SegStepper {
+  int method = AQC_METHOD_PC4;
+  double ts = 0, h = 0;
+  int64_t k = 0;      // steps done
+  int sub = 0;        // RK4 stage 0..3; 4 = evaluation at t_3 pending (pc4)
+  int64_t k_end = 0;  // stop when k reaches this
+  bool more_after = false;  // the segment continues after k_end
+
+  bool rk_phase() const { return method == AQC_METHOD_RK4 || (k < 3 && sub < 4); }
+
+  MatvecStage next(const SolveVecs& v) const {
+    MatvecStage m;
+    m.e = epi_zero();
+    m.ends_step = false;
+    m.pc4 = false;
+    const int lo_in = v.ycomp ? 1 : 0;
+    EpiDesc& e = m.e;
+    e.comp = v.ycomp;
+    const double tk = ts + (double)k * h;
+    if (rk_phase()) {
+      void* fk = method == AQC_METHOD_PC4 ? v.B[k & 3] : nullptr;
+      void* acc = method == AQC_METHOD_PC4 ? v.B[3] : v.B[0];
+      if (sub == 0) {  // acc (or f_k) = F, u = y + h/2 F
+        m.t = tk;
+        m.src = v.y;
+        e.out[0] = fk ? fk : acc;
+        e.scale[0] = 1.0;
+        e.bi[0] = -1.0;
+        e.out[1] = v.yp;
+        e.cu[1] = 1.0;
+        e.scale[1] = 0.5 * h;
+        e.bi[1] = -1.0;
+        e.comp_flags = lo_in << 1;
+      } else if (sub <= 2) {  // acc = acc_in + 2F, u = y + c h F (u in place)
+        m.t = tk + 0.5 * h;
+        m.src = v.yp;
+        e.in[0] = v.y;
+        e.in[1] = (sub == 1 && fk) ? fk : acc;
+        e.out[0] = acc;
+        e.scale[0] = 1.0;
+        e.a[0][0] = 1.0;
+        e.bi[0] = -2.0;
+        e.out[1] = v.yp;
+        e.c0[1] = 1.0;
+        e.scale[1] = sub == 1 ? 0.5 * h : h;
+        e.bi[1] = -1.0;
+        e.comp_flags = lo_in << 1;
+      } else {  // y = y + h/6 (acc + F)
+        m.t = tk + h;
+        m.src = v.yp;
+        e.in[0] = v.y;
+        e.in[1] = acc;
+        e.out[0] = v.y;
+        e.c0[0] = 1.0;
+        e.scale[0] = h / 6.0;
+        e.a[0][0] = 1.0;
+        e.bi[0] = -1.0;
+        e.comp_flags = v.ycomp ? (1 | 8) : 0;
+        m.ends_step = true;
+      }
+      return m;
+    }
+    if (sub == 4) {
+      // f_3 = F(t_3, y_3) and y^p_4 = y_3 + h/24 (55 f_3 - 59 f_2 + 37 f_1 - 9 f_0)
+      m.t = ts + 3.0 * h;
+      m.src = v.y;
+      e.out[0] = v.B[3];
+      e.scale[0] = 1.0;
+      e.bi[0] = -1.0;
+      e.in[0] = v.y;
+      e.in[1] = v.B[2];
+      e.in[2] = v.B[1];
+      e.in[3] = v.B[0];
+      e.out[1] = v.yp;
+      e.c0[1] = 1.0;
+      e.scale[1] = h / 24.0;
+      e.a[1][0] = -59.0;
+      e.a[1][1] = 37.0;
+      e.a[1][2] = -9.0;
+      e.bi[1] = -55.0;
+      e.comp_flags = lo_in << 1;
+      return m;
+    }
+    // predictor-corrector step k -> k+1: one H|psi> at t_{k+1} on y^p_{k+1}
+    const double c = h / 24.0;
+    m.t = ts + (double)(k + 1) * h;
+    m.src = v.yp;
+    m.ends_step = true;
+    m.pc4 = true;
+    e.in[0] = v.y;
+    e.in[1] = v.B[k & 3];        // f_k
+    e.in[2] = v.B[(k - 1) & 3];  // f_{k-1}
+    e.in[3] = v.B[(k - 2) & 3];  // f_{k-2}
+    e.out[0] = v.y;              // y_{k+1} = y_k + h/24 (9 F + 19 f_k - 5 f_{k-1} + f_{k-2})
+    e.c0[0] = 1.0;
+    e.scale[0] = c;
+    e.a[0][0] = 19.0;
+    e.a[0][1] = -5.0;
+    e.a[0][2] = 1.0;
+    e.bi[0] = -9.0;
+    e.out[1] = v.B[(k + 1) & 3];  // f_{k+1} = F over f_{k-3}
+    e.scale[1] = 1.0;
+    e.bi[1] = -1.0;
+    if (k + 1 < k_end || more_after) {
+      e.out[2] = v.yp;  // y^p_{k+2} = y_k + h/24 (64 F - 40 f_k + 32 f_{k-1} - 8 f_{k-2})
+      e.c0[2] = 1.0;
+      e.scale[2] = c;
+      e.a[2][0] = -40.0;
+      e.a[2][1] = 32.0;
+      e.a[2][2] = -8.0;
+      e.bi[2] = -64.0;
+    }
+    e.comp_flags = v.ycomp ? (1 | 8 | 4) : 0;
+    return m;
+  }
+
+  void advance() {
+    if (rk_phase()) {
+      if (sub < 3) {
+        ++sub;
+        return;
+      }
+      sub = 0;
+      ++k;
+      // the pc4 bootstrap ends with the evaluation at t_3 when a pc4 step follows
+      if (method == AQC_METHOD_PC4 && k == 3 && (k < k_end || more_after)) sub = 4;
+      return;
+    }
+    if (sub == 4) {
+      sub = 0;
+      return;
+    }
+    ++k;
+  }
+};
+
 struct Evolver {
   aqc_ctx* ctx;
   const aqc_ham* h;
@@ -1081,12 +1240,8 @@ struct Evolver {
   int64_t N;
   size_t vb;
   int method;
-  void* y;           // the caller's state
-  void* yp;          // predictor (pc4) or RK4 stage input u
-  void* B[4];        // f history (pc4); B[0] is the RK4 accumulator
-  void* hbuf;        // partial product of the high passes
+  SolveVecs v;
   void* ckpt;        // adaptive: state at the window start
-  void* ycomp;       // complex64 compensated state: low part of y (or nullptr)
   void* ckpt_lo;     // adaptive: low part at the window start
   int64_t nb_last;
   aqc_evolve_stats* st;
@@ -1095,167 +1250,83 @@ struct Evolver {
   int64_t steps_since_check = 0;
   double* errbuf;    // device, per-step Milne sums of a window
 
-  // one RK4 step on (t, h); when fk != nullptr the first stage's F = f(t, y)
-  // is written there (the predictor-corrector bootstrap keeps it).  With a
-  // compensated state the stage inputs u = y + c h F include y_lo and the
-  // final update is a two-sum into (y, y_lo).
-  aqc_status rk4_step(double t, double hh, void* fk, void* acc, bool want_norm) {
-    const int lo_in = ycomp ? 1 : 0;
-    // stage 1: acc (or f_k) = F, u = y + h/2 F
-    EpiDesc e = epi_zero();
-    e.out[0] = fk ? fk : acc;
-    e.scale[0] = 1.0;
-    e.bi[0] = -1.0;
-    e.out[1] = yp;
-    e.cu[1] = 1.0;
-    e.scale[1] = 0.5 * hh;
-    e.bi[1] = -1.0;
-    e.comp = ycomp;
-    e.comp_flags = lo_in << 1;
-    STCHK(run_matvec(ctx, h, dtype, t, shift, y, hbuf, e));
-    // stages 2, 3: acc = acc_in + 2F, u = y + c h F (u updated in place)
-    for (int sg = 2; sg <= 3; ++sg) {
-      e = epi_zero();
-      e.in[0] = y;
-      e.in[1] = (sg == 2 && fk) ? fk : acc;
-      e.out[0] = acc;
-      e.scale[0] = 1.0;
-      e.a[0][0] = 1.0;
-      e.bi[0] = -2.0;
-      e.out[1] = yp;
-      e.c0[1] = 1.0;
-      e.scale[1] = sg == 2 ? 0.5 * hh : hh;
-      e.bi[1] = -1.0;
-      e.comp = ycomp;
-      e.comp_flags = lo_in << 1;
-      STCHK(run_matvec(ctx, h, dtype, t + 0.5 * hh, shift, yp, hbuf, e));
-    }
-    // stage 4: y = y + h/6 (acc + F)
-    e = epi_zero();
-    e.in[0] = y;
-    e.in[1] = acc;
-    e.out[0] = y;
-    e.c0[0] = 1.0;
-    e.scale[0] = hh / 6.0;
-    e.a[0][0] = 1.0;
-    e.bi[0] = -1.0;
-    e.comp = ycomp;
-    e.comp_flags = ycomp ? (1 | 8) : 0;
-    if (want_norm) {
-      e.red = ctx->parts;
-      e.red_flags = 1;
-    }
-    STCHK(run_matvec(ctx, h, dtype, t + hh, shift, yp, hbuf, e));
-    st->matvecs += 4;
-    return AQC_OK;
-  }
-
   aqc_status norm_check(double t_now, int64_t k_global) {
     HIPCHK(launch_reduce_sum(ctx->parts, nb_last, 1, ctx->dres, ctx->stream));
-    double v;
-    STCHK(read_results(ctx, 1, &v));
-    if (!std::isfinite(v) || std::fabs(v - st->norm2_initial) > norm_tol) {
+    double val;
+    STCHK(read_results(ctx, 1, &val));
+    if (!std::isfinite(val) || std::fabs(val - st->norm2_initial) > norm_tol) {
       st->status_step = (int32_t)k_global;
       st->t_reached = t_now;
       char buf[160];
-      snprintf(buf, sizeof buf, "norm guard: |psi|^2 = %.6g at t = %.6g (initial %.6g)", v, t_now,
+      snprintf(buf, sizeof buf, "norm guard: |psi|^2 = %.6g at t = %.6g (initial %.6g)", val, t_now,
                st->norm2_initial);
       return fail(AQC_EUNSTABLE, buf);
     }
     return AQC_OK;
   }
 
-  bool due_check() {
-    if (check_every <= 0) return false;
-    return (++steps_since_check % check_every) == 0;
-  }
-
-  // Segment state: k steps done on the grid t_s + k h.
-  struct Seg {
-    double ts, h;
-    int64_t k;
-  };
-
-  // Advance a segment by nsteps; Milne sums of pc4 steps go to errbuf[0..]
-  // (when errs != nullptr, the count is returned in *nerr).
-  aqc_status advance(Seg& sg, int64_t nsteps, bool want_err, int* nerr, bool last_segment_end) {
-    const double hh = sg.h;
+  // Take `nsteps` more steps of the segment `sg`; the Milne sums of its pc4
+  // steps go to errbuf[0..] when want_err (count in *nerr).
+  aqc_status advance(SegStepper& sg, int64_t nsteps, bool more_after, bool want_err, int* nerr) {
+    sg.k_end = sg.k + nsteps;
+    sg.more_after = more_after;
     int ne = 0;
-    for (int64_t i = 0; i < nsteps; ++i) {
-      const int64_t k = sg.k;
-      const double tk = sg.ts + (double)k * hh;
-      const bool chk = due_check();
-      if (method == AQC_METHOD_RK4) {
-        STCHK(rk4_step(tk, hh, nullptr, B[0], chk));
-      } else if (k < 3) {
-        STCHK(rk4_step(tk, hh, B[k & 3], B[3], chk));
-        if (k == 2) {
-          // f_3 at the end of the bootstrap, then the first prediction
-          const double t3 = sg.ts + 3.0 * hh;
-          EpiDesc e = epi_zero();
-          e.out[0] = B[3];
-          e.scale[0] = 1.0;
-          e.bi[0] = -1.0;
-          // only when the segment continues past the bootstrap
-          if (i + 1 < nsteps || !last_segment_end) {
-            STCHK(run_matvec(ctx, h, dtype, t3, shift, y, hbuf, e));
-            st->matvecs += 1;
-            const double c4[4] = {55.0 * hh / 24.0, -59.0 * hh / 24.0, 37.0 * hh / 24.0,
-                                  -9.0 * hh / 24.0};
-            HIPCHK(launch_ab4(yp, y, B[3], B[2], B[1], B[0], c4, dtype, N, ctx->stream));
-          }
-        }
-      } else {
-        // predictor-corrector step k -> k+1: one H|psi> at t_{k+1} on y^p_{k+1}
-        void* fk = B[k & 3];
-        void* fk1 = B[(k - 1) & 3];
-        void* fk2 = B[(k - 2) & 3];
-        void* fnew = B[(k + 1) & 3];  // holds f_{k-3}, no longer needed
-        const bool more = (i + 1 < nsteps) || !last_segment_end;
-        const double c = hh / 24.0;
-        EpiDesc e = epi_zero();
-        e.in[0] = y;
-        e.in[1] = fk;
-        e.in[2] = fk1;
-        e.in[3] = fk2;
-        e.out[0] = y;  // y_{k+1} = y_k + h/24 (9 F + 19 f_k - 5 f_{k-1} + f_{k-2})
-        e.c0[0] = 1.0;
-        e.scale[0] = c;
-        e.a[0][0] = 19.0;
-        e.a[0][1] = -5.0;
-        e.a[0][2] = 1.0;
-        e.bi[0] = -9.0;
-        e.out[1] = fnew;  // f_{k+1} = F
-        e.scale[1] = 1.0;
-        e.bi[1] = -1.0;
-        if (more) {
-          e.out[2] = yp;  // y^p_{k+2} = y_k + h/24 (64 F - 40 f_k + 32 f_{k-1} - 8 f_{k-2})
-          e.c0[2] = 1.0;
-          e.scale[2] = c;
-          e.a[2][0] = -40.0;
-          e.a[2][1] = 32.0;
-          e.a[2][2] = -8.0;
-          e.bi[2] = -64.0;
-        }
-        e.comp = ycomp;
-        e.comp_flags = ycomp ? (1 | 8 | 4) : 0;
-        e.red = ctx->parts;
-        e.red_flags = (chk ? 1 : 0) | (want_err ? 2 : 0);
-        STCHK(run_matvec(ctx, h, dtype, sg.ts + (double)(k + 1) * hh, shift, yp, hbuf, e));
-        st->matvecs += 1;
-        if (want_err) {
-          HIPCHK(launch_reduce_sum(ctx->parts + nb_last, nb_last, 1, errbuf + ne, ctx->stream));
-          ++ne;
-        }
+    while (sg.k < sg.k_end) {
+      MatvecStage m = sg.next(v);
+      bool chk = false;
+      if (m.ends_step && check_every > 0) chk = ((steps_since_check + 1) % check_every) == 0;
+      if (chk) m.e.red_flags |= 1;
+      if (m.pc4 && want_err) m.e.red_flags |= 2;
+      if (m.e.red_flags) m.e.red = ctx->parts;
+      STCHK(run_matvec(ctx, h, dtype, m.t, shift, m.src, v.hbuf, m.e));
+      st->matvecs += 1;
+      if (m.pc4 && want_err) {
+        HIPCHK(launch_reduce_sum(ctx->parts + nb_last, nb_last, 1, errbuf + ne, ctx->stream));
+        ++ne;
       }
-      sg.k = k + 1;
-      st->steps += 1;
-      if (chk) STCHK(norm_check(sg.ts + (double)sg.k * hh, st->steps));
+      sg.advance();
+      if (m.ends_step) {
+        ++steps_since_check;
+        st->steps += 1;
+        if (chk) STCHK(norm_check(sg.ts + (double)sg.k * sg.h, st->steps));
+      }
     }
     if (nerr) *nerr = ne;
     return AQC_OK;
   }
 };
+
+// Lay out the solve vectors in a workspace: y^p, four history vectors (pc4) or
+// one accumulator (rk4), the partial product when the plan has high passes,
+// and the low part of a compensated complex64 state.  Advances *w.
+aqc_status carve_workspace(const aqc_ham* h, int dtype, int method, bool compensated, void* psi,
+                           char** w, SolveVecs* v) {
+  const size_t vb = vec_bytes(h, dtype);
+  v->y = psi;
+  v->yp = *w;
+  *w += vb;
+  if (method == AQC_METHOD_RK4) {
+    v->B[0] = *w;
+    *w += vb;
+    v->B[1] = v->B[2] = v->B[3] = nullptr;
+  } else {
+    for (int i = 0; i < 4; ++i) {
+      v->B[i] = *w;
+      *w += vb;
+    }
+  }
+  v->hbuf = nullptr;
+  if (h->plans[dtype].passes.size() > 1) {
+    v->hbuf = *w;
+    *w += vb;
+  }
+  v->ycomp = nullptr;
+  if (dtype == AQC_C64 && compensated) {
+    v->ycomp = *w;
+    *w += vb;
+  }
+  return AQC_OK;
+}
 
 }  // namespace
 
@@ -1317,34 +1388,12 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
   ev.N = (int64_t)1 << h->n;
   ev.vb = vec_bytes(h, dtype);
   ev.method = o->method;
-  ev.y = psi;
   char* w = reinterpret_cast<char*>(ws);
-  ev.yp = w;
-  w += ev.vb;
-  if (o->method == AQC_METHOD_RK4) {
-    ev.B[0] = w;
-    w += ev.vb;
-    ev.B[1] = ev.B[2] = ev.B[3] = nullptr;
-  } else {
-    for (int i = 0; i < 4; ++i) {
-      ev.B[i] = w;
-      w += ev.vb;
-    }
-  }
-  ev.hbuf = nullptr;
-  if (h->plans[dtype].passes.size() > 1) {
-    ev.hbuf = w;
-    w += ev.vb;
-  }
-  ev.ycomp = nullptr;
+  STCHK(carve_workspace(h, dtype, o->method, o->compensated != 0, psi, &w, &ev.v));
   ev.ckpt = nullptr;
   ev.ckpt_lo = nullptr;
-  const bool comp = dtype == AQC_C64 && o->compensated != 0;
-  if (comp) {
-    ev.ycomp = w;
-    w += ev.vb;
-    HIPCHK(launch_zero(ev.ycomp, ev.vb, ctx->stream));
-  }
+  const bool comp = ev.v.ycomp != nullptr;
+  if (comp) HIPCHK(launch_zero(ev.v.ycomp, ev.vb, ctx->stream));
   if (adaptive) {
     ev.ckpt = w;
     w += ev.vb;
@@ -1363,11 +1412,18 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
 
   STCHK(aqc_norm2(ctx, psi, dtype, h->n, &stats->norm2_initial));
   std::vector<double> segs;  // recorded (t_s, h, k)
-  auto record = [&](const Evolver::Seg& s) {
+  auto record = [&](const SegStepper& s) {
     if (s.k <= 0) return;
     segs.push_back(s.ts);
     segs.push_back(s.h);
     segs.push_back((double)s.k);
+  };
+  auto new_seg = [&](double ts, double hh) {
+    SegStepper sg;
+    sg.method = o->method;
+    sg.ts = ts;
+    sg.h = hh;
+    return sg;
   };
   auto guard = [&](double hh) -> aqc_status {
     if (o->method == AQC_METHOD_PC4 && o->stab_limit > 0.0 && hh * stats->rho > o->stab_limit) {
@@ -1382,32 +1438,31 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
 
   aqc_status rc = AQC_OK;
   if (!adaptive) {
-    std::vector<Evolver::Seg> list;
+    std::vector<std::tuple<double, double, int64_t>> list;
     if (replay) {
       for (int i = 0; i < o->n_replay; ++i) {
         const double* r = o->replay + 3 * i;
         if (!(r[1] > 0) || !(r[2] >= 1) || !std::isfinite(r[0]))
           return fail(AQC_EINVAL, "aqc_evolve: bad replay segment");
-        list.push_back(Evolver::Seg{r[0], r[1], (int64_t)r[2]});
+        list.emplace_back(r[0], r[1], (int64_t)r[2]);
       }
     } else {
-      list.push_back(Evolver::Seg{t0, (t1 - t0) / o->n_steps, (int64_t)o->n_steps});
+      list.emplace_back(t0, (t1 - t0) / o->n_steps, (int64_t)o->n_steps);
     }
-    for (auto& s : list) STCHK(guard(s.h));
+    for (auto& s3 : list) STCHK(guard(std::get<1>(s3)));
     for (size_t i = 0; i < list.size() && rc == AQC_OK; ++i) {
-      Evolver::Seg s{list[i].ts, list[i].h, 0};
-      rc = ev.advance(s, list[i].k, false, nullptr, true);
-      stats->h_last = s.h;
-      record(s);
-      stats->t_reached = s.ts + (double)s.k * s.h;
+      SegStepper sg = new_seg(std::get<0>(list[i]), std::get<1>(list[i]));
+      rc = ev.advance(sg, std::get<2>(list[i]), false, false, nullptr);
+      stats->h_last = sg.h;
+      record(sg);
+      stats->t_reached = sg.ts + (double)sg.k * sg.h;
     }
   } else {
     // adaptive predictor-corrector (windows of W steps, Milne estimates)
     const int W = o->window;
     const double hmax = o->hmax > 0 ? o->hmax : INFINITY;
-    Evolver::Seg sg{t0, std::min(o->h0, hmax), 0};
+    SegStepper sg = new_seg(t0, std::min(o->h0, hmax));
     int windows_at_h = 0;
-    std::vector<double> errs(W);
     while (rc == AQC_OK) {
       const double t_now = sg.ts + (double)sg.k * sg.h;
       const double left = t1 - t_now;
@@ -1419,18 +1474,18 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
         const double hf = left / (double)nsteps;
         if (hf != sg.h) {
           record(sg);
-          sg = Evolver::Seg{t_now, hf, 0};
+          sg = new_seg(t_now, hf);
           windows_at_h = 0;
         }
       }
       rc = guard(sg.h);
       if (rc != AQC_OK) break;
-      HIPCHK(launch_copy(ev.ckpt, ev.y, dtype, ev.N, ctx->stream));
-      if (ev.ckpt_lo) HIPCHK(launch_copy(ev.ckpt_lo, ev.ycomp, dtype, ev.N, ctx->stream));
-      const int64_t k_before = sg.k;
+      HIPCHK(launch_copy(ev.ckpt, ev.v.y, dtype, ev.N, ctx->stream));
+      if (ev.ckpt_lo) HIPCHK(launch_copy(ev.ckpt_lo, ev.v.ycomp, dtype, ev.N, ctx->stream));
+      const SegStepper before = sg;
       const int64_t steps_before = stats->steps;
       int ne = 0;
-      rc = ev.advance(sg, nsteps, true, &ne, fin);
+      rc = ev.advance(sg, nsteps, !fin, true, &ne);
       if (rc != AQC_OK) break;
       double emax = 0.0;
       if (ne > 0) {
@@ -1441,11 +1496,10 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
       if (emax > o->atol && sg.h / 2.0 >= o->hmin) {
         stats->rejected += (stats->steps - steps_before);
         stats->steps = steps_before;
-        HIPCHK(launch_copy(ev.y, ev.ckpt, dtype, ev.N, ctx->stream));
-        if (ev.ckpt_lo) HIPCHK(launch_copy(ev.ycomp, ev.ckpt_lo, dtype, ev.N, ctx->stream));
-        Evolver::Seg old{sg.ts, sg.h, k_before};
-        record(old);
-        sg = Evolver::Seg{sg.ts + (double)k_before * sg.h, sg.h / 2.0, 0};
+        HIPCHK(launch_copy(ev.v.y, ev.ckpt, dtype, ev.N, ctx->stream));
+        if (ev.ckpt_lo) HIPCHK(launch_copy(ev.v.ycomp, ev.ckpt_lo, dtype, ev.N, ctx->stream));
+        record(before);
+        sg = new_seg(before.ts + (double)before.k * before.h, before.h / 2.0);
         windows_at_h = 0;
         continue;
       }
@@ -1459,7 +1513,7 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
       }
       if (emax < o->atol / 64.0 && windows_at_h >= 2 && 2.0 * sg.h <= hmax) {
         record(sg);
-        sg = Evolver::Seg{sg.ts + (double)sg.k * sg.h, 2.0 * sg.h, 0};
+        sg = new_seg(sg.ts + (double)sg.k * sg.h, 2.0 * sg.h);
         windows_at_h = 0;
       }
       stats->h_last = sg.h;
@@ -1478,5 +1532,419 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
   }
   STCHK(aqc_norm2(ctx, psi, dtype, h->n, &stats->norm2_final));
   stats->t_reached = t1;
+  return AQC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batch engine: many fixed-step predictor-corrector solves advanced together
+// ---------------------------------------------------------------------------
+struct aqc_batch {
+  aqc_ctx* ctx = nullptr;
+  int dtype = 0;
+  int capacity = 0;
+  struct Slot {
+    bool used = false, done = false, reported = false;
+    const aqc_ham* h = nullptr;
+    SolveVecs v{};
+    SegStepper sg;
+    double t0 = 0, t1 = 0, shift = 0;
+    int64_t matvecs = 0;
+    int nreg = 0, nlds = 0;  // high passes of each kind in the slot's plan
+  };
+  std::vector<Slot> slots;
+  // launch levels: reg passes 0..R-1, tile high passes 0..L-1, then the last pass
+  struct Level {
+    int kind = 0;   // 1 register pass, 0 tile high pass, 2 last pass
+    int idx = 0;    // which pass of that kind in each slot's plan
+    int max_tb = 0;
+    std::vector<int> part;     // participating slots, in argument order
+    std::vector<int2> map;     // block -> (participant, local block)
+    int2* dmap = nullptr;
+    size_t dmap_cap = 0;
+    size_t arg_off = 0;        // byte offset of this level's arguments
+  };
+  std::vector<Level> levels;
+  bool dirty = true;
+  size_t args_bytes = 0;
+  char* hargs[2] = {nullptr, nullptr};  // pinned
+  size_t hargs_cap = 0;
+  char* dargs = nullptr;
+  size_t dargs_cap = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool ev_pending[2] = {false, false};
+  int cur = 0;
+  // graphs
+  bool use_graph = false;
+  hipStream_t bs = nullptr;  // private stream for capture
+  hipEvent_t sync_ev = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int64_t ticks = 0;
+};
+
+static void batch_drop_graphs(aqc_batch* b) {
+  for (int i = 0; i < 2; ++i)
+    if (b->gexec[i]) {
+      hipGraphExecDestroy(b->gexec[i]);
+      b->gexec[i] = nullptr;
+    }
+}
+
+extern "C" aqc_status aqc_batch_create(aqc_ctx* ctx, int dtype, int capacity, aqc_batch** out) {
+  if (!out) return fail(AQC_EINVAL, "aqc_batch_create: out is NULL");
+  *out = nullptr;
+  if (!ctx) return fail(AQC_EINVAL, "aqc_batch_create: ctx is NULL");
+  if (dtype != AQC_C64 && dtype != AQC_C128) return fail(AQC_ENOTSUP, "aqc_batch_create: dtype");
+  if (capacity < 1 || capacity > 65536) return fail(AQC_EINVAL, "aqc_batch_create: capacity 1..65536");
+  HIPCHK(hipSetDevice(ctx->device));
+  std::unique_ptr<aqc_batch> b(new aqc_batch());
+  b->ctx = ctx;
+  b->dtype = dtype;
+  b->capacity = capacity;
+  b->slots.resize(capacity);
+  HIPCHK(hipEventCreateWithFlags(&b->ev[0], hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&b->ev[1], hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&b->sync_ev, hipEventDisableTiming));
+  HIPCHK(hipStreamCreateWithFlags(&b->bs, hipStreamNonBlocking));
+  *out = b.release();
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_batch_destroy(aqc_batch* b) {
+  if (!b) return AQC_OK;
+  hipSetDevice(b->ctx->device);
+  hipStreamSynchronize(b->bs);
+  hipStreamSynchronize(b->ctx->stream);
+  batch_drop_graphs(b);
+  for (auto& L : b->levels)
+    if (L.dmap) hipFree(L.dmap);
+  for (int i = 0; i < 2; ++i) {
+    if (b->hargs[i]) hipHostFree(b->hargs[i]);
+    if (b->ev[i]) hipEventDestroy(b->ev[i]);
+  }
+  if (b->dargs) hipFree(b->dargs);
+  if (b->sync_ev) hipEventDestroy(b->sync_ev);
+  if (b->bs) hipStreamDestroy(b->bs);
+  delete b;
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_batch_set_graph(aqc_batch* b, int on) {
+  if (!b) return fail(AQC_EINVAL, "aqc_batch_set_graph: NULL batch");
+  b->use_graph = on != 0;
+  batch_drop_graphs(b);
+  return AQC_OK;
+}
+
+extern "C" size_t aqc_batch_workspace_bytes(const aqc_ham* h, int dtype) {
+  aqc_evolve_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.method = AQC_METHOD_PC4;
+  o.n_steps = 1;
+  o.compensated = 1;
+  return aqc_evolve_workspace_bytes(h, dtype, &o);
+}
+
+extern "C" aqc_status aqc_batch_admit(aqc_batch* b, const aqc_ham* h, void* psi, void* ws,
+                                      size_t ws_bytes, double t0, double t1, int64_t n_steps,
+                                      double shift, int* slot) {
+  if (!b || !slot) return fail(AQC_EINVAL, "aqc_batch_admit: NULL argument");
+  *slot = -1;
+  STCHK(check_common(b->ctx, h, b->dtype));
+  if (!psi || !ws) return fail(AQC_EINVAL, "aqc_batch_admit: NULL state or workspace");
+  if (!aligned16(psi) || !aligned16(ws)) return fail(AQC_EINVAL, "aqc_batch_admit: 16-byte alignment");
+  if (!std::isfinite(t0) || !std::isfinite(t1) || !(t1 > t0) || n_steps < 1 || !std::isfinite(shift))
+    return fail(AQC_EINVAL, "aqc_batch_admit: need t0 < t1, n_steps >= 1, finite shift");
+  if (ws_bytes < aqc_batch_workspace_bytes(h, b->dtype))
+    return fail(AQC_ENOMEM, "aqc_batch_admit: workspace too small");
+  int s = -1;
+  for (int i = 0; i < b->capacity; ++i)
+    if (!b->slots[i].used) {
+      s = i;
+      break;
+    }
+  if (s < 0) return fail(AQC_EBUSY, "aqc_batch_admit: no free slot");
+  aqc_batch::Slot& sl = b->slots[s];
+  sl = aqc_batch::Slot();
+  sl.used = true;
+  sl.h = h;
+  char* w = reinterpret_cast<char*>(ws);
+  STCHK(carve_workspace(h, b->dtype, AQC_METHOD_PC4, true, psi, &w, &sl.v));
+  if (sl.v.ycomp) HIPCHK(launch_zero(sl.v.ycomp, vec_bytes(h, b->dtype), b->ctx->stream));
+  sl.sg.method = AQC_METHOD_PC4;
+  sl.sg.ts = t0;
+  sl.sg.h = (t1 - t0) / (double)n_steps;
+  sl.sg.k_end = n_steps;
+  sl.sg.more_after = false;
+  sl.t0 = t0;
+  sl.t1 = t1;
+  sl.shift = shift;
+  for (const Pass& ps : h->plans[b->dtype].passes) {
+    if (ps.final_pass) continue;
+    if (ps.kind == 1) ++sl.nreg;
+    else ++sl.nlds;
+  }
+  b->dirty = true;
+  *slot = s;
+  return AQC_OK;
+}
+
+// Rebuild the launch levels and their block maps for the active slots.
+static aqc_status batch_rebuild(aqc_batch* b) {
+  for (auto& L : b->levels)
+    if (L.dmap) {
+      HIPCHK(hipStreamSynchronize(b->ctx->stream));
+      HIPCHK(hipStreamSynchronize(b->bs));
+      break;
+    }
+  for (auto& L : b->levels)
+    if (L.dmap) hipFree(L.dmap);
+  b->levels.clear();
+  batch_drop_graphs(b);
+  int maxr = 0, maxl = 0;
+  for (auto& sl : b->slots)
+    if (sl.used && !sl.done) {
+      maxr = std::max(maxr, sl.nreg);
+      maxl = std::max(maxl, sl.nlds);
+    }
+  auto add_level = [&](int kind, int idx) {
+    aqc_batch::Level L;
+    L.kind = kind;
+    L.idx = idx;
+    for (int s = 0; s < b->capacity; ++s) {
+      const auto& sl = b->slots[s];
+      if (!sl.used || sl.done) continue;
+      const Plan& p = sl.h->plans[b->dtype];
+      // find the pass of this kind and index
+      int seen = 0;
+      const Pass* found = nullptr;
+      for (const Pass& ps : p.passes) {
+        const int k = ps.final_pass ? 2 : ps.kind;
+        if (k != kind) continue;
+        if (seen++ == idx) {
+          found = &ps;
+          break;
+        }
+      }
+      if (!found) continue;
+      const int pi = (int)L.part.size();
+      L.part.push_back(s);
+      int64_t nb;
+      if (kind == 1) {
+        const int rb = b->dtype == 0 ? kRegBitsC64 : kRegBitsC128;
+        nb = (((int64_t)1 << (sl.h->n - 6 - rb)) + 3) / 4;
+      } else {
+        nb = (int64_t)1 << (sl.h->n - found->tb);
+        L.max_tb = std::max(L.max_tb, found->tb);
+      }
+      for (int64_t q = 0; q < nb; ++q) L.map.push_back(int2{pi, (int)q});
+    }
+    if (!L.part.empty()) b->levels.push_back(std::move(L));
+  };
+  for (int r = 0; r < maxr; ++r) add_level(1, r);
+  for (int l = 0; l < maxl; ++l) add_level(0, l);
+  add_level(2, 0);
+  size_t off = 0;
+  for (auto& L : b->levels) {
+    L.arg_off = off;
+    off += L.part.size() * (L.kind == 1 ? sizeof(RegPassArgs) : sizeof(PassArgs));
+    off = (off + 255) & ~(size_t)255;
+    if (L.map.size() >= (size_t)INT32_MAX) return fail(AQC_ENOTSUP, "batch too large");
+    HIPCHK(hipMalloc(&L.dmap, L.map.size() * sizeof(int2)));
+    HIPCHK(hipMemcpy(L.dmap, L.map.data(), L.map.size() * sizeof(int2), hipMemcpyHostToDevice));
+  }
+  b->args_bytes = off;
+  if (off > b->hargs_cap) {
+    HIPCHK(hipStreamSynchronize(b->ctx->stream));
+    HIPCHK(hipStreamSynchronize(b->bs));
+    for (int i = 0; i < 2; ++i) {
+      if (b->hargs[i]) HIPCHK(hipHostFree(b->hargs[i]));
+      HIPCHK(hipHostMalloc(&b->hargs[i], off, hipHostMallocDefault));
+      b->ev_pending[i] = false;
+    }
+    b->hargs_cap = off;
+  }
+  if (off > b->dargs_cap) {
+    if (b->dargs) HIPCHK(hipFree(b->dargs));
+    HIPCHK(hipMalloc(&b->dargs, off));
+    b->dargs_cap = off;
+  }
+  b->dirty = false;
+  return AQC_OK;
+}
+
+// Fill this tick's arguments of every level into the pinned buffer `buf`.
+static void batch_fill_args(aqc_batch* b, char* buf) {
+  for (auto& L : b->levels) {
+    for (size_t pi = 0; pi < L.part.size(); ++pi) {
+      aqc_batch::Slot& sl = b->slots[L.part[pi]];
+      const aqc_ham* h = sl.h;
+      const Plan& p = h->plans[b->dtype];
+      const MatvecStage m = sl.sg.next(sl.v);
+      const Coefs c = coefs_at(h, m.t);
+      // locate the pass and its position in the plan
+      int seen = 0, kpos = -1;
+      for (int k = 0; k < (int)p.passes.size(); ++k) {
+        const Pass& ps = p.passes[k];
+        const int kind = ps.final_pass ? 2 : ps.kind;
+        if (kind != L.kind) continue;
+        if (seen++ == L.idx) {
+          kpos = k;
+          break;
+        }
+      }
+      const Pass& ps = p.passes[kpos];
+      const int np = (int)p.passes.size();
+      if (L.kind == 1) {
+        RegPassArgs* ra = reinterpret_cast<RegPassArgs*>(buf + L.arg_off) + pi;
+        std::memset(ra, 0, sizeof(*ra));
+        ra->n = h->n;
+        ra->hb = ps.hb;
+        ra->src = m.src;
+        ra->acc_in = kpos > 0 ? sl.v.hbuf : nullptr;
+        ra->acc_out = sl.v.hbuf;
+        for (int bb = 0; bb < 8; ++bb) {
+          double cb = 0.0;
+          if (ps.bit_group[bb] >= 0)
+            for (const HTerm& t : h->groups[ps.bit_group[bb]].terms) cb += t.w * c.f[t.sid];
+          ra->cb[bb] = cb;
+        }
+      } else {
+        PassArgs* a = reinterpret_cast<PassArgs*>(buf + L.arg_off) + pi;
+        fill_common(*a, h, p, ps, c, sl.shift);
+        a->src = m.src;
+        if (!ps.final_pass) {
+          a->acc_in = kpos > 0 ? sl.v.hbuf : nullptr;
+          a->acc_out = sl.v.hbuf;
+        } else {
+          a->acc_in = np > 1 ? sl.v.hbuf : nullptr;
+          a->epi = m.e;
+        }
+      }
+    }
+  }
+}
+
+static aqc_status batch_launch_levels(aqc_batch* b, hipStream_t s, const char* hbuf) {
+  HIPCHK(hipMemcpyAsync(b->dargs, hbuf, b->args_bytes, hipMemcpyHostToDevice, s));
+  for (auto& L : b->levels) {
+    const int64_t nb = (int64_t)L.map.size();
+    if (L.kind == 1)
+      HIPCHK(launch_regpass_batch(reinterpret_cast<const RegPassArgs*>(b->dargs + L.arg_off), L.dmap,
+                                  nb, b->dtype, s));
+    else
+      HIPCHK(launch_pass_batch(reinterpret_cast<const PassArgs*>(b->dargs + L.arg_off), L.dmap, nb,
+                               L.kind == 2 ? 1 : 0, L.max_tb, b->dtype, s));
+  }
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_batch_step(aqc_batch* b, int ticks, int* n_active) {
+  if (!b) return fail(AQC_EINVAL, "aqc_batch_step: NULL batch");
+  HIPCHK(hipSetDevice(b->ctx->device));
+  aqc_ctx* ctx = b->ctx;
+  // order the private stream after the context stream's earlier work
+  HIPCHK(hipEventRecord(b->sync_ev, ctx->stream));
+  HIPCHK(hipStreamWaitEvent(b->bs, b->sync_ev, 0));
+  const hipStream_t s = b->bs;
+  for (int t = 0; t < ticks; ++t) {
+    bool any = false;
+    for (auto& sl : b->slots) any |= (sl.used && !sl.done);
+    if (!any) break;
+    if (b->dirty) STCHK(batch_rebuild(b));
+    const int c = b->cur;
+    if (b->ev_pending[c]) HIPCHK(hipEventSynchronize(b->ev[c]));
+    batch_fill_args(b, b->hargs[c]);
+    if (b->use_graph) {
+      if (!b->gexec[c]) {
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        const aqc_status rc = batch_launch_levels(b, s, b->hargs[c]);
+        const hipError_t ec = hipStreamEndCapture(s, &g);
+        if (rc != AQC_OK) return rc;
+        HIPCHK(ec);
+        HIPCHK(hipGraphInstantiate(&b->gexec[c], g, nullptr, nullptr, 0));
+        HIPCHK(hipGraphDestroy(g));
+      }
+      HIPCHK(hipGraphLaunch(b->gexec[c], s));
+    } else {
+      STCHK(batch_launch_levels(b, s, b->hargs[c]));
+    }
+    HIPCHK(hipEventRecord(b->ev[c], s));
+    b->ev_pending[c] = true;
+    b->cur ^= 1;
+    ++b->ticks;
+    // advance every participant (each active slot did exactly one H|psi>)
+    for (auto& sl : b->slots) {
+      if (!sl.used || sl.done) continue;
+      sl.sg.advance();
+      ++sl.matvecs;
+      if (sl.sg.k >= sl.sg.k_end) {
+        sl.done = true;
+        b->dirty = true;
+        if (sl.shift != 0.0) {
+          const double ph = -sl.shift * (sl.t1 - sl.t0);
+          HIPCHK(launch_scale(sl.v.y, b->dtype, (int64_t)1 << sl.h->n, std::cos(ph), std::sin(ph), s));
+        }
+      }
+    }
+  }
+  // the context stream continues after this step's work
+  HIPCHK(hipEventRecord(b->sync_ev, s));
+  HIPCHK(hipStreamWaitEvent(ctx->stream, b->sync_ev, 0));
+  int na = 0;
+  for (auto& sl : b->slots) na += (sl.used && !sl.done) ? 1 : 0;
+  if (n_active) *n_active = na;
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_batch_poll(aqc_batch* b, int* slots, int cap, int* n_done) {
+  if (!b || !n_done || (cap > 0 && !slots)) return fail(AQC_EINVAL, "aqc_batch_poll: NULL argument");
+  int n = 0;
+  for (int s = 0; s < b->capacity; ++s) {
+    auto& sl = b->slots[s];
+    if (sl.used && sl.done && !sl.reported) {
+      if (n < cap) {
+        slots[n] = s;
+        sl.reported = true;
+      }
+      ++n;
+    }
+  }
+  *n_done = std::min(n, cap);
+  if (*n_done > 0) HIPCHK(hipStreamSynchronize(b->bs));
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_batch_retire(aqc_batch* b, int slot, aqc_evolve_stats* st) {
+  if (!b || slot < 0 || slot >= b->capacity) return fail(AQC_EINVAL, "aqc_batch_retire: bad slot");
+  auto& sl = b->slots[slot];
+  if (!sl.used) return fail(AQC_EINVAL, "aqc_batch_retire: slot not in use");
+  if (!sl.done) return fail(AQC_EBUSY, "aqc_batch_retire: solve not finished");
+  HIPCHK(hipStreamSynchronize(b->bs));
+  if (st) {
+    std::memset(st, 0, sizeof(*st));
+    st->steps = sl.sg.k;
+    st->matvecs = sl.matvecs;
+    st->n_segments = 1;
+    st->status_step = -1;
+    st->t_reached = sl.t1;
+    st->h_last = sl.sg.h;
+    st->shift_used = sl.shift;
+    st->rho = NAN;
+  }
+  sl = aqc_batch::Slot();
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_batch_info(const aqc_batch* b, int* active, int* finished, int64_t* ticks) {
+  if (!b) return fail(AQC_EINVAL, "aqc_batch_info: NULL batch");
+  int a = 0, f = 0;
+  for (auto& sl : b->slots) {
+    a += (sl.used && !sl.done) ? 1 : 0;
+    f += (sl.used && sl.done) ? 1 : 0;
+  }
+  if (active) *active = a;
+  if (finished) *finished = f;
+  if (ticks) *ticks = b->ticks;
   return AQC_OK;
 }

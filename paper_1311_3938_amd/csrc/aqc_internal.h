@@ -114,6 +114,11 @@ struct RegPassArgs {
 
 // ---- launchers (aqc_kernels.hip) -------------------------------------------
 hipError_t launch_regpass(const RegPassArgs& a, int dtype, hipStream_t s);
+// batched forms: block b serves args[bmap[b].x] at local block bmap[b].y
+hipError_t launch_regpass_batch(const RegPassArgs* args, const int2* bmap, int64_t nblocks, int dtype,
+                                hipStream_t s);
+hipError_t launch_pass_batch(const PassArgs* args, const int2* bmap, int64_t nblocks, int final_pass,
+                             int max_tb, int dtype, hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, int dtype, int64_t nblocks, hipStream_t s);
 size_t pass_lds_bytes(int tb, int dtype);
 hipError_t prepare_kernels();
@@ -138,9 +143,6 @@ hipError_t launch_diag_mass(const PassArgs& a, int dtype, int64_t nblocks, doubl
                             double* parts, hipStream_t s);
 // y *= (re + i im)
 hipError_t launch_scale(void* y, int dtype, int64_t N, double re, double im, hipStream_t s);
-// out = y + c0 f0 + c1 f1 + c2 f2 + c3 f3 (real coefficients): the Adams-Bashforth predictor
-hipError_t launch_ab4(void* out, const void* y, const void* f0, const void* f1, const void* f2,
-                      const void* f3, const double c[4], int dtype, int64_t N, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, int dtype, int64_t N, hipStream_t s);
 // zero `bytes` (a multiple of 16) with a fill kernel
 hipError_t launch_zero(void* dst, size_t bytes, hipStream_t s);

@@ -19,6 +19,25 @@ namespace aqc {
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// Streaming (non-temporal) access for vectors that are touched once per pass.
+__device__ __forceinline__ float2 ldnt(const float2* p) {
+  const f32x2 e = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p));
+  return float2{e.x, e.y};
+}
+__device__ __forceinline__ double2 ldnt(const double2* p) {
+  const f64x2 e = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p));
+  return double2{e.x, e.y};
+}
+__device__ __forceinline__ void stnt(float2* p, float2 v) {
+  __builtin_nontemporal_store(f32x2{v.x, v.y}, reinterpret_cast<f32x2*>(p));
+}
+__device__ __forceinline__ void stnt(double2* p, double2 v) {
+  __builtin_nontemporal_store(f64x2{v.x, v.y}, reinterpret_cast<f64x2*>(p));
+}
+
 template <typename R> struct CT2;
 template <> struct CT2<float> { using V = float2; };
 template <> struct CT2<double> { using V = double2; };
@@ -184,9 +203,9 @@ __device__ __forceinline__ void load_tile(const V* src, V* tile, uint64_t base, 
 }
 
 template <typename R, bool FINAL>
-__global__ __launch_bounds__(kThreads) void k_pass(const PassArgs a) {
+__device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, const int64_t nblocks,
+                                          unsigned char* smem) {
   using V = typename CT2<R>::V;
-  extern __shared__ __align__(16) unsigned char smem[];
   double* fsh = reinterpret_cast<double*>(smem + Lds::kF);
   double* lin = reinterpret_cast<double*>(smem + Lds::kLin);
   double* cps = reinterpret_cast<double*>(smem + Lds::kC);
@@ -201,8 +220,6 @@ __global__ __launch_bounds__(kThreads) void k_pass(const PassArgs a) {
   const int tid = threadIdx.x;
   const int tb = a.tb;
   const uint32_t ntile = 1u << tb;
-  const int64_t bid = blockIdx.x;
-  const int64_t nblocks = gridDim.x;
   const uint64_t lowmask = (1ull << a.lbits) - 1ull;
   const uint64_t tmask = lowmask | a.hmask;
   const uint64_t base = FINAL ? ((uint64_t)bid << tb) : pdep64((uint64_t)bid, a.cmask);
@@ -297,7 +314,7 @@ __global__ __launch_bounds__(kThreads) void k_pass(const PassArgs a) {
       hr[u] = 0;
       hi[u] = 0;
       if (!FINAL && ok[u] && accin) {
-        const V av = accin[gidx[u]];
+        const V av = ldnt(accin + gidx[u]);
         hr[u] = av.x;
         hi[u] = av.y;
       }
@@ -352,7 +369,7 @@ __global__ __launch_bounds__(kThreads) void k_pass(const PassArgs a) {
     if (!FINAL) {
 #pragma unroll
       for (int u = 0; u < EB; ++u)
-        if (ok[u]) accout[gidx[u]] = V{hr[u], hi[u]};
+        if (ok[u]) stnt(accout + gidx[u], V{hr[u], hi[u]});
       continue;
     }
 #pragma unroll
@@ -366,11 +383,11 @@ __global__ __launch_bounds__(kThreads) void k_pass(const PassArgs a) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) xin[u][i] = V{0, 0};
         if (!ok[q]) continue;
-        if (accin) ain[u] = accin[gidx[q]];
+        if (accin) ain[u] = ldnt(accin + gidx[q]);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          if (e.in[i]) xin[u][i] = reinterpret_cast<const V*>(e.in[i])[gidx[q]];
-        if (has_comp) lo[u] = compv[gidx[q]];
+          if (e.in[i]) xin[u][i] = ldnt(reinterpret_cast<const V*>(e.in[i]) + gidx[q]);
+        if (has_comp) lo[u] = ldnt(compv + gidx[q]);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -403,9 +420,9 @@ __global__ __launch_bounds__(kThreads) void k_pass(const PassArgs a) {
             const R tr = sr - bre, ti = si - bim;
             const R er = (bre - (sr - tr)) + (vr - tr);
             const R ei = (bim - (si - ti)) + (vi - ti);
-            compv[g] = V{er, ei};
+            stnt(compv + g, V{er, ei});
           }
-          reinterpret_cast<V*>(e.out[o])[g] = V{sr, si};
+          stnt(reinterpret_cast<V*>(e.out[o]) + g, V{sr, si});
           if (o == 0) {
             if (e.red_flags & 1) r0 += (double)sr * (double)sr + (double)si * (double)si;
             if (e.red_flags & 2) {
@@ -421,19 +438,36 @@ __global__ __launch_bounds__(kThreads) void k_pass(const PassArgs a) {
   if (FINAL && e.red_flags) block_reduce3<kThreads>(r0, r1, r2, e.red_flags, rbuf, e.red, nblocks, bid);
 }
 
+template <typename R, bool FINAL>
+__global__ __launch_bounds__(kThreads) void k_pass(const PassArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  pass_body<R, FINAL>(a, blockIdx.x, gridDim.x, smem);
+}
+
+// Many solves in one launch: block b works on tile bmap[b].y of the solve whose
+// arguments are args[bmap[b].x] (x < 0: nothing to do).
+template <typename R, bool FINAL>
+__global__ __launch_bounds__(kThreads) void k_pass_batch(const PassArgs* __restrict__ args,
+                                                         const int2* __restrict__ bmap) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int2 m = bmap[blockIdx.x];
+  if (m.x < 0) return;
+  const PassArgs& a = args[m.x];
+  pass_body<R, FINAL>(a, m.y, (int64_t)1 << (a.n - a.tb), smem);
+}
+
 // High-qubit flips without LDS: lane = bits 0..5 (64 contiguous amplitudes per
 // load instruction), registers = the 2^RB vertices of the hypercube over bits
 // [hb, hb + RB), waves = all remaining bits.  A flip of bit hb + b pairs
 // vertex v with v ^ 2^b inside the same lane's registers.
 template <typename R, int RB>
-__global__ __launch_bounds__(256) void k_regpass(const RegPassArgs a) {
+__device__ __forceinline__ void regpass_body(const RegPassArgs& a, const uint64_t blk) {
   using V = typename CT2<R>::V;
   constexpr int NV = 1 << RB;
   const int lane = threadIdx.x & 63;
   // the wave index is uniform: keep the row bases in scalar registers and add
   // only the lane offset per thread
-  const uint64_t wave =
-      (uint64_t)blockIdx.x * 4 + (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t wave = blk * 4 + (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int hb = a.hb;
   if (wave >= (1ull << (a.n - 6 - RB))) return;
   const int lowcnt = hb - 6;
@@ -443,7 +477,7 @@ __global__ __launch_bounds__(256) void k_regpass(const RegPassArgs a) {
   V* accout = reinterpret_cast<V*>(a.acc_out);
   V x[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) x[v] = (src + (ubase + ((uint64_t)v << hb)))[lane];
+  for (int v = 0; v < NV; ++v) x[v] = ldnt(src + (ubase + ((uint64_t)v << hb)) + lane);
   R c[RB];
 #pragma unroll
   for (int b = 0; b < RB; ++b) c[b] = (R)a.cb[b];
@@ -453,7 +487,7 @@ __global__ __launch_bounds__(256) void k_regpass(const RegPassArgs a) {
     V ain[VB];
 #pragma unroll
     for (int u = 0; u < VB; ++u)
-      ain[u] = accin ? (accin + (ubase + ((uint64_t)(v0 + u) << hb)))[lane] : V{0, 0};
+      ain[u] = accin ? ldnt(accin + (ubase + ((uint64_t)(v0 + u) << hb)) + lane) : V{0, 0};
 #pragma unroll
     for (int u = 0; u < VB; ++u) {
       const int v = v0 + u;
@@ -463,9 +497,47 @@ __global__ __launch_bounds__(256) void k_regpass(const RegPassArgs a) {
         hr += c[b] * x[v ^ (1 << b)].x;
         hi += c[b] * x[v ^ (1 << b)].y;
       }
-      (accout + (ubase + ((uint64_t)v << hb)))[lane] = V{hr + ain[u].x, hi + ain[u].y};
+      stnt(accout + (ubase + ((uint64_t)v << hb)) + lane, V{hr + ain[u].x, hi + ain[u].y});
     }
   }
+}
+
+template <typename R, int RB>
+__global__ __launch_bounds__(256) void k_regpass(const RegPassArgs a) {
+  regpass_body<R, RB>(a, blockIdx.x);
+}
+
+template <typename R, int RB>
+__global__ __launch_bounds__(256) void k_regpass_batch(const RegPassArgs* __restrict__ args,
+                                                       const int2* __restrict__ bmap) {
+  const int2 m = bmap[blockIdx.x];
+  if (m.x < 0) return;
+  regpass_body<R, RB>(args[m.x], (uint64_t)m.y);
+}
+
+hipError_t launch_regpass_batch(const RegPassArgs* args, const int2* bmap, int64_t nblocks, int dtype,
+                                hipStream_t s) {
+  if (dtype == 0)
+    hipLaunchKernelGGL((k_regpass_batch<float, kRegBitsC64>), dim3((unsigned)nblocks), dim3(256), 0, s,
+                       args, bmap);
+  else
+    hipLaunchKernelGGL((k_regpass_batch<double, kRegBitsC128>), dim3((unsigned)nblocks), dim3(256), 0,
+                       s, args, bmap);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_batch(const PassArgs* args, const int2* bmap, int64_t nblocks, int final_pass,
+                             int max_tb, int dtype, hipStream_t s) {
+  const size_t lds = pass_lds_bytes(max_tb, dtype);
+  dim3 grid((unsigned)nblocks), block(kThreads);
+  if (dtype == 0) {
+    if (final_pass) hipLaunchKernelGGL((k_pass_batch<float, true>), grid, block, lds, s, args, bmap);
+    else hipLaunchKernelGGL((k_pass_batch<float, false>), grid, block, lds, s, args, bmap);
+  } else {
+    if (final_pass) hipLaunchKernelGGL((k_pass_batch<double, true>), grid, block, lds, s, args, bmap);
+    else hipLaunchKernelGGL((k_pass_batch<double, false>), grid, block, lds, s, args, bmap);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_regpass(const RegPassArgs& a, int dtype, hipStream_t s) {
@@ -479,9 +551,12 @@ hipError_t launch_regpass(const RegPassArgs& a, int dtype, hipStream_t s) {
 
 template <typename R, bool FINAL>
 static hipError_t set_lds_attr() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass<R, FINAL>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)pass_lds_bytes(sizeof(R) == 4 ? 14 : 13, sizeof(R) == 4 ? 0 : 1));
+  const int bytes = (int)pass_lds_bytes(sizeof(R) == 4 ? 14 : 13, sizeof(R) == 4 ? 0 : 1);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass<R, FINAL>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass_batch<R, FINAL>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 hipError_t prepare_kernels() {
@@ -725,29 +800,6 @@ hipError_t launch_scale(void* y, int dtype, int64_t N, double re, double im, hip
   return hipGetLastError();
 }
 
-template <typename V, typename R>
-__global__ void k_ab4(V* out, const V* y, const V* f0, const V* f1, const V* f2, const V* f3, R c0,
-                      R c1, R c2, R c3, int64_t N) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const V a = y[i], b0 = f0[i], b1 = f1[i], b2 = f2[i], b3 = f3[i];
-    out[i] = V{a.x + c0 * b0.x + c1 * b1.x + c2 * b2.x + c3 * b3.x,
-               a.y + c0 * b0.y + c1 * b1.y + c2 * b2.y + c3 * b3.y};
-  }
-}
-
-hipError_t launch_ab4(void* out, const void* y, const void* f0, const void* f1, const void* f2,
-                      const void* f3, const double c[4], int dtype, int64_t N, hipStream_t s) {
-  if (dtype == 0)
-    hipLaunchKernelGGL((k_ab4<float2, float>), dim3(ew_blocks(N)), dim3(256), 0, s, (float2*)out,
-                       (const float2*)y, (const float2*)f0, (const float2*)f1, (const float2*)f2,
-                       (const float2*)f3, (float)c[0], (float)c[1], (float)c[2], (float)c[3], N);
-  else
-    hipLaunchKernelGGL((k_ab4<double2, double>), dim3(ew_blocks(N)), dim3(256), 0, s,
-                       (double2*)out, (const double2*)y, (const double2*)f0, (const double2*)f1,
-                       (const double2*)f2, (const double2*)f3, c[0], c[1], c[2], c[3], N);
-  return hipGetLastError();
-}
 
 __global__ void k_zero(uint4* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;

@@ -258,3 +258,72 @@ def profile_read(ctx):
         check(lib().aqc_profile_read(ctx.handle, kind, C.byref(ms), C.byref(n), C.byref(b)))
         out[name] = (ms.value, n.value, b.value)
     return out
+
+
+class Batch:
+    """Many fixed-step predictor-corrector solves advanced together (aqc_batch_*)."""
+
+    def __init__(self, ctx: Context, dtype=torch.complex64, capacity=512, graph=True):
+        self.ctx = ctx
+        self.dtype = dtype
+        self.dt = L.C64 if dtype == torch.complex64 else L.C128
+        h = C.c_void_p()
+        check(lib().aqc_batch_create(ctx.handle, self.dt, int(capacity), C.byref(h)))
+        self._h = h
+        self.capacity = capacity
+        self.set_graph(graph)
+        self._keep = {}   # slot -> (psi, workspace) kept alive until retired
+
+    def set_graph(self, on):
+        check(lib().aqc_batch_set_graph(self._h, 1 if on else 0))
+
+    def workspace_bytes(self, ham):
+        return lib().aqc_batch_workspace_bytes(ham.handle, self.dt)
+
+    def admit(self, ham, psi, t0, t1, n_steps, shift, ws=None):
+        if psi.dtype != self.dtype:
+            raise TypeError("state dtype differs from the batch dtype")
+        _check_state(self.ctx, ham.n, psi)
+        need = self.workspace_bytes(ham)
+        if ws is None or ws.numel() < need:
+            ws = workspace(self.ctx, need)
+        slot = C.c_int()
+        check(lib().aqc_batch_admit(self._h, ham.handle, _ptr(psi), _ptr(ws), ws.numel(), float(t0),
+                                    float(t1), int(n_steps), float(shift), C.byref(slot)))
+        self._keep[slot.value] = (psi, ws, ham)
+        return slot.value
+
+    def step(self, ticks=1):
+        na = C.c_int()
+        check(lib().aqc_batch_step(self._h, int(ticks), C.byref(na)))
+        return na.value
+
+    def poll(self):
+        cap = self.capacity
+        arr = (C.c_int * cap)()
+        n = C.c_int()
+        check(lib().aqc_batch_poll(self._h, arr, cap, C.byref(n)))
+        return [arr[i] for i in range(n.value)]
+
+    def retire(self, slot):
+        st = L.EvolveStats()
+        check(lib().aqc_batch_retire(self._h, int(slot), C.byref(st)))
+        psi, ws, ham = self._keep.pop(slot)
+        return psi, st.as_dict()
+
+    def info(self):
+        a, f, t = C.c_int(), C.c_int(), C.c_int64()
+        check(lib().aqc_batch_info(self._h, C.byref(a), C.byref(f), C.byref(t)))
+        return {"active": a.value, "finished": f.value, "ticks": t.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().aqc_batch_destroy(self._h)
+            self._h = C.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

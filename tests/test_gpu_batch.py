@@ -1,0 +1,95 @@
+"""GPU: the batch engine (aqc_batch_*) gives each solve exactly the result it
+gets alone, and matches the oracle."""
+import numpy as np
+import pytest
+
+from oracle import integrate
+from paper_1311_3938_amd import instances as I
+from tests._gpu import TOL, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def eng():
+    from paper_1311_3938_amd import engine
+    ctx = engine.Context(0)
+    yield engine, ctx
+    ctx.close()
+
+
+def _mix():
+    """Solves of different size and plan: one pass (n <= 13 for complex64),
+    register hypercube passes, tile high passes for straddling pairs."""
+    out = []
+    for i, n in enumerate([9, 12, 14, 16, 15, 17]):
+        inst = I.workload_batch_member(i, n_lo=n, n_hi=n)
+        K = 20 + 7 * i
+        T = inst.path["T"]
+        t0, t1 = 0.1 * T, 0.1 * T + K * 0.004
+        out.append((inst, t0, t1, K, 5.0 + i))
+    return out
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_equals_alone_bitwise(eng, dt, graph):
+    engine, ctx = eng
+    import torch
+    tdt = torch.complex64 if dt == "c64" else torch.complex128
+    mix = _mix()
+    hams = [engine.Hamiltonian(ctx, inst) for inst, *_ in mix]
+    psi0 = [I.random_state(inst.n, np.random.default_rng(50 + j)) for j, (inst, *_r) in enumerate(mix)]
+    alone = []
+    for j, (inst, t0, t1, K, sh) in enumerate(mix):
+        p = to_dev(psi0[j], dt)
+        engine.evolve(ctx, hams[j], p, t0, t1, method="pc4", n_steps=K, shift=sh)
+        alone.append(to_host(p))
+    b = engine.Batch(ctx, tdt, capacity=8, graph=graph)
+    states = {}
+    # admit half, run a few ticks, then admit the rest (continuous batching)
+    for j in range(3):
+        inst, t0, t1, K, sh = mix[j]
+        states[b.admit(hams[j], to_dev(psi0[j], dt), t0, t1, K, sh)] = j
+    b.step(5)
+    for j in range(3, len(mix)):
+        inst, t0, t1, K, sh = mix[j]
+        states[b.admit(hams[j], to_dev(psi0[j], dt), t0, t1, K, sh)] = j
+    done = {}
+    while True:
+        na = b.step(4)
+        for slot in b.poll():
+            psi, st = b.retire(slot)
+            j = states[slot]
+            assert st["steps"] == mix[j][3]
+            done[j] = to_host(psi)
+        if na == 0 and len(done) == len(mix):
+            break
+    for j in range(len(mix)):
+        assert np.array_equal(done[j], alone[j]), (j, np.abs(done[j] - alone[j]).max())
+    b.close()
+    for hm in hams:
+        hm.free()
+
+
+def test_batch_matches_oracle(eng):
+    engine, ctx = eng
+    import torch
+    rng = np.random.default_rng(3)
+    insts = [I.workload_batch_member(i, n_lo=8, n_hi=10) for i in range(4)]
+    b = engine.Batch(ctx, torch.complex128, capacity=4)
+    slots = {}
+    for j, inst in enumerate(insts):
+        psi0 = I.random_state(inst.n, rng)
+        hm = engine.Hamiltonian(ctx, inst)
+        K = 30 + 5 * j
+        slots[b.admit(hm, to_dev(psi0, "c128"), 0.0, K * 0.003, K, 2.0)] = (inst, psi0, K, hm)
+    got = {}
+    while b.step(16) > 0 or len(got) < len(insts):
+        for s in b.poll():
+            got[s] = to_host(b.retire(s)[0])
+    for s, (inst, psi0, K, hm) in slots.items():
+        ref = integrate.evolve(inst, psi0, 0.0, K * 0.003, K, "pc4", 2.0)
+        assert np.linalg.norm(got[s] - ref) < TOL["c128"]
+        hm.free()
+    b.close()
