@@ -82,6 +82,87 @@ def measured_traffic(args):
     return rec.get("traffic_bytes_per_launch")
 
 
+def run_batch_mode(args):
+    """Mixed batch of independent solves (EC3 and SK, n uniform in 14..22, XX
+    catalysts, T uniform in 10..100) admitted together into one batch;
+    complex64 state, float64 reductions, graph-captured ticks."""
+    import numpy as np
+    import torch
+    from paper_1311_3938_amd import engine, serve
+    from paper_1311_3938_amd import instances as I
+    insts = [I.workload_batch_member(i) for i in range(args.instances)]
+    ctx = engine.Context(0)
+    reqs = [serve.Request(i, inst) for i, inst in enumerate(insts)]
+    srv = serve.Server(dtype=torch.complex64, hbm_budget_bytes=args.hbm_budget * 1e9,
+                       size_classes=((34, args.instances),), ticks=args.ticks, graph=True,
+                       autotune=not args.no_autotune)
+    log(f"batch: {len(reqs)} solves, n in [{min(r.n for r in reqs)}, {max(r.n for r in reqs)}]")
+    t0 = time.perf_counter()
+    res, wall = srv.run(reqs)
+    amp_steps = sum((1 << r.n) * r.steps for r in res)
+    srv.close()
+    log(f"batch done in {wall:.1f} s")
+    sub = reqs[:args.baseline_subset]
+    seq = serve.sequential_plain(sub)
+    seq_time = sum(s[0] for s in seq)
+    dF = max(abs(seq[i][1] - res[i].fidelity) for i in range(len(sub)))
+    out = {
+        "metric": "batched solves/s", "value": len(res) / wall, "unit": "solves/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": wall * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": f"{len(res)} mixed EC3/SK solves, n 14..22, XX catalysts, "
+                               "T 10..100, pc4, graph-captured batch ticks",
+                   "solves": len(res)},
+        "amp_updates_per_s": amp_steps / wall,
+        "baseline_plain_c128_sequential": {
+            "solves": len(sub), "seconds": seq_time, "solves_per_s": len(sub) / seq_time,
+            "batched_solves_per_s_on_same": None},
+        "max_abs_dF_vs_c128_plain": dF,
+        "latency_s": {"p50": serve.percentile([r.latency for r in res], 50),
+                      "p99": serve.percentile([r.latency for r in res], 99)},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_serve_mode(args):
+    """Poisson-arriving requests, n in [12, n_max] with P(n) ~ 2^-(n-12)/2,
+    EC3 or SK, linear or catalysed path, T uniform in 10..100; admitted by HBM
+    budget, states resident, continuous batching in two size classes."""
+    import numpy as np
+    import torch
+    from paper_1311_3938_amd import engine, serve
+    from paper_1311_3938_amd import instances as I
+    arr = serve.poisson_arrivals(args.requests, args.qps)
+    reqs = [serve.Request(i, I.workload_serving_request(i, n_hi=args.n_max), float(arr[i]))
+            for i in range(args.requests)]
+    srv = serve.Server(dtype=torch.complex64, hbm_budget_bytes=args.hbm_budget * 1e9,
+                       size_classes=((20, 256), (34, 8)), ticks=args.ticks, graph=True,
+                       autotune=not args.no_autotune)
+    log(f"serve: {len(reqs)} requests at {args.qps} qps, n in "
+        f"[{min(r.n for r in reqs)}, {max(r.n for r in reqs)}]")
+    res, wall = srv.run(reqs)
+    srv.close()
+    lat = [r.latency for r in res]
+    log(f"served in {wall:.1f} s")
+    seq = serve.sequential_plain(reqs)
+    seq_lat = serve.fifo_latencies([r.arrival for r in reqs], [s[0] for s in seq])
+    dF = max(abs(seq[i][1] - res[i].fidelity) for i in range(len(reqs)))
+    out = {
+        "metric": "served solves/s", "value": len(res) / wall, "unit": "solves/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": wall * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": f"{len(res)} Poisson requests at {args.qps} qps, n 12..{args.n_max}, "
+                               "EC3/SK, linear or catalysed, T 10..100; continuous batching",
+                   "requests": len(res), "qps": args.qps},
+        "latency_s": {"p50": serve.percentile(lat, 50), "p99": serve.percentile(lat, 99)},
+        "baseline_plain_c128_sequential": {
+            "solves_per_s": len(reqs) / sum(s[0] for s in seq),
+            "latency_s": {"p50": serve.percentile(seq_lat, 50), "p99": serve.percentile(seq_lat, 99)}},
+        "max_abs_dF_vs_c128_plain": dF,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,10 +177,23 @@ def main():
                     help="skip the complex128 comparison of the first window")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB copy (for scaling hardware byte counters)")
+    ap.add_argument("--mode", choices=["single", "batch", "serve"], default="single")
+    ap.add_argument("--instances", type=int, default=512)
+    ap.add_argument("--baseline-subset", type=int, default=16)
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--qps", type=float, default=1.0)
+    ap.add_argument("--n-max", type=int, default=28)
+    ap.add_argument("--ticks", type=int, default=64)
+    ap.add_argument("--hbm-budget", type=float, default=200.0, help="GB")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "batch":
+        return run_batch_mode(args)
+    if args.mode == "serve":
+        return run_serve_mode(args)
 
     import torch
     from paper_1311_3938_amd import engine

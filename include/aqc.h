@@ -125,6 +125,17 @@ typedef struct {
 } aqc_ham_info_t;
 aqc_status aqc_ham_info(const aqc_ham* ham, aqc_ham_info_t* out);
 
+/* Tiling of the tile passes for this Hamiltonian and dtype (replaces the
+ * default and rebuilds the plan at the next use; synchronises the device).
+ * tbf: bits of the last pass's contiguous tile (1..14 complex64, 1..13
+ * complex128); tbh: bits of a high-pass tile; lh: its contiguous low bits
+ * (1 <= lh < tbh); register_passes: 1 lets single-qubit flips above the last
+ * tile run as register hypercube passes.  EINVAL for values out of range,
+ * ENOTSUP when some flip pattern does not fit the tiles (the old tiling stays).
+ * Used by the autotuner.                                                     */
+aqc_status aqc_ham_set_tiling(aqc_ham* ham, int dtype, int tbf, int tbh, int lh,
+                              int register_passes);
+
 /* Spectral enclosure [lo, hi] of H(t) on [t0, t1]: exact minimum and maximum of
  * each schedule's diagonal part (device reduction) combined with the triangle
  * inequality for the flip terms, over a grid of 257 times (Weyl bound).      */

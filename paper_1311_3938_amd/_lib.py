@@ -85,6 +85,7 @@ SIGNATURES = {
                                     C.POINTER(Path), C.POINTER(P)]),
     "aqc_ham_free": (I32, [P]),
     "aqc_ham_info": (I32, [P, C.POINTER(HamInfo)]),
+    "aqc_ham_set_tiling": (I32, [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
     "aqc_spectral_bounds": (I32, [P, P, D, D, C.POINTER(D), C.POINTER(D)]),
     "aqc_apply_workspace_bytes": (SZ, [P, C.c_int]),
     "aqc_apply": (I32, [P, P, D, P, P, C.c_int, P, SZ]),

@@ -1,0 +1,118 @@
+"""Autotuner for the tile-pass plan of H|psi>.
+
+For a Hamiltonian and a dtype it times H|psi> (aqc_apply, HIP events) under a
+set of candidate tilings (aqc_ham_set_tiling): the last pass's tile bits, the
+high-pass tile bits and contiguous low bits, and register hypercube passes on
+or off.  The fastest candidate is applied to the Hamiltonian and cached in a
+JSON file keyed by the GPU architecture, the dtype, n and the flip-group
+structure, so the search runs once per kind of problem.
+"""
+from __future__ import annotations
+
+import json
+import os
+import threading
+
+import torch
+
+from . import _lib as L
+from . import engine
+
+CANDIDATES = {
+    L.C64: [(tbf, tbh, lh, reg) for tbf in (12, 13, 14) for (tbh, lh) in ((13, 4), (13, 5), (12, 4), (14, 6))
+            for reg in (1, 0)],
+    L.C128: [(tbf, tbh, lh, reg) for tbf in (11, 12, 13) for (tbh, lh) in ((12, 3), (12, 4), (11, 3), (13, 5))
+             for reg in (1, 0)],
+}
+
+_lock = threading.Lock()
+_memo = {}
+
+
+def cache_path():
+    base = os.environ.get("AQC_TUNE_CACHE")
+    if base:
+        return base
+    root = os.environ.get("XDG_CACHE_HOME", os.path.join(os.path.expanduser("~"), ".cache"))
+    return os.path.join(root, "aqc", "tiling.json")
+
+
+def _arch():
+    try:
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return "unknown"
+
+
+def structure_key(inst, dtype_code):
+    """n, dtype and the multiset of flip patterns' bit counts."""
+    from collections import Counter
+    flips = Counter(bin(int(x)).count("1") for x in inst.x if int(x) != 0)
+    pats = len({int(x) for x in inst.x if int(x) != 0})
+    return f"{_arch()}|{dtype_code}|n{inst.n}|groups{pats}|" + ",".join(
+        f"{k}:{v}" for k, v in sorted(flips.items()))
+
+
+def time_apply(ctx, ham, psi, out, reps=5):
+    ws = engine.workspace(ctx, L.lib().aqc_apply_workspace_bytes(ham.handle, engine.dtype_code(psi)))
+    engine.apply(ctx, ham, 0.37, psi, out, ws)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record(ctx.stream)
+    for _ in range(reps):
+        engine.apply(ctx, ham, 0.37, psi, out, ws)
+    e.record(ctx.stream)
+    e.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def tune(ctx, ham, inst, dtype=torch.complex64, candidates=None, reps=5):
+    """Time every candidate tiling; apply and return the best
+    ((tbf, tbh, lh, reg), ms, {candidate: ms})."""
+    dt = engine.dtype_code(torch.empty(0, dtype=dtype))
+    cands = candidates if candidates is not None else CANDIDATES[dt]
+    N = 1 << inst.n
+    psi = torch.randn(N, dtype=dtype, device=ctx.device)
+    out = torch.empty_like(psi)
+    times = {}
+    for c in cands:
+        tbf, tbh, lh, reg = c
+        try:
+            ham.set_tiling(dtype, tbf, tbh, lh, bool(reg))
+        except L.AqcError:
+            continue
+        times[c] = time_apply(ctx, ham, psi, out, reps)
+    best = min(times, key=times.get)
+    ham.set_tiling(dtype, *best[:3], bool(best[3]))
+    return best, times[best], times
+
+
+def tune_cached(ctx, ham, inst, dtype=torch.complex64, path=None):
+    """Use the cached choice for this kind of problem, or tune and store it."""
+    path = path or cache_path()
+    dt = engine.dtype_code(torch.empty(0, dtype=dtype))
+    key = structure_key(inst, dt)
+    with _lock:
+        hit = _memo.get((path, key))
+        if hit is not None:
+            ham.set_tiling(dtype, hit[0], hit[1], hit[2], bool(hit[3]))
+            return tuple(hit), None, False
+        cache = {}
+        if os.path.exists(path):
+            try:
+                cache = json.load(open(path))
+            except ValueError:
+                cache = {}
+        if key in cache:
+            c = cache[key]["tiling"]
+            ham.set_tiling(dtype, c[0], c[1], c[2], bool(c[3]))
+            _memo[(path, key)] = list(c)
+            return tuple(c), cache[key]["ms"], False
+        best, ms, _ = tune(ctx, ham, inst, dtype)
+        cache[key] = {"tiling": list(best), "ms": ms}
+        _memo[(path, key)] = list(best)
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1)
+        os.replace(tmp, path)
+        return best, ms, True

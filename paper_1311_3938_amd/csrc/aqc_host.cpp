@@ -259,6 +259,9 @@ struct aqc_ham {
   std::vector<HTerm> ident;      // x == 0, z == 0
   std::vector<GroupH> groups;    // x != 0
   Plan plans[2];
+  // tiling chosen for this Hamiltonian (aqc_ham_set_tiling), per dtype
+  bool tiling_set[2] = {false, false};
+  int tiling[2][4] = {{0, 0, 0, 1}, {0, 0, 0, 1}};  // tbf, tbh, lh, register passes
   // diagonal minimum and maximum per schedule (spectral enclosure)
   bool have_minmax = false;
   std::vector<double> dmin, dmax;  // per schedule
@@ -514,6 +517,13 @@ static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& 
   tl.tbf = env_int(dtype == 0 ? "AQC_TBF_C64" : "AQC_TBF_C128", tl.tbf);
   tl.tbh = env_int(dtype == 0 ? "AQC_TBH_C64" : "AQC_TBH_C128", tl.tbh);
   tl.lh = env_int(dtype == 0 ? "AQC_LH_C64" : "AQC_LH_C128", tl.lh);
+  int use_reg = env_int("AQC_REGPASS", 1);
+  if (h->tiling_set[dtype]) {
+    tl.tbf = h->tiling[dtype][0];
+    tl.tbh = h->tiling[dtype][1];
+    tl.lh = h->tiling[dtype][2];
+    use_reg = h->tiling[dtype][3];
+  }
   const int maxtb = dtype == 0 ? 14 : 13;
   if (tl.tbf < 1 || tl.tbf > maxtb || tl.tbh < 2 || tl.tbh > maxtb || tl.lh < 1 || tl.lh >= tl.tbh)
     return fail(AQC_EINVAL, "tiling parameters out of range");
@@ -552,7 +562,7 @@ static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& 
   // register hypercube passes over contiguous ranges of RB bits
   std::vector<Pass> regp;
   const int rb = dtype == 0 ? kRegBitsC64 : kRegBitsC128;
-  if (env_int("AQC_REGPASS", 1) && n - 6 - rb >= 2) {
+  if (use_reg && n - 6 - rb >= 2) {
     std::map<int, int> single;  // bit -> group
     std::vector<int> keep;
     for (int gi : rest) {
@@ -805,6 +815,39 @@ extern "C" aqc_status aqc_ham_info(const aqc_ham* h, aqc_ham_info_t* out) {
   }
   out->spec_lo = NAN;
   out->spec_hi = NAN;
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_ham_set_tiling(aqc_ham* h, int dtype, int tbf, int tbh, int lh,
+                                         int register_passes) {
+  if (!h) return fail(AQC_EINVAL, "aqc_ham_set_tiling: ham is NULL");
+  if (dtype != AQC_C64 && dtype != AQC_C128) return fail(AQC_ENOTSUP, "aqc_ham_set_tiling: dtype");
+  const int maxtb = dtype == 0 ? 14 : 13;
+  if (tbf < 1 || tbf > maxtb || tbh < 2 || tbh > maxtb || lh < 1 || lh >= tbh)
+    return fail(AQC_EINVAL, "aqc_ham_set_tiling: tile bits out of range");
+  // check the layout before replacing the plan
+  const bool old_set = h->tiling_set[dtype];
+  int old[4];
+  std::memcpy(old, h->tiling[dtype], sizeof(old));
+  h->tiling_set[dtype] = true;
+  h->tiling[dtype][0] = tbf;
+  h->tiling[dtype][1] = tbh;
+  h->tiling[dtype][2] = lh;
+  h->tiling[dtype][3] = register_passes ? 1 : 0;
+  std::vector<Pass> passes;
+  int tb_out = 0;
+  const aqc_status st = layout_passes(h, dtype, passes, &tb_out);
+  if (st != AQC_OK) {
+    h->tiling_set[dtype] = old_set;
+    std::memcpy(h->tiling[dtype], old, sizeof(old));
+    return st;
+  }
+  if (h->plans[dtype].built) {
+    // the old plan's tables may still be read by queued launches
+    HIPCHK(hipSetDevice(h->device));
+    HIPCHK(hipDeviceSynchronize());
+    free_plan(h->plans[dtype]);
+  }
   return AQC_OK;
 }
 
@@ -1573,20 +1616,24 @@ struct aqc_batch {
   hipEvent_t ev[2] = {nullptr, nullptr};
   bool ev_pending[2] = {false, false};
   int cur = 0;
-  // graphs
+  // graphs: one executable per (pinned buffer, ticks per launch)
   bool use_graph = false;
   hipStream_t bs = nullptr;  // private stream for capture
   hipEvent_t sync_ev = nullptr;
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  std::map<std::pair<int, int>, hipGraphExec_t> gexec;
   int64_t ticks = 0;
 };
 
+// ticks per launch group: arguments of up to this many ticks go up in one copy
+// and (with graphs) run as one graph
+constexpr int kBatchGroup = 32;
+
+// H|psi> evaluations a fixed-step pc4 solve of K steps takes
+static int64_t pc4_matvecs(int64_t K) { return K <= 3 ? 4 * K : 12 + 1 + (K - 3); }
+
 static void batch_drop_graphs(aqc_batch* b) {
-  for (int i = 0; i < 2; ++i)
-    if (b->gexec[i]) {
-      hipGraphExecDestroy(b->gexec[i]);
-      b->gexec[i] = nullptr;
-    }
+  for (auto& kv : b->gexec) hipGraphExecDestroy(kv.second);
+  b->gexec.clear();
 }
 
 extern "C" aqc_status aqc_batch_create(aqc_ctx* ctx, int dtype, int capacity, aqc_batch** out) {
@@ -1753,20 +1800,23 @@ static aqc_status batch_rebuild(aqc_batch* b) {
     HIPCHK(hipMemcpy(L.dmap, L.map.data(), L.map.size() * sizeof(int2), hipMemcpyHostToDevice));
   }
   b->args_bytes = off;
-  if (off > b->hargs_cap) {
+  const size_t group_bytes = off * kBatchGroup;
+  if (group_bytes > b->hargs_cap) {
     HIPCHK(hipStreamSynchronize(b->ctx->stream));
     HIPCHK(hipStreamSynchronize(b->bs));
     for (int i = 0; i < 2; ++i) {
       if (b->hargs[i]) HIPCHK(hipHostFree(b->hargs[i]));
-      HIPCHK(hipHostMalloc(&b->hargs[i], off, hipHostMallocDefault));
+      HIPCHK(hipHostMalloc(&b->hargs[i], group_bytes, hipHostMallocDefault));
       b->ev_pending[i] = false;
     }
-    b->hargs_cap = off;
+    b->hargs_cap = group_bytes;
   }
-  if (off > b->dargs_cap) {
+  if (group_bytes > b->dargs_cap) {
+    HIPCHK(hipStreamSynchronize(b->ctx->stream));
+    HIPCHK(hipStreamSynchronize(b->bs));
     if (b->dargs) HIPCHK(hipFree(b->dargs));
-    HIPCHK(hipMalloc(&b->dargs, off));
-    b->dargs_cap = off;
+    HIPCHK(hipMalloc(&b->dargs, group_bytes));
+    b->dargs_cap = group_bytes;
   }
   b->dirty = false;
   return AQC_OK;
@@ -1774,13 +1824,23 @@ static aqc_status batch_rebuild(aqc_batch* b) {
 
 // Fill this tick's arguments of every level into the pinned buffer `buf`.
 static void batch_fill_args(aqc_batch* b, char* buf) {
+  // stage and coefficients of every active slot (one H|psi> each this tick)
+  std::vector<MatvecStage> stage(b->capacity);
+  std::vector<Coefs> coef(b->capacity);
+  for (int s = 0; s < b->capacity; ++s) {
+    auto& sl = b->slots[s];
+    if (!sl.used || sl.done) continue;
+    stage[s] = sl.sg.next(sl.v);
+    coef[s] = coefs_at(sl.h, stage[s].t);
+  }
   for (auto& L : b->levels) {
     for (size_t pi = 0; pi < L.part.size(); ++pi) {
-      aqc_batch::Slot& sl = b->slots[L.part[pi]];
+      const int sidx = L.part[pi];
+      aqc_batch::Slot& sl = b->slots[sidx];
       const aqc_ham* h = sl.h;
       const Plan& p = h->plans[b->dtype];
-      const MatvecStage m = sl.sg.next(sl.v);
-      const Coefs c = coefs_at(h, m.t);
+      const MatvecStage& m = stage[sidx];
+      const Coefs& c = coef[sidx];
       // locate the pass and its position in the plan
       int seen = 0, kpos = -1;
       for (int k = 0; k < (int)p.passes.size(); ++k) {
@@ -1824,16 +1884,20 @@ static void batch_fill_args(aqc_batch* b, char* buf) {
   }
 }
 
-static aqc_status batch_launch_levels(aqc_batch* b, hipStream_t s, const char* hbuf) {
-  HIPCHK(hipMemcpyAsync(b->dargs, hbuf, b->args_bytes, hipMemcpyHostToDevice, s));
-  for (auto& L : b->levels) {
-    const int64_t nb = (int64_t)L.map.size();
-    if (L.kind == 1)
-      HIPCHK(launch_regpass_batch(reinterpret_cast<const RegPassArgs*>(b->dargs + L.arg_off), L.dmap,
-                                  nb, b->dtype, s));
-    else
-      HIPCHK(launch_pass_batch(reinterpret_cast<const PassArgs*>(b->dargs + L.arg_off), L.dmap, nb,
-                               L.kind == 2 ? 1 : 0, L.max_tb, b->dtype, s));
+// Copy G ticks of arguments and launch every level of each tick in order.
+static aqc_status batch_launch_group(aqc_batch* b, hipStream_t s, const char* hbuf, int G) {
+  HIPCHK(hipMemcpyAsync(b->dargs, hbuf, b->args_bytes * (size_t)G, hipMemcpyHostToDevice, s));
+  for (int g = 0; g < G; ++g) {
+    const char* dbase = b->dargs + b->args_bytes * (size_t)g;
+    for (auto& L : b->levels) {
+      const int64_t nb = (int64_t)L.map.size();
+      if (L.kind == 1)
+        HIPCHK(launch_regpass_batch(reinterpret_cast<const RegPassArgs*>(dbase + L.arg_off), L.dmap,
+                                    nb, b->dtype, s));
+      else
+        HIPCHK(launch_pass_batch(reinterpret_cast<const PassArgs*>(dbase + L.arg_off), L.dmap, nb,
+                                 L.kind == 2 ? 1 : 0, L.max_tb, b->dtype, s));
+    }
   }
   return AQC_OK;
 }
@@ -1846,38 +1910,53 @@ extern "C" aqc_status aqc_batch_step(aqc_batch* b, int ticks, int* n_active) {
   HIPCHK(hipEventRecord(b->sync_ev, ctx->stream));
   HIPCHK(hipStreamWaitEvent(b->bs, b->sync_ev, 0));
   const hipStream_t s = b->bs;
-  for (int t = 0; t < ticks; ++t) {
+  int t = 0;
+  while (t < ticks) {
     bool any = false;
     for (auto& sl : b->slots) any |= (sl.used && !sl.done);
     if (!any) break;
     if (b->dirty) STCHK(batch_rebuild(b));
+    // ticks in this group: no solve may finish inside it
+    int64_t G = std::min<int64_t>(ticks - t, kBatchGroup);
+    for (auto& sl : b->slots)
+      if (sl.used && !sl.done) G = std::min<int64_t>(G, pc4_matvecs(sl.sg.k_end) - sl.matvecs);
+    if (G < 1) G = 1;
     const int c = b->cur;
     if (b->ev_pending[c]) HIPCHK(hipEventSynchronize(b->ev[c]));
-    batch_fill_args(b, b->hargs[c]);
+    for (int g = 0; g < (int)G; ++g) {
+      batch_fill_args(b, b->hargs[c] + b->args_bytes * (size_t)g);
+      for (auto& sl : b->slots)
+        if (sl.used && !sl.done) {
+          sl.sg.advance();
+          ++sl.matvecs;
+        }
+    }
     if (b->use_graph) {
-      if (!b->gexec[c]) {
-        hipGraph_t g = nullptr;
+      auto key = std::make_pair(c, (int)G);
+      auto it = b->gexec.find(key);
+      if (it == b->gexec.end()) {
+        hipGraph_t gr = nullptr;
+        hipGraphExec_t ex = nullptr;
         HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        const aqc_status rc = batch_launch_levels(b, s, b->hargs[c]);
-        const hipError_t ec = hipStreamEndCapture(s, &g);
+        const aqc_status rc = batch_launch_group(b, s, b->hargs[c], (int)G);
+        const hipError_t ec = hipStreamEndCapture(s, &gr);
         if (rc != AQC_OK) return rc;
         HIPCHK(ec);
-        HIPCHK(hipGraphInstantiate(&b->gexec[c], g, nullptr, nullptr, 0));
-        HIPCHK(hipGraphDestroy(g));
+        HIPCHK(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
+        HIPCHK(hipGraphDestroy(gr));
+        it = b->gexec.emplace(key, ex).first;
       }
-      HIPCHK(hipGraphLaunch(b->gexec[c], s));
+      HIPCHK(hipGraphLaunch(it->second, s));
     } else {
-      STCHK(batch_launch_levels(b, s, b->hargs[c]));
+      STCHK(batch_launch_group(b, s, b->hargs[c], (int)G));
     }
     HIPCHK(hipEventRecord(b->ev[c], s));
     b->ev_pending[c] = true;
     b->cur ^= 1;
-    ++b->ticks;
-    // advance every participant (each active slot did exactly one H|psi>)
+    b->ticks += G;
+    t += (int)G;
     for (auto& sl : b->slots) {
       if (!sl.used || sl.done) continue;
-      sl.sg.advance();
-      ++sl.matvecs;
       if (sl.sg.k >= sl.sg.k_end) {
         sl.done = true;
         b->dirty = true;

@@ -91,6 +91,11 @@ class Hamiltonian:
                 "n_groups": i.n_groups, "n_passes": list(i.n_passes),
                 "tile_bits": list(i.tile_bits)}
 
+    def set_tiling(self, dtype, tbf, tbh, lh, register_passes=True):
+        dt = L.C64 if dtype in (torch.complex64, L.C64) else L.C128
+        check(lib().aqc_ham_set_tiling(self._h, dt, int(tbf), int(tbh), int(lh),
+                                       1 if register_passes else 0))
+
     def spectral_bounds(self, t0, t1):
         lo, hi = C.c_double(), C.c_double()
         check(lib().aqc_spectral_bounds(self.ctx.handle, self._h, t0, t1, C.byref(lo), C.byref(hi)))

@@ -1,0 +1,48 @@
+"""GPU: the autotuner picks a tiling by timing aqc_apply, the chosen plan is
+still exact, and the choice is cached."""
+import json
+
+import numpy as np
+import pytest
+
+from oracle import sqh
+from paper_1311_3938_amd import instances as I
+from tests._gpu import to_dev, to_host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autotune_picks_and_caches(tmp_path):
+    import torch
+    from paper_1311_3938_amd import autotune, engine
+    ctx = engine.Context(0)
+    inst = I.workload_ec3_catalyst(n=17, m=13, n_pairs=17, T=5.0, seed=9)
+    ham = engine.Hamiltonian(ctx, inst)
+    path = str(tmp_path / "tune.json")
+    best, ms, fresh = autotune.tune_cached(ctx, ham, inst, torch.complex64, path=path)
+    assert fresh and ms > 0
+    cache = json.load(open(path))
+    assert list(cache.values())[0]["tiling"] == list(best)
+    psi = I.random_state(17, np.random.default_rng(1))
+    got = to_host(engine.apply(ctx, ham, 2.0, to_dev(psi, "c64")))
+    assert rel_err(got, sqh.apply_h(inst, 2.0, psi)) < 5e-6
+    ham2 = engine.Hamiltonian(ctx, inst)
+    best2, _, fresh2 = autotune.tune_cached(ctx, ham2, inst, torch.complex64, path=path)
+    assert not fresh2 and tuple(best2) == tuple(best)
+    ham.free()
+    ham2.free()
+    ctx.close()
+
+
+def test_set_tiling_rejects_bad_values():
+    from paper_1311_3938_amd import _lib, engine
+    import torch
+    ctx = engine.Context(0)
+    inst = I.workload_ec3_linear(n=10, m=8, T=2.0, seed=4)
+    ham = engine.Hamiltonian(ctx, inst)
+    with pytest.raises(_lib.AqcError):
+        ham.set_tiling(torch.complex64, 15, 13, 4)
+    with pytest.raises(_lib.AqcError):
+        ham.set_tiling(torch.complex64, 13, 6, 6)
+    ham.free()
+    ctx.close()
