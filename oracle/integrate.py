@@ -24,7 +24,9 @@ scheme out; the reading used here (and by the library) is:
     taken in windows of W steps; after each window the largest estimate decides:
     above ``atol`` the window is undone and the segment restarts from the
     window's first state with h/2; below atol/64 (after at least two windows at
-    this h) the next segment starts with 2h.  Every restart re-runs the RK4
+    this h) the next segment starts with 2h.  The step is never halved below
+    max(hmin, 1e-12 (t1 - t0)) and at most 60 windows in a row are undone: an
+    estimate that stays above atol ends the run with an error.  Every restart re-runs the RK4
     bootstrap, since the multistep history needs equal spacing.  The last
     segment is shortened to end exactly at t1.
 """
@@ -155,6 +157,10 @@ def evolve_adaptive(ham, psi0, t0, t1, atol, h0, hmin=0.0, hmax=math.inf, window
     h = min(h0, hmax)
     seg = Segment(ham, psi0, t0, h, "pc4", shift, cnt)
     windows_at_h = 0
+    # the step is not halved below this floor, and at most 60 windows in a row
+    # are undone: an estimate that never falls below atol ends the run
+    h_floor = max(hmin, 1e-12 * (t1 - t0))
+    rejections_in_row = 0
     while True:
         t_now = seg.t(seg.k)
         left = t1 - t_now
@@ -175,7 +181,10 @@ def evolve_adaptive(ham, psi0, t0, t1, atol, h0, hmin=0.0, hmax=math.inf, window
         errs = []
         seg.advance(nsteps, errs)
         emax = max(errs) if errs else 0.0
-        if emax > atol and seg.h / 2.0 >= hmin:
+        if emax > atol:
+            rejections_in_row += 1
+            if seg.h / 2.0 < h_floor or rejections_in_row > 60:
+                raise RuntimeError("adaptive step: error estimate stays above atol")
             # undo the window, restart from its first state with half the step
             cnt.rejected += nsteps
             cnt.steps -= nsteps
@@ -185,6 +194,7 @@ def evolve_adaptive(ham, psi0, t0, t1, atol, h0, hmin=0.0, hmax=math.inf, window
             seg = Segment(ham, seg.y, seg.t(seg.k), seg.h / 2.0, "pc4", shift, cnt)
             windows_at_h = 0
             continue
+        rejections_in_row = 0
         windows_at_h += 1
         if final:
             segments.append((seg.t_s, seg.h, seg.k))

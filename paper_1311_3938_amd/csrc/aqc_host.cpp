@@ -1501,11 +1501,18 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
       stats->t_reached = sg.ts + (double)sg.k * sg.h;
     }
   } else {
-    // adaptive predictor-corrector (windows of W steps, Milne estimates)
+    // adaptive predictor-corrector (windows of W steps, Milne estimates); the
+    // step never grows past the stability guard
     const int W = o->window;
-    const double hmax = o->hmax > 0 ? o->hmax : INFINITY;
+    double hmax = o->hmax > 0 ? o->hmax : INFINITY;
+    if (o->stab_limit > 0.0 && stats->rho > 0.0) hmax = std::min(hmax, o->stab_limit / stats->rho);
     SegStepper sg = new_seg(t0, std::min(o->h0, hmax));
     int windows_at_h = 0;
+    // halving stops at this floor: an error estimate that never falls below
+    // atol (atol under the rounding floor of the dtype) ends the run instead
+    // of shrinking the step without bound
+    const double h_floor = std::max(o->hmin, 1e-12 * (t1 - t0));
+    int rejections_in_row = 0;
     while (rc == AQC_OK) {
       const double t_now = sg.ts + (double)sg.k * sg.h;
       const double left = t1 - t_now;
@@ -1536,7 +1543,18 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
         STCHK(read_results(ctx, 8 + ne, tmp.data()));
         for (int i = 0; i < ne; ++i) emax = std::max(emax, kMilne * std::sqrt(tmp[8 + i]));
       }
-      if (emax > o->atol && sg.h / 2.0 >= o->hmin) {
+      if (emax > o->atol) {
+        if (sg.h / 2.0 < h_floor || ++rejections_in_row > 60) {
+          stats->t_reached = before.ts + (double)before.k * before.h;
+          HIPCHK(launch_copy(ev.v.y, ev.ckpt, dtype, ev.N, ctx->stream));
+          if (ev.ckpt_lo) HIPCHK(launch_copy(ev.v.ycomp, ev.ckpt_lo, dtype, ev.N, ctx->stream));
+          char buf[200];
+          snprintf(buf, sizeof buf,
+                   "adaptive step: error estimate %.3g stays above atol %.3g down to h = %.3g "
+                   "(atol below the precision floor?)", emax, o->atol, sg.h);
+          rc = fail(AQC_EUNSTABLE, buf);
+          break;
+        }
         stats->rejected += (stats->steps - steps_before);
         stats->steps = steps_before;
         HIPCHK(launch_copy(ev.v.y, ev.ckpt, dtype, ev.N, ctx->stream));
@@ -1547,6 +1565,7 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
         continue;
       }
       stats->max_err = std::max(stats->max_err, emax);
+      rejections_in_row = 0;
       ++windows_at_h;
       if (fin) {
         record(sg);

@@ -164,3 +164,19 @@ def test_deterministic_bitwise(eng):
         outs.append(to_host(psi))
     assert np.array_equal(outs[0], outs[1])
     ham.free()
+
+
+def test_adaptive_below_precision_floor_fails_fast(eng):
+    """complex64 cannot meet atol = 1e-12 at 2^12 amplitudes (its rounding
+    floor is far above): the controller stops with AQC_EUNSTABLE."""
+    engine, ctx = eng
+    from paper_1311_3938_amd import _lib
+    inst, psi0 = _ec3_12()
+    ham = engine.Hamiltonian(ctx, inst)
+    psi = to_dev(psi0, "c64")
+    with pytest.raises(_lib.AqcError) as ei:
+        engine.evolve(ctx, ham, psi, 0.0, 1.0, method="pc4", n_steps=0, atol=1e-12, h0=0.01,
+                      window=8, shift=20.0)
+    assert ei.value.status == _lib.AQC_EUNSTABLE
+    assert "precision floor" in str(ei.value)
+    ham.free()

@@ -191,3 +191,10 @@ def test_planted_mistakes_are_caught(monkeypatch):
     errs = [np.linalg.norm(integrate.evolve(inst, psi0, 0.0, 2.0, K, "pc4") - ref)
             for K in (100, 200)]
     assert not (11.0 < errs[0] / errs[1] < 22.0)
+
+
+def test_adaptive_refuses_unreachable_tolerance():
+    """An estimate that cannot fall below atol ends the run (no endless halving)."""
+    inst, rng = _random_td_instance(3, 91)
+    with pytest.raises(RuntimeError):
+        integrate.evolve_adaptive(inst, I.random_state(3, rng), 0.0, 2.0, atol=1e-30, h0=0.1)
