@@ -95,7 +95,7 @@ def run_batch_mode(args):
     reqs = [serve.Request(i, inst) for i, inst in enumerate(insts)]
     srv = serve.Server(dtype=torch.complex64, hbm_budget_bytes=args.hbm_budget * 1e9,
                        size_classes=((34, args.instances),), ticks=args.ticks, graph=True,
-                       autotune=not args.no_autotune)
+                       autotune=not args.no_autotune, progress=8)
     log(f"batch: {len(reqs)} solves, n in [{min(r.n for r in reqs)}, {max(r.n for r in reqs)}]")
     t0 = time.perf_counter()
     res, wall = srv.run(reqs)
@@ -103,7 +103,8 @@ def run_batch_mode(args):
     srv.close()
     log(f"batch done in {wall:.1f} s")
     sub = reqs[:args.baseline_subset]
-    seq = serve.sequential_plain(sub)
+    log(f"sequential complex128 on {len(sub)} of the solves")
+    seq = serve.sequential_plain(sub, progress=True)
     seq_time = sum(s[0] for s in seq)
     dF = max(abs(seq[i][1] - res[i].fidelity) for i in range(len(sub)))
     out = {
@@ -137,14 +138,15 @@ def run_serve_mode(args):
             for i in range(args.requests)]
     srv = serve.Server(dtype=torch.complex64, hbm_budget_bytes=args.hbm_budget * 1e9,
                        size_classes=((20, 256), (34, 8)), ticks=args.ticks, graph=True,
-                       autotune=not args.no_autotune)
+                       autotune=not args.no_autotune, progress=8)
     log(f"serve: {len(reqs)} requests at {args.qps} qps, n in "
         f"[{min(r.n for r in reqs)}, {max(r.n for r in reqs)}]")
     res, wall = srv.run(reqs)
     srv.close()
     lat = [r.latency for r in res]
     log(f"served in {wall:.1f} s")
-    seq = serve.sequential_plain(reqs)
+    log("sequential complex128 on the same requests")
+    seq = serve.sequential_plain(reqs, progress=True)
     seq_lat = serve.fifo_latencies([r.arrival for r in reqs], [s[0] for s in seq])
     dF = max(abs(seq[i][1] - res[i].fidelity) for i in range(len(reqs)))
     out = {

@@ -20,6 +20,7 @@ of solving the request alone.
 from __future__ import annotations
 
 import math
+import sys
 import threading
 import time
 from dataclasses import dataclass, field
@@ -88,6 +89,7 @@ class _Class:
         self.live = {}      # slot -> (request, ham, bytes, admitted time)
         self.lock = threading.Lock()
         self.thread = None
+        self.ticks_done = 0
 
     def run(self):
         srv = self.server
@@ -105,8 +107,10 @@ class _Class:
                         self._admit(req, need)
                 if self.live:
                     self.batch.step(srv.ticks)
+                    self.ticks_done += srv.ticks
                     for slot in self.batch.poll():
                         self._finish(slot)
+                    srv.report_ticks(self)
                 else:
                     with self.lock:
                         empty = not self.queue
@@ -127,6 +131,9 @@ class _Class:
         psi = torch.full((N,), 1.0 / math.sqrt(N), dtype=srv.dtype, device=srv.device)
         slot = self.batch.admit(ham, psi, 0.0, req.T, K, shift)
         self.live[slot] = (req, ham, need, srv.now())
+        srv.n_admitted += 1
+        if srv.progress and srv.n_admitted % (8 * srv.progress) == 0:
+            srv.log(f"{srv.n_admitted} admitted, t={srv.now():.1f}s")
 
     def _finish(self, slot):
         srv = self.server
@@ -149,7 +156,7 @@ class Server:
 
     def __init__(self, device=0, dtype=torch.complex64, hbm_budget_bytes=200e9,
                  size_classes=((20, 256), (34, 8)), ticks=8, graph=True, keep_states=False,
-                 autotune=False):
+                 autotune=False, progress=0):
         self.device = torch.device("cuda", device)
         self.dtype = dtype
         self.budget = float(hbm_budget_bytes)
@@ -158,6 +165,9 @@ class Server:
         self.graph = graph
         self.keep_states = keep_states
         self.autotune = autotune
+        self.progress = progress     # print a line every `progress` results (0: quiet)
+        self.n_admitted = 0
+        self._last_report = 0.0
         self._mem = threading.Lock()
         self._res = threading.Lock()
         self.results = []
@@ -184,9 +194,27 @@ class Server:
         with self._mem:
             self.used -= b
 
+    def log(self, msg):
+        print(f"[serve] {msg}", file=sys.stderr, flush=True)
+
     def add_result(self, r):
         with self._res:
             self.results.append(r)
+            if self.progress and len(self.results) % self.progress == 0:
+                active = sum(len(c.live) for c in self.classes)
+                self.log(f"{len(self.results)} done, {active} running, t={self.now():.1f}s")
+
+    def report_ticks(self, klass):
+        """A progress line after a batch step, at most every 20 seconds."""
+        if not self.progress:
+            return
+        with self._res:
+            now = self.now()
+            if now - self._last_report < 20.0:
+                return
+            self._last_report = now
+            self.log(f"class {klass.idx}: {klass.ticks_done} ticks, {len(klass.live)} running, "
+                     f"{len(self.results)} done, t={now:.1f}s")
 
     def run(self, requests):
         """Serve the requests (arrival times relative to the start); returns
@@ -222,7 +250,7 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=float), q)) if len(xs) else float("nan")
 
 
-def sequential_plain(requests, device=0, dtype=torch.complex128):
+def sequential_plain(requests, device=0, dtype=torch.complex128, progress=False):
     """The plain path: each request solved alone with aqc_evolve, one after the
     other in arrival order.  Returns per-request (service seconds, fidelity)."""
     ctx = engine.Context(device)
@@ -238,6 +266,9 @@ def sequential_plain(requests, device=0, dtype=torch.complex128):
         mass, _ = engine.ground_mass(ctx, ham, req.T, psi)
         torch.cuda.synchronize()
         out.append((time.perf_counter() - t0, mass, K))
+        if progress:
+            print(f"[serve] sequential {len(out)}/{len(requests)} (n={req.n}, {out[-1][0]:.2f} s)",
+                  file=sys.stderr, flush=True)
         ham.free()
         del psi
     ctx.close()
