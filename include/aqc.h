@@ -129,8 +129,11 @@ aqc_status aqc_ham_info(const aqc_ham* ham, aqc_ham_info_t* out);
  * default and rebuilds the plan at the next use; synchronises the device).
  * tbf: bits of the last pass's contiguous tile (1..14 complex64, 1..13
  * complex128); tbh: bits of a high-pass tile; lh: its contiguous low bits
- * (1 <= lh < tbh); register_passes: 1 lets single-qubit flips above the last
- * tile run as register hypercube passes.  EINVAL for values out of range,
+ * (1 <= lh < tbh); register_passes: how single-qubit flips above the last
+ * tile run: 0 in tile passes, 1 in register hypercube passes of the width the
+ * library picks for n, 2 in narrow register passes (one wave per hypercube),
+ * 3 in wide ones (eight waves of a workgroup span three more bits and trade
+ * vertices through LDS).  EINVAL for values out of range,
  * ENOTSUP when some flip pattern does not fit the tiles (the old tiling stays).
  * Used by the autotuner.                                                     */
 aqc_status aqc_ham_set_tiling(aqc_ham* ham, int dtype, int tbf, int tbh, int lh,

@@ -2,8 +2,8 @@
 
 For a Hamiltonian and a dtype it times H|psi> (aqc_apply, HIP events) under a
 set of candidate tilings (aqc_ham_set_tiling): the last pass's tile bits, the
-high-pass tile bits and contiguous low bits, and register hypercube passes on
-or off.  The fastest candidate is applied to the Hamiltonian and cached in a
+high-pass tile bits and contiguous low bits, and register hypercube passes
+(wide, narrow or none).  The fastest candidate is applied to the Hamiltonian and cached in a
 JSON file keyed by the GPU architecture, the dtype, n and the flip-group
 structure, so the search runs once per kind of problem.
 """
@@ -18,11 +18,12 @@ import torch
 from . import _lib as L
 from . import engine
 
+# register passes: 3 wide, 2 narrow, 0 none (flips in tile passes)
 CANDIDATES = {
     L.C64: [(tbf, tbh, lh, reg) for tbf in (12, 13, 14) for (tbh, lh) in ((13, 4), (13, 5), (12, 4), (14, 6))
-            for reg in (1, 0)],
+            for reg in (3, 2, 0)],
     L.C128: [(tbf, tbh, lh, reg) for tbf in (11, 12, 13) for (tbh, lh) in ((12, 3), (12, 4), (11, 3), (13, 5))
-             for reg in (1, 0)],
+             for reg in (3, 2, 0)],
 }
 
 _lock = threading.Lock()
@@ -77,12 +78,12 @@ def tune(ctx, ham, inst, dtype=torch.complex64, candidates=None, reps=5):
     for c in cands:
         tbf, tbh, lh, reg = c
         try:
-            ham.set_tiling(dtype, tbf, tbh, lh, bool(reg))
+            ham.set_tiling(dtype, tbf, tbh, lh, reg)
         except L.AqcError:
             continue
         times[c] = time_apply(ctx, ham, psi, out, reps)
     best = min(times, key=times.get)
-    ham.set_tiling(dtype, *best[:3], bool(best[3]))
+    ham.set_tiling(dtype, *best)
     return best, times[best], times
 
 
@@ -94,7 +95,7 @@ def tune_cached(ctx, ham, inst, dtype=torch.complex64, path=None):
     with _lock:
         hit = _memo.get((path, key))
         if hit is not None:
-            ham.set_tiling(dtype, hit[0], hit[1], hit[2], bool(hit[3]))
+            ham.set_tiling(dtype, *hit)
             return tuple(hit), None, False
         cache = {}
         if os.path.exists(path):
@@ -104,7 +105,7 @@ def tune_cached(ctx, ham, inst, dtype=torch.complex64, path=None):
                 cache = {}
         if key in cache:
             c = cache[key]["tiling"]
-            ham.set_tiling(dtype, c[0], c[1], c[2], bool(c[3]))
+            ham.set_tiling(dtype, *c)
             _memo[(path, key)] = list(c)
             return tuple(c), cache[key]["ms"], False
         best, ms, _ = tune(ctx, ham, inst, dtype)

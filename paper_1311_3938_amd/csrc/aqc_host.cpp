@@ -219,8 +219,9 @@ struct HTerm {
 
 struct Pass {
   int kind = 0;              // 0: LDS tile pass, 1: register hypercube pass
-  int hb = 0;                // kind 1: hypercube bits [hb, hb + RB)
-  int bit_group[8] = {-1, -1, -1, -1, -1, -1, -1, -1};  // kind 1: group per bit
+  int hb = 0;                // kind 1: hypercube bits [hb, hb + RB + wb)
+  int wb = 0;                // kind 1: bits spanned by the waves of a workgroup
+  int bit_group[16] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
   int tb = 0, lbits = 0;
   uint64_t hmask = 0, cmask = 0;
   bool final_pass = false;
@@ -372,6 +373,9 @@ struct Tiling {
   int tbf, tbh, lh;
 };
 
+// wide register passes when they give at least 2^this many workgroups
+constexpr int kWideMinLogBlocks = 8;
+
 static Tiling default_tiling(int dtype) {
   // last pass: 2^13 (c64) / 2^12 (c128) amplitudes = 64 KiB of LDS, so two
   // workgroups share a CU; high passes use the same tile with 128-byte chunks.
@@ -518,6 +522,7 @@ static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& 
   tl.tbh = env_int(dtype == 0 ? "AQC_TBH_C64" : "AQC_TBH_C128", tl.tbh);
   tl.lh = env_int(dtype == 0 ? "AQC_LH_C64" : "AQC_LH_C128", tl.lh);
   int use_reg = env_int("AQC_REGPASS", 1);
+  if (use_reg < 0 || use_reg > 3) use_reg = 1;
   if (h->tiling_set[dtype]) {
     tl.tbf = h->tiling[dtype][0];
     tl.tbh = h->tiling[dtype][1];
@@ -559,9 +564,15 @@ static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& 
     }
   }
   // single-qubit flips with real coefficients above the last pass's tile go to
-  // register hypercube passes over contiguous ranges of RB bits
+  // register hypercube passes over contiguous ranges of RB (+ kWaveBits) bits.
+  // use_reg: 0 none, 1 wide passes when the state is large enough to give
+  // every CU several workgroups, else narrow; 2 narrow only; 3 wide only.
   std::vector<Pass> regp;
   const int rb = dtype == 0 ? kRegBitsC64 : kRegBitsC128;
+  int wb = 0;
+  if (use_reg == 3 || (use_reg == 1 && n - 6 - rb - kWaveBits >= kWideMinLogBlocks)) wb = kWaveBits;
+  if (wb && n - 6 - rb - wb < 1) wb = 0;
+  const int width = rb + wb;
   if (use_reg && n - 6 - rb >= 2) {
     std::map<int, int> single;  // bit -> group
     std::vector<int> keep;
@@ -573,11 +584,12 @@ static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& 
     }
     while (!single.empty()) {
       const int b0 = single.begin()->first;
-      const int hb = std::max(6, std::min(b0, n - rb));
+      const int hb = std::max(6, std::min(b0, n - width));
       Pass ps;
       ps.kind = 1;
       ps.hb = hb;
-      for (int b = 0; b < rb; ++b) {
+      ps.wb = wb;
+      for (int b = 0; b < width; ++b) {
         auto it = single.find(hb + b);
         if (it != single.end()) {
           ps.bit_group[b] = it->second;
@@ -585,7 +597,7 @@ static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& 
           single.erase(it);
         }
       }
-      ps.tb = rb;
+      ps.tb = width;
       regp.push_back(ps);
     }
     rest.swap(keep);
@@ -691,6 +703,16 @@ static void fill_common(PassArgs& a, const aqc_ham* h, const Plan& p, const Pass
   a.dg = p.dg;
 }
 
+// coefficient of each bit's single-qubit flip in a register pass
+static void fill_reg_coefs(RegPassArgs& ra, const aqc_ham* h, const Pass& ps, const Coefs& c) {
+  for (int b = 0; b < 12; ++b) {
+    double cb = 0.0;
+    if (b < ps.tb && ps.bit_group[b] >= 0)
+      for (const HTerm& t : h->groups[ps.bit_group[b]].terms) cb += t.w * c.f[t.sid];
+    ra.cb[b] = cb;
+  }
+}
+
 // (H(t) - shift) u, with the last pass's epilogue `epi`.  hbuf: one vector when
 // the plan has high passes.
 static aqc_status run_matvec(aqc_ctx* ctx, const aqc_ham* h, int dtype, double t, double shift,
@@ -706,15 +728,11 @@ static aqc_status run_matvec(aqc_ctx* ctx, const aqc_ham* h, int dtype, double t
       std::memset(&ra, 0, sizeof(ra));
       ra.n = h->n;
       ra.hb = ps.hb;
+      ra.wb = ps.wb;
       ra.src = u;
       ra.acc_in = k > 0 ? hbuf : nullptr;
       ra.acc_out = hbuf;
-      for (int b = 0; b < 8; ++b) {
-        double cb = 0.0;
-        if (ps.bit_group[b] >= 0)
-          for (const HTerm& t : h->groups[ps.bit_group[b]].terms) cb += t.w * c.f[t.sid];
-        ra.cb[b] = cb;
-      }
+      fill_reg_coefs(ra, h, ps, c);
       if (ctx->prof_on) {
         aqc_ctx::Rec r;
         r.kind = AQC_PROF_HIGH_PASS;
@@ -825,6 +843,8 @@ extern "C" aqc_status aqc_ham_set_tiling(aqc_ham* h, int dtype, int tbf, int tbh
   const int maxtb = dtype == 0 ? 14 : 13;
   if (tbf < 1 || tbf > maxtb || tbh < 2 || tbh > maxtb || lh < 1 || lh >= tbh)
     return fail(AQC_EINVAL, "aqc_ham_set_tiling: tile bits out of range");
+  if (register_passes < 0 || register_passes > 3)
+    return fail(AQC_EINVAL, "aqc_ham_set_tiling: register_passes is 0..3");
   // check the layout before replacing the plan
   const bool old_set = h->tiling_set[dtype];
   int old[4];
@@ -833,7 +853,7 @@ extern "C" aqc_status aqc_ham_set_tiling(aqc_ham* h, int dtype, int tbf, int tbh
   h->tiling[dtype][0] = tbf;
   h->tiling[dtype][1] = tbh;
   h->tiling[dtype][2] = lh;
-  h->tiling[dtype][3] = register_passes ? 1 : 0;
+  h->tiling[dtype][3] = register_passes;
   std::vector<Pass> passes;
   int tb_out = 0;
   const aqc_status st = layout_passes(h, dtype, passes, &tb_out);
@@ -1611,12 +1631,13 @@ struct aqc_batch {
     SegStepper sg;
     double t0 = 0, t1 = 0, shift = 0;
     int64_t matvecs = 0;
-    int nreg = 0, nlds = 0;  // high passes of each kind in the slot's plan
+    int nreg = 0, nwide = 0, nlds = 0;  // high passes of each kind in the slot's plan
   };
   std::vector<Slot> slots;
-  // launch levels: reg passes 0..R-1, tile high passes 0..L-1, then the last pass
+  // launch levels: register passes 0..R-1 (narrow, then wide), tile high
+  // passes 0..L-1, then the last pass
   struct Level {
-    int kind = 0;   // 1 register pass, 0 tile high pass, 2 last pass
+    int kind = 0;   // 1 narrow / 3 wide register pass, 0 tile high pass, 2 last pass
     int idx = 0;    // which pass of that kind in each slot's plan
     int max_tb = 0;
     std::vector<int> part;     // participating slots, in argument order
@@ -1646,6 +1667,16 @@ struct aqc_batch {
 // ticks per launch group: arguments of up to this many ticks go up in one copy
 // and (with graphs) run as one graph
 constexpr int kBatchGroup = 32;
+
+// launch level of a pass: 0 tile high pass, 1 narrow register pass, 2 last
+// pass, 3 wide register pass
+static int level_kind(const Pass& ps) {
+  if (ps.final_pass) return 2;
+  if (ps.kind == 1) return ps.wb ? 3 : 1;
+  return 0;
+}
+
+static bool is_reg_level(int kind) { return kind == 1 || kind == 3; }
 
 // H|psi> evaluations a fixed-step pc4 solve of K steps takes
 static int64_t pc4_matvecs(int64_t K) { return K <= 3 ? 4 * K : 12 + 1 + (K - 3); }
@@ -1746,7 +1777,9 @@ extern "C" aqc_status aqc_batch_admit(aqc_batch* b, const aqc_ham* h, void* psi,
   sl.shift = shift;
   for (const Pass& ps : h->plans[b->dtype].passes) {
     if (ps.final_pass) continue;
-    if (ps.kind == 1) ++sl.nreg;
+    const int k = level_kind(ps);
+    if (k == 1) ++sl.nreg;
+    else if (k == 3) ++sl.nwide;
     else ++sl.nlds;
   }
   b->dirty = true;
@@ -1766,10 +1799,11 @@ static aqc_status batch_rebuild(aqc_batch* b) {
     if (L.dmap) hipFree(L.dmap);
   b->levels.clear();
   batch_drop_graphs(b);
-  int maxr = 0, maxl = 0;
+  int maxr = 0, maxw = 0, maxl = 0;
   for (auto& sl : b->slots)
     if (sl.used && !sl.done) {
       maxr = std::max(maxr, sl.nreg);
+      maxw = std::max(maxw, sl.nwide);
       maxl = std::max(maxl, sl.nlds);
     }
   auto add_level = [&](int kind, int idx) {
@@ -1784,8 +1818,7 @@ static aqc_status batch_rebuild(aqc_batch* b) {
       int seen = 0;
       const Pass* found = nullptr;
       for (const Pass& ps : p.passes) {
-        const int k = ps.final_pass ? 2 : ps.kind;
-        if (k != kind) continue;
+        if (level_kind(ps) != kind) continue;
         if (seen++ == idx) {
           found = &ps;
           break;
@@ -1795,9 +1828,8 @@ static aqc_status batch_rebuild(aqc_batch* b) {
       const int pi = (int)L.part.size();
       L.part.push_back(s);
       int64_t nb;
-      if (kind == 1) {
-        const int rb = b->dtype == 0 ? kRegBitsC64 : kRegBitsC128;
-        nb = (((int64_t)1 << (sl.h->n - 6 - rb)) + 3) / 4;
+      if (kind == 1 || kind == 3) {
+        nb = regpass_blocks(sl.h->n, found->wb, b->dtype);
       } else {
         nb = (int64_t)1 << (sl.h->n - found->tb);
         L.max_tb = std::max(L.max_tb, found->tb);
@@ -1806,13 +1838,16 @@ static aqc_status batch_rebuild(aqc_batch* b) {
     }
     if (!L.part.empty()) b->levels.push_back(std::move(L));
   };
+  // a plan's register passes all have one width, so each slot still runs its
+  // passes in plan order
   for (int r = 0; r < maxr; ++r) add_level(1, r);
+  for (int r = 0; r < maxw; ++r) add_level(3, r);
   for (int l = 0; l < maxl; ++l) add_level(0, l);
   add_level(2, 0);
   size_t off = 0;
   for (auto& L : b->levels) {
     L.arg_off = off;
-    off += L.part.size() * (L.kind == 1 ? sizeof(RegPassArgs) : sizeof(PassArgs));
+    off += L.part.size() * (is_reg_level(L.kind) ? sizeof(RegPassArgs) : sizeof(PassArgs));
     off = (off + 255) & ~(size_t)255;
     if (L.map.size() >= (size_t)INT32_MAX) return fail(AQC_ENOTSUP, "batch too large");
     HIPCHK(hipMalloc(&L.dmap, L.map.size() * sizeof(int2)));
@@ -1863,9 +1898,7 @@ static void batch_fill_args(aqc_batch* b, char* buf) {
       // locate the pass and its position in the plan
       int seen = 0, kpos = -1;
       for (int k = 0; k < (int)p.passes.size(); ++k) {
-        const Pass& ps = p.passes[k];
-        const int kind = ps.final_pass ? 2 : ps.kind;
-        if (kind != L.kind) continue;
+        if (level_kind(p.passes[k]) != L.kind) continue;
         if (seen++ == L.idx) {
           kpos = k;
           break;
@@ -1873,20 +1906,16 @@ static void batch_fill_args(aqc_batch* b, char* buf) {
       }
       const Pass& ps = p.passes[kpos];
       const int np = (int)p.passes.size();
-      if (L.kind == 1) {
+      if (is_reg_level(L.kind)) {
         RegPassArgs* ra = reinterpret_cast<RegPassArgs*>(buf + L.arg_off) + pi;
         std::memset(ra, 0, sizeof(*ra));
         ra->n = h->n;
         ra->hb = ps.hb;
+        ra->wb = ps.wb;
         ra->src = m.src;
         ra->acc_in = kpos > 0 ? sl.v.hbuf : nullptr;
         ra->acc_out = sl.v.hbuf;
-        for (int bb = 0; bb < 8; ++bb) {
-          double cb = 0.0;
-          if (ps.bit_group[bb] >= 0)
-            for (const HTerm& t : h->groups[ps.bit_group[bb]].terms) cb += t.w * c.f[t.sid];
-          ra->cb[bb] = cb;
-        }
+        fill_reg_coefs(*ra, h, ps, c);
       } else {
         PassArgs* a = reinterpret_cast<PassArgs*>(buf + L.arg_off) + pi;
         fill_common(*a, h, p, ps, c, sl.shift);
@@ -1910,9 +1939,9 @@ static aqc_status batch_launch_group(aqc_batch* b, hipStream_t s, const char* hb
     const char* dbase = b->dargs + b->args_bytes * (size_t)g;
     for (auto& L : b->levels) {
       const int64_t nb = (int64_t)L.map.size();
-      if (L.kind == 1)
+      if (is_reg_level(L.kind))
         HIPCHK(launch_regpass_batch(reinterpret_cast<const RegPassArgs*>(dbase + L.arg_off), L.dmap,
-                                    nb, b->dtype, s));
+                                    nb, L.kind == 3 ? kWaveBits : 0, b->dtype, s));
       else
         HIPCHK(launch_pass_batch(reinterpret_cast<const PassArgs*>(dbase + L.arg_off), L.dmap, nb,
                                  L.kind == 2 ? 1 : 0, L.max_tb, b->dtype, s));

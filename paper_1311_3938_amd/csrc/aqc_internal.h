@@ -99,24 +99,31 @@ struct PassArgs {
 };
 
 // Register hypercube pass: single-qubit flips (real coefficients) on the bits
-// [hb, hb + RB), with RB = kRegBitsC64 / kRegBitsC128.  A wave owns 64
-// contiguous amplitudes (one per lane) at each vertex of the hypercube.
+// [hb, hb + RB + wb), with RB = kRegBitsC64 / kRegBitsC128 and wb = 0 or
+// kWaveBits.  A wave owns 64 contiguous amplitudes (one per lane) at each
+// vertex of the hypercube over [hb, hb + RB); with wb > 0 the 2^wb waves of a
+// workgroup span the next wb bits and exchange vertices through LDS.
 constexpr int kRegBitsC64 = 6;
 constexpr int kRegBitsC128 = 5;
+constexpr int kWaveBits = 3;
 struct RegPassArgs {
   int32_t n;
   int32_t hb;
+  int32_t wb;
+  int32_t pad;
   const void* src;
   const void* acc_in;
   void* acc_out;
-  double cb[8];       // coefficient of the flip of bit hb + b
+  double cb[12];      // coefficient of the flip of bit hb + b
 };
 
 // ---- launchers (aqc_kernels.hip) -------------------------------------------
 hipError_t launch_regpass(const RegPassArgs& a, int dtype, hipStream_t s);
+// workgroups of a register pass over n qubits
+int64_t regpass_blocks(int n, int wb, int dtype);
 // batched forms: block b serves args[bmap[b].x] at local block bmap[b].y
-hipError_t launch_regpass_batch(const RegPassArgs* args, const int2* bmap, int64_t nblocks, int dtype,
-                                hipStream_t s);
+hipError_t launch_regpass_batch(const RegPassArgs* args, const int2* bmap, int64_t nblocks, int wb,
+                                int dtype, hipStream_t s);
 hipError_t launch_pass_batch(const PassArgs* args, const int2* bmap, int64_t nblocks, int final_pass,
                              int max_tb, int dtype, hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, int dtype, int64_t nblocks, hipStream_t s);

@@ -456,22 +456,42 @@ __global__ __launch_bounds__(kThreads) void k_pass_batch(const PassArgs* __restr
   pass_body<R, FINAL>(a, m.y, (int64_t)1 << (a.n - a.tb), smem);
 }
 
-// High-qubit flips without LDS: lane = bits 0..5 (64 contiguous amplitudes per
-// load instruction), registers = the 2^RB vertices of the hypercube over bits
-// [hb, hb + RB), waves = all remaining bits.  A flip of bit hb + b pairs
-// vertex v with v ^ 2^b inside the same lane's registers.
-template <typename R, int RB>
-__device__ __forceinline__ void regpass_body(const RegPassArgs& a, const uint64_t blk) {
+// High-qubit flips on a hypercube held in registers: lane = bits 0..5 (64
+// contiguous amplitudes per load instruction), registers = the 2^RB vertices of
+// the hypercube over bits [hb, hb + RB).  A flip of bit hb + b pairs vertex v
+// with v ^ 2^b inside the same lane's registers.
+//
+// WB = 0: every wave is independent (four per workgroup, no LDS, no barriers).
+// WB > 0: the 2^WB waves of a workgroup are the values of the next WB bits
+// [hb + RB, hb + RB + WB), so one pass covers RB + WB bits.  A flip of one of
+// those bits pairs a wave with wave ^ 2^j; the partner's vertices are passed
+// through LDS in chunks of CV vertices (double-buffered, one barrier a chunk).
+template <int WB> struct RegShape {
+  static constexpr int threads = WB == 0 ? 256 : (64 << WB);
+};
+
+template <typename R, int RB, int WB>
+__device__ __forceinline__ void regpass_body(const RegPassArgs& a, const uint64_t blk,
+                                             typename CT2<R>::V* ex) {
   using V = typename CT2<R>::V;
   constexpr int NV = 1 << RB;
+  constexpr int NT = RegShape<WB>::threads;
   const int lane = threadIdx.x & 63;
+  const int hb = a.hb;
   // the wave index is uniform: keep the row bases in scalar registers and add
   // only the lane offset per thread
-  const uint64_t wave = blk * 4 + (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int hb = a.hb;
-  if (wave >= (1ull << (a.n - 6 - RB))) return;
-  const int lowcnt = hb - 6;
-  const uint64_t ubase = ((wave & ((1ull << lowcnt) - 1ull)) << 6) | ((wave >> lowcnt) << (hb + RB));
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint64_t ubase;
+  if constexpr (WB == 0) {
+    const uint64_t wave = blk * 4 + (uint64_t)wv;
+    if (wave >= (1ull << (a.n - 6 - RB))) return;
+    const int lowcnt = hb - 6;
+    ubase = ((wave & ((1ull << lowcnt) - 1ull)) << 6) | ((wave >> lowcnt) << (hb + RB));
+  } else {
+    const int lowcnt = hb - 6;
+    ubase = ((blk & ((1ull << lowcnt) - 1ull)) << 6) | ((blk >> lowcnt) << (hb + RB + WB)) |
+            ((uint64_t)wv << (hb + RB));
+  }
   const V* src = reinterpret_cast<const V*>(a.src);
   const V* accin = reinterpret_cast<const V*>(a.acc_in);
   V* accout = reinterpret_cast<V*>(a.acc_out);
@@ -481,48 +501,109 @@ __device__ __forceinline__ void regpass_body(const RegPassArgs& a, const uint64_
   R c[RB];
 #pragma unroll
   for (int b = 0; b < RB; ++b) c[b] = (R)a.cb[b];
-  constexpr int VB = 8;
+  if constexpr (WB == 0) {
+    constexpr int VB = 8;
 #pragma unroll
-  for (int v0 = 0; v0 < NV; v0 += VB) {
-    V ain[VB];
+    for (int v0 = 0; v0 < NV; v0 += VB) {
+      V ain[VB];
 #pragma unroll
-    for (int u = 0; u < VB; ++u)
-      ain[u] = accin ? ldnt(accin + (ubase + ((uint64_t)(v0 + u) << hb)) + lane) : V{0, 0};
+      for (int u = 0; u < VB; ++u)
+        ain[u] = accin ? ldnt(accin + (ubase + ((uint64_t)(v0 + u) << hb)) + lane) : V{0, 0};
 #pragma unroll
-    for (int u = 0; u < VB; ++u) {
-      const int v = v0 + u;
-      R hr = 0, hi = 0;
+      for (int u = 0; u < VB; ++u) {
+        const int v = v0 + u;
+        R hr = 0, hi = 0;
 #pragma unroll
-      for (int b = 0; b < RB; ++b) {
-        hr += c[b] * x[v ^ (1 << b)].x;
-        hi += c[b] * x[v ^ (1 << b)].y;
+        for (int b = 0; b < RB; ++b) {
+          hr += c[b] * x[v ^ (1 << b)].x;
+          hi += c[b] * x[v ^ (1 << b)].y;
+        }
+        stnt(accout + (ubase + ((uint64_t)v << hb)) + lane, V{hr + ain[u].x, hi + ain[u].y});
       }
-      stnt(accout + (ubase + ((uint64_t)v << hb)) + lane, V{hr + ain[u].x, hi + ain[u].y});
+    }
+  } else {
+    constexpr int CV = sizeof(R) == 4 ? 4 : 2;   // vertices per exchange chunk
+    R cw[WB];
+#pragma unroll
+    for (int j = 0; j < WB; ++j) cw[j] = (R)a.cb[RB + j];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int v0 = 0; v0 < NV; v0 += CV) {
+      V* buf = ex + ((v0 / CV) & 1) * (CV * NT);
+#pragma unroll
+      for (int u = 0; u < CV; ++u) buf[u * NT + tid] = x[v0 + u];
+      V ain[CV];
+#pragma unroll
+      for (int u = 0; u < CV; ++u)
+        ain[u] = accin ? ldnt(accin + (ubase + ((uint64_t)(v0 + u) << hb)) + lane) : V{0, 0};
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < CV; ++u) {
+        const int v = v0 + u;
+        R hr = 0, hi = 0;
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+          hr += c[b] * x[v ^ (1 << b)].x;
+          hi += c[b] * x[v ^ (1 << b)].y;
+        }
+#pragma unroll
+        for (int j = 0; j < WB; ++j) {
+          const V p = buf[u * NT + (tid ^ (64 << j))];
+          hr += cw[j] * p.x;
+          hi += cw[j] * p.y;
+        }
+        stnt(accout + (ubase + ((uint64_t)v << hb)) + lane, V{hr + ain[u].x, hi + ain[u].y});
+      }
     }
   }
 }
 
-template <typename R, int RB>
-__global__ __launch_bounds__(256) void k_regpass(const RegPassArgs a) {
-  regpass_body<R, RB>(a, blockIdx.x);
+// LDS of the wide form: two chunk buffers of CV vertices for every thread
+template <typename R, int WB> struct RegLds {
+  static constexpr int CV = sizeof(R) == 4 ? 4 : 2;
+  static constexpr int count = WB == 0 ? 1 : 2 * CV * RegShape<WB>::threads;
+};
+
+template <typename R, int RB, int WB>
+__global__ __launch_bounds__(RegShape<WB>::threads) void k_regpass(const RegPassArgs a) {
+  __shared__ typename CT2<R>::V ex[RegLds<R, WB>::count];
+  regpass_body<R, RB, WB>(a, blockIdx.x, ex);
 }
 
-template <typename R, int RB>
-__global__ __launch_bounds__(256) void k_regpass_batch(const RegPassArgs* __restrict__ args,
-                                                       const int2* __restrict__ bmap) {
+template <typename R, int RB, int WB>
+__global__ __launch_bounds__(RegShape<WB>::threads) void k_regpass_batch(
+    const RegPassArgs* __restrict__ args, const int2* __restrict__ bmap) {
+  __shared__ typename CT2<R>::V ex[RegLds<R, WB>::count];
   const int2 m = bmap[blockIdx.x];
-  if (m.x < 0) return;
-  regpass_body<R, RB>(args[m.x], (uint64_t)m.y);
+  if (m.x < 0) return;   // uniform over the workgroup
+  regpass_body<R, RB, WB>(args[m.x], (uint64_t)m.y, ex);
 }
 
-hipError_t launch_regpass_batch(const RegPassArgs* args, const int2* bmap, int64_t nblocks, int dtype,
-                                hipStream_t s) {
-  if (dtype == 0)
-    hipLaunchKernelGGL((k_regpass_batch<float, kRegBitsC64>), dim3((unsigned)nblocks), dim3(256), 0, s,
-                       args, bmap);
-  else
-    hipLaunchKernelGGL((k_regpass_batch<double, kRegBitsC128>), dim3((unsigned)nblocks), dim3(256), 0,
-                       s, args, bmap);
+int64_t regpass_blocks(int n, int wb, int dtype) {
+  const int rb = dtype == 0 ? kRegBitsC64 : kRegBitsC128;
+  if (wb == 0) return (((int64_t)1 << (n - 6 - rb)) + 3) / 4;
+  return (int64_t)1 << (n - 6 - rb - wb);
+}
+
+hipError_t launch_regpass_batch(const RegPassArgs* args, const int2* bmap, int64_t nblocks, int wb,
+                                int dtype, hipStream_t s) {
+  const dim3 grid((unsigned)nblocks);
+  if (wb != 0 && wb != kWaveBits) return hipErrorInvalidValue;
+  if (dtype == 0) {
+    if (wb == 0)
+      hipLaunchKernelGGL((k_regpass_batch<float, kRegBitsC64, 0>), grid, dim3(RegShape<0>::threads), 0,
+                         s, args, bmap);
+    else
+      hipLaunchKernelGGL((k_regpass_batch<float, kRegBitsC64, kWaveBits>), grid,
+                         dim3(RegShape<kWaveBits>::threads), 0, s, args, bmap);
+  } else {
+    if (wb == 0)
+      hipLaunchKernelGGL((k_regpass_batch<double, kRegBitsC128, 0>), grid, dim3(RegShape<0>::threads),
+                         0, s, args, bmap);
+    else
+      hipLaunchKernelGGL((k_regpass_batch<double, kRegBitsC128, kWaveBits>), grid,
+                         dim3(RegShape<kWaveBits>::threads), 0, s, args, bmap);
+  }
   return hipGetLastError();
 }
 
@@ -541,11 +622,22 @@ hipError_t launch_pass_batch(const PassArgs* args, const int2* bmap, int64_t nbl
 }
 
 hipError_t launch_regpass(const RegPassArgs& a, int dtype, hipStream_t s) {
-  const int rb = dtype == 0 ? kRegBitsC64 : kRegBitsC128;
-  const int64_t nwaves = (int64_t)1 << (a.n - 6 - rb);
-  const unsigned blocks = (unsigned)((nwaves + 3) / 4);
-  if (dtype == 0) hipLaunchKernelGGL((k_regpass<float, kRegBitsC64>), dim3(blocks), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((k_regpass<double, kRegBitsC128>), dim3(blocks), dim3(256), 0, s, a);
+  const dim3 grid((unsigned)regpass_blocks(a.n, a.wb, dtype));
+  if (a.wb != 0 && a.wb != kWaveBits) return hipErrorInvalidValue;
+  if (dtype == 0) {
+    if (a.wb == 0)
+      hipLaunchKernelGGL((k_regpass<float, kRegBitsC64, 0>), grid, dim3(RegShape<0>::threads), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_regpass<float, kRegBitsC64, kWaveBits>), grid,
+                         dim3(RegShape<kWaveBits>::threads), 0, s, a);
+  } else {
+    if (a.wb == 0)
+      hipLaunchKernelGGL((k_regpass<double, kRegBitsC128, 0>), grid, dim3(RegShape<0>::threads), 0, s,
+                         a);
+    else
+      hipLaunchKernelGGL((k_regpass<double, kRegBitsC128, kWaveBits>), grid,
+                         dim3(RegShape<kWaveBits>::threads), 0, s, a);
+  }
   return hipGetLastError();
 }
 

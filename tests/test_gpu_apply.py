@@ -145,15 +145,18 @@ def test_errors_are_reported(eng):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-@pytest.mark.parametrize("regpass", ["1", "0"])
-def test_apply_register_hypercube_pass(eng, dt, regpass, monkeypatch):
-    """20 qubits: single-qubit flips above the last tile run in register
-    hypercube passes (or, switched off, in tile passes); pairs and Y/Z mixes
-    that straddle the tile stay in tile passes."""
+@pytest.mark.parametrize("regpass,n", [("1", 20), ("0", 20), ("2", 20), ("3", 20), ("3", 17),
+                                       ("3", 16)])
+def test_apply_register_hypercube_pass(eng, dt, regpass, n, monkeypatch):
+    """Single-qubit flips above the last tile run in register hypercube passes:
+    narrow (one wave per hypercube), wide (the waves of a workgroup span three
+    more bits and trade vertices through LDS), or, switched off, in tile
+    passes; pairs and Y/Z mixes that straddle the tile stay in tile passes.
+    n = 16 and 17 are the smallest states with wide passes (one and two
+    workgroups per pass)."""
     engine, ctx = eng
     monkeypatch.setenv("AQC_REGPASS", regpass)
-    rng = np.random.default_rng(2020)
-    n = 20
+    rng = np.random.default_rng(2020 + n)
     t = I.TermList(n)
     for q in range(1, n + 1):
         t.add({q: "X"}, rng.normal(), 0)

@@ -44,5 +44,7 @@ def test_set_tiling_rejects_bad_values():
         ham.set_tiling(torch.complex64, 15, 13, 4)
     with pytest.raises(_lib.AqcError):
         ham.set_tiling(torch.complex64, 13, 6, 6)
+    with pytest.raises(_lib.AqcError):
+        ham.set_tiling(torch.complex64, 13, 13, 4, 4)
     ham.free()
     ctx.close()

@@ -31,14 +31,23 @@ def _mix():
     return out
 
 
+DEFAULT_TILING = {"c64": (13, 13, 4), "c128": (12, 12, 3)}
+
+
 @pytest.mark.parametrize("dt", ["c64", "c128"])
-@pytest.mark.parametrize("graph", [True, False])
-def test_batch_equals_alone_bitwise(eng, dt, graph):
+@pytest.mark.parametrize("graph,reg", [(True, "auto"), (False, "auto"), (True, "mixed")])
+def test_batch_equals_alone_bitwise(eng, dt, graph, reg):
+    """reg = "mixed": the 16-qubit solve runs wide register passes and the
+    17-qubit one narrow ones, so one tick launches both kinds of levels."""
     engine, ctx = eng
     import torch
     tdt = torch.complex64 if dt == "c64" else torch.complex128
     mix = _mix()
     hams = [engine.Hamiltonian(ctx, inst) for inst, *_ in mix]
+    if reg == "mixed":
+        for j, (inst, *_r) in enumerate(mix):
+            if inst.n >= 16:
+                hams[j].set_tiling(tdt, *DEFAULT_TILING[dt], 3 if inst.n == 16 else 2)
     psi0 = [I.random_state(inst.n, np.random.default_rng(50 + j)) for j, (inst, *_r) in enumerate(mix)]
     alone = []
     for j, (inst, t0, t1, K, sh) in enumerate(mix):
