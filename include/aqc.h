@@ -129,15 +129,19 @@ aqc_status aqc_ham_info(const aqc_ham* ham, aqc_ham_info_t* out);
  * default and rebuilds the plan at the next use; synchronises the device).
  * tbf: bits of the last pass's contiguous tile (1..14 complex64, 1..13
  * complex128); tbh: bits of a high-pass tile; lh: its contiguous low bits
- * (1 <= lh < tbh); register_passes: how single-qubit flips above the last
+ * (1 <= lh < tbh).  options, bits 0-1: how single-qubit flips above the last
  * tile run: 0 in tile passes, 1 in register hypercube passes of the width the
  * library picks for n, 2 in narrow register passes (one wave per hypercube),
  * 3 in wide ones (eight waves of a workgroup span three more bits and trade
- * vertices through LDS).  EINVAL for values out of range,
+ * vertices through LDS); bit 2 (value 4): the other flip patterns above the
+ * tile are applied by the last pass, which reads their partners from the
+ * source vector (stream groups), instead of by tile high passes.  Stream
+ * groups add one vector to the evolve workspace (a second y^p buffer), so
+ * query the workspace size after this call.  EINVAL for values out of range,
  * ENOTSUP when some flip pattern does not fit the tiles (the old tiling stays).
  * Used by the autotuner.                                                     */
 aqc_status aqc_ham_set_tiling(aqc_ham* ham, int dtype, int tbf, int tbh, int lh,
-                              int register_passes);
+                              int options);
 
 /* Spectral enclosure [lo, hi] of H(t) on [t0, t1]: exact minimum and maximum of
  * each schedule's diagonal part (device reduction) combined with the triangle

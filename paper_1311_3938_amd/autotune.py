@@ -2,8 +2,9 @@
 
 For a Hamiltonian and a dtype it times H|psi> (aqc_apply, HIP events) under a
 set of candidate tilings (aqc_ham_set_tiling): the last pass's tile bits, the
-high-pass tile bits and contiguous low bits, and register hypercube passes
-(wide, narrow or none).  The fastest candidate is applied to the Hamiltonian and cached in a
+high-pass tile bits and contiguous low bits, register hypercube passes (wide,
+narrow or none), and whether the last pass applies the remaining high flips
+itself by reading their partners from memory (stream groups).  The fastest candidate is applied to the Hamiltonian and cached in a
 JSON file keyed by the GPU architecture, the dtype, n and the flip-group
 structure, so the search runs once per kind of problem.
 """
@@ -18,12 +19,18 @@ import torch
 from . import _lib as L
 from . import engine
 
-# register passes: 3 wide, 2 narrow, 0 none (flips in tile passes)
+# options: register passes 3 wide, 2 narrow, 0 none (flips in tile passes);
+# + 4: the remaining flips above the last tile as stream groups of the last
+# pass (then the high-pass tile shape does not matter, so it is not varied)
+def _candidates(tbfs, shapes):
+    out = [(tbf, tbh, lh, reg) for tbf in tbfs for (tbh, lh) in shapes for reg in (3, 2, 0)]
+    out += [(tbf, shapes[0][0], shapes[0][1], 4 | reg) for tbf in tbfs for reg in (3, 2, 0)]
+    return out
+
+
 CANDIDATES = {
-    L.C64: [(tbf, tbh, lh, reg) for tbf in (12, 13, 14) for (tbh, lh) in ((13, 4), (13, 5), (12, 4), (14, 6))
-            for reg in (3, 2, 0)],
-    L.C128: [(tbf, tbh, lh, reg) for tbf in (11, 12, 13) for (tbh, lh) in ((12, 3), (12, 4), (11, 3), (13, 5))
-             for reg in (3, 2, 0)],
+    L.C64: _candidates((12, 13, 14), ((13, 4), (13, 5), (12, 4), (14, 6))),
+    L.C128: _candidates((11, 12, 13), ((12, 3), (12, 4), (11, 3), (13, 5))),
 }
 
 _lock = threading.Lock()

@@ -225,6 +225,7 @@ struct Pass {
   int tb = 0, lbits = 0;
   uint64_t hmask = 0, cmask = 0;
   bool final_pass = false;
+  bool stream = false;       // last pass: some groups flip bits outside the tile
   std::vector<int> groups;   // indices into Ham::groups
   DevGroup* dgroups = nullptr;
   DevTerm* dterms = nullptr;
@@ -233,6 +234,7 @@ struct Pass {
 
 struct Plan {
   bool built = false;
+  bool has_stream = false;   // the last pass reads partners outside its tile
   int tbf = 0;               // last pass tile bits
   std::vector<Pass> passes;  // high passes first, last pass last
   // split diagonal tables for tile bits tbf
@@ -375,6 +377,9 @@ struct Tiling {
 
 // wide register passes when they give at least 2^this many workgroups
 constexpr int kWideMinLogBlocks = 8;
+// flip patterns above the last tile that no register pass takes are applied
+// by the last pass from memory (1) or by tile high passes (0)
+constexpr int kStreamDefault = 0;
 
 static Tiling default_tiling(int dtype) {
   // last pass: 2^13 (c64) / 2^12 (c128) amplitudes = 64 KiB of LDS, so two
@@ -523,11 +528,13 @@ static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& 
   tl.lh = env_int(dtype == 0 ? "AQC_LH_C64" : "AQC_LH_C128", tl.lh);
   int use_reg = env_int("AQC_REGPASS", 1);
   if (use_reg < 0 || use_reg > 3) use_reg = 1;
+  bool use_stream = env_int("AQC_STREAM", kStreamDefault) != 0;
   if (h->tiling_set[dtype]) {
     tl.tbf = h->tiling[dtype][0];
     tl.tbh = h->tiling[dtype][1];
     tl.lh = h->tiling[dtype][2];
-    use_reg = h->tiling[dtype][3];
+    use_reg = h->tiling[dtype][3] & 3;
+    use_stream = (h->tiling[dtype][3] & 4) != 0;
   }
   const int maxtb = dtype == 0 ? 14 : 13;
   if (tl.tbf < 1 || tl.tbf > maxtb || tl.tbh < 2 || tl.tbh > maxtb || tl.lh < 1 || tl.lh >= tl.tbh)
@@ -602,6 +609,22 @@ static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& 
     }
     rest.swap(keep);
   }
+  // stream groups: the remaining flip patterns are applied by the last pass,
+  // which reads their partners from the source vector directly
+  if (use_stream) {
+    std::vector<int> keep;
+    for (int gi : rest) {
+      const GroupH& g = h->groups[gi];
+      if ((int)last.groups.size() < kMaxPassGroups && lterms + (int)g.terms.size() <= kMaxPassTerms) {
+        last.groups.push_back(gi);
+        lterms += (int)g.terms.size();
+        last.stream = true;
+      } else {
+        keep.push_back(gi);
+      }
+    }
+    rest.swap(keep);
+  }
   std::sort(rest.begin(), rest.end(), [&](int a, int b) {
     const uint64_t xa = h->groups[a].x, xb = h->groups[b].x;
     const int ha = 63 - __builtin_clzll(xa), hb = 63 - __builtin_clzll(xb);
@@ -662,6 +685,8 @@ static aqc_status build_plan(aqc_ham* h, int dtype, hipStream_t s) {
   STCHK(layout_passes(h, dtype, passes, &tbf));
   p.tbf = tbf;
   p.passes = passes;
+  p.has_stream = false;
+  for (const Pass& ps : p.passes) p.has_stream = p.has_stream || ps.stream;
   for (Pass& ps : p.passes)
     if (ps.kind == 0) STCHK(build_pass_tables(ps, h, s));
   STCHK(build_diag_tables(p, h, s));
@@ -837,14 +862,14 @@ extern "C" aqc_status aqc_ham_info(const aqc_ham* h, aqc_ham_info_t* out) {
 }
 
 extern "C" aqc_status aqc_ham_set_tiling(aqc_ham* h, int dtype, int tbf, int tbh, int lh,
-                                         int register_passes) {
+                                         int options) {
   if (!h) return fail(AQC_EINVAL, "aqc_ham_set_tiling: ham is NULL");
   if (dtype != AQC_C64 && dtype != AQC_C128) return fail(AQC_ENOTSUP, "aqc_ham_set_tiling: dtype");
   const int maxtb = dtype == 0 ? 14 : 13;
   if (tbf < 1 || tbf > maxtb || tbh < 2 || tbh > maxtb || lh < 1 || lh >= tbh)
     return fail(AQC_EINVAL, "aqc_ham_set_tiling: tile bits out of range");
-  if (register_passes < 0 || register_passes > 3)
-    return fail(AQC_EINVAL, "aqc_ham_set_tiling: register_passes is 0..3");
+  if (options < 0 || options > 7)
+    return fail(AQC_EINVAL, "aqc_ham_set_tiling: options is 0..7");
   // check the layout before replacing the plan
   const bool old_set = h->tiling_set[dtype];
   int old[4];
@@ -853,7 +878,7 @@ extern "C" aqc_status aqc_ham_set_tiling(aqc_ham* h, int dtype, int tbf, int tbh
   h->tiling[dtype][0] = tbf;
   h->tiling[dtype][1] = tbh;
   h->tiling[dtype][2] = lh;
-  h->tiling[dtype][3] = register_passes;
+  h->tiling[dtype][3] = options;
   std::vector<Pass> passes;
   int tb_out = 0;
   const aqc_status st = layout_passes(h, dtype, passes, &tb_out);
@@ -871,16 +896,29 @@ extern "C" aqc_status aqc_ham_set_tiling(aqc_ham* h, int dtype, int tbf, int tbh
   return AQC_OK;
 }
 
+// Number of passes of the plan and whether its last pass has stream groups
+// (from the built plan, else from a layout computed on the host).
+static aqc_status plan_shape(const aqc_ham* h, int dtype, size_t* np, bool* stream) {
+  const Plan& p = h->plans[dtype];
+  if (p.built) {
+    *np = p.passes.size();
+    *stream = p.has_stream;
+    return AQC_OK;
+  }
+  std::vector<Pass> passes;
+  int tbf = 0;
+  STCHK(layout_passes(h, dtype, passes, &tbf));
+  *np = passes.size();
+  *stream = false;
+  for (const Pass& ps : passes) *stream = *stream || ps.stream;
+  return AQC_OK;
+}
+
 extern "C" size_t aqc_apply_workspace_bytes(const aqc_ham* h, int dtype) {
   if (!h || (dtype != 0 && dtype != 1)) return 0;
-  const Plan& p = h->plans[dtype];
-  size_t np = p.passes.size();
-  if (!p.built) {
-    std::vector<Pass> passes;
-    int tbf = 0;
-    if (layout_passes(h, dtype, passes, &tbf) != AQC_OK) return 0;
-    np = passes.size();
-  }
+  size_t np = 0;
+  bool stream = false;
+  if (plan_shape(h, dtype, &np, &stream) != AQC_OK) return 0;
   return np > 1 ? vec_bytes(h, dtype) : 0;
 }
 
@@ -1140,6 +1178,8 @@ constexpr double kMilne = 19.0 / 270.0;
 struct SolveVecs {
   void* y;       // the caller's state
   void* yp;      // y^p (pc4) or the RK4 stage input u
+  void* yp2;     // second y^p buffer when the last pass reads other tiles of
+                 // its source (stream groups), so no stage updates it in place
   void* B[4];    // f history (pc4, rotating); RK4 accumulator: B[3] (pc4 bootstrap) or B[0]
   void* hbuf;    // partial product of the high passes
   void* ycomp;   // complex64 compensated state: low part of y, or nullptr
@@ -1166,8 +1206,18 @@ struct SegStepper {
   int sub = 0;        // RK4 stage 0..3; 4 = evaluation at t_3 pending (pc4)
   int64_t k_end = 0;  // stop when k reaches this
   bool more_after = false;  // the segment continues after k_end
+  bool dbl = false;   // y^p alternates between yp and yp2
+  int ypc = 0;        // which buffer holds the current y^p
 
   bool rk_phase() const { return method == AQC_METHOD_RK4 || (k < 3 && sub < 4); }
+  void* yp_cur(const SolveVecs& v) const { return (dbl && ypc) ? v.yp2 : v.yp; }
+  void* yp_next(const SolveVecs& v) const { return dbl ? (ypc ? v.yp : v.yp2) : v.yp; }
+  // the stage next() describes reads y^p and writes its successor
+  bool swaps_yp() const {
+    if (rk_phase()) return sub == 1 || sub == 2;
+    if (sub == 4) return false;
+    return k + 1 < k_end || more_after;
+  }
 
   MatvecStage next(const SolveVecs& v) const {
     MatvecStage m;
@@ -1187,28 +1237,28 @@ struct SegStepper {
         e.out[0] = fk ? fk : acc;
         e.scale[0] = 1.0;
         e.bi[0] = -1.0;
-        e.out[1] = v.yp;
+        e.out[1] = yp_cur(v);
         e.cu[1] = 1.0;
         e.scale[1] = 0.5 * h;
         e.bi[1] = -1.0;
         e.comp_flags = lo_in << 1;
-      } else if (sub <= 2) {  // acc = acc_in + 2F, u = y + c h F (u in place)
+      } else if (sub <= 2) {  // acc = acc_in + 2F, u = y + c h F
         m.t = tk + 0.5 * h;
-        m.src = v.yp;
+        m.src = yp_cur(v);
         e.in[0] = v.y;
         e.in[1] = (sub == 1 && fk) ? fk : acc;
         e.out[0] = acc;
         e.scale[0] = 1.0;
         e.a[0][0] = 1.0;
         e.bi[0] = -2.0;
-        e.out[1] = v.yp;
+        e.out[1] = yp_next(v);
         e.c0[1] = 1.0;
         e.scale[1] = sub == 1 ? 0.5 * h : h;
         e.bi[1] = -1.0;
         e.comp_flags = lo_in << 1;
       } else {  // y = y + h/6 (acc + F)
         m.t = tk + h;
-        m.src = v.yp;
+        m.src = yp_cur(v);
         e.in[0] = v.y;
         e.in[1] = acc;
         e.out[0] = v.y;
@@ -1232,7 +1282,7 @@ struct SegStepper {
       e.in[1] = v.B[2];
       e.in[2] = v.B[1];
       e.in[3] = v.B[0];
-      e.out[1] = v.yp;
+      e.out[1] = yp_cur(v);
       e.c0[1] = 1.0;
       e.scale[1] = h / 24.0;
       e.a[1][0] = -59.0;
@@ -1245,7 +1295,7 @@ struct SegStepper {
     // predictor-corrector step k -> k+1: one H|psi> at t_{k+1} on y^p_{k+1}
     const double c = h / 24.0;
     m.t = ts + (double)(k + 1) * h;
-    m.src = v.yp;
+    m.src = yp_cur(v);
     m.ends_step = true;
     m.pc4 = true;
     e.in[0] = v.y;
@@ -1263,7 +1313,7 @@ struct SegStepper {
     e.scale[1] = 1.0;
     e.bi[1] = -1.0;
     if (k + 1 < k_end || more_after) {
-      e.out[2] = v.yp;  // y^p_{k+2} = y_k + h/24 (64 F - 40 f_k + 32 f_{k-1} - 8 f_{k-2})
+      e.out[2] = yp_next(v);  // y^p_{k+2} = y_k + h/24 (64 F - 40 f_k + 32 f_{k-1} - 8 f_{k-2})
       e.c0[2] = 1.0;
       e.scale[2] = c;
       e.a[2][0] = -40.0;
@@ -1276,6 +1326,7 @@ struct SegStepper {
   }
 
   void advance() {
+    if (dbl && swaps_yp()) ypc ^= 1;
     if (rk_phase()) {
       if (sub < 3) {
         ++sub;
@@ -1361,7 +1412,8 @@ struct Evolver {
 
 // Lay out the solve vectors in a workspace: y^p, four history vectors (pc4) or
 // one accumulator (rk4), the partial product when the plan has high passes,
-// and the low part of a compensated complex64 state.  Advances *w.
+// the second y^p buffer when the last pass has stream groups, and the low part
+// of a compensated complex64 state.  Advances *w.
 aqc_status carve_workspace(const aqc_ham* h, int dtype, int method, bool compensated, void* psi,
                            char** w, SolveVecs* v) {
   const size_t vb = vec_bytes(h, dtype);
@@ -1383,6 +1435,11 @@ aqc_status carve_workspace(const aqc_ham* h, int dtype, int method, bool compens
     v->hbuf = *w;
     *w += vb;
   }
+  v->yp2 = nullptr;
+  if (h->plans[dtype].has_stream) {
+    v->yp2 = *w;
+    *w += vb;
+  }
   v->ycomp = nullptr;
   if (dtype == AQC_C64 && compensated) {
     v->ycomp = *w;
@@ -1398,7 +1455,11 @@ extern "C" size_t aqc_evolve_workspace_bytes(const aqc_ham* h, int dtype, const 
   const size_t vb = vec_bytes(h, dtype);
   const int method = o ? o->method : AQC_METHOD_PC4;
   size_t nv = method == AQC_METHOD_RK4 ? 2 : 5;
-  if (aqc_apply_workspace_bytes(h, dtype) > 0) nv += 1;
+  size_t np = 0;
+  bool stream = false;
+  if (plan_shape(h, dtype, &np, &stream) != AQC_OK) return 0;
+  if (np > 1) nv += 1;
+  if (stream) nv += 1;
   const bool adaptive = o && o->n_steps == 0 && o->n_replay <= 0 && method == AQC_METHOD_PC4;
   const bool comp = dtype == AQC_C64 && (!o || o->compensated != 0);
   if (comp) nv += 1;
@@ -1486,6 +1547,7 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
     sg.method = o->method;
     sg.ts = ts;
     sg.h = hh;
+    sg.dbl = ev.v.yp2 != nullptr;
     return sg;
   };
   auto guard = [&](double hh) -> aqc_status {
@@ -1772,6 +1834,7 @@ extern "C" aqc_status aqc_batch_admit(aqc_batch* b, const aqc_ham* h, void* psi,
   sl.sg.h = (t1 - t0) / (double)n_steps;
   sl.sg.k_end = n_steps;
   sl.sg.more_after = false;
+  sl.sg.dbl = sl.v.yp2 != nullptr;
   sl.t0 = t0;
   sl.t1 = t1;
   sl.shift = shift;

@@ -5,8 +5,10 @@
 // vector u in LDS: `lbits` contiguous low bits (coalesced 16-byte loads) plus
 // the high bits in `hmask`.  Every flip pattern x whose bits all lie in the
 // tile is applied from LDS: (H u)[g] += c_x(g) u[g ^ x].  Flip patterns with
-// bits above the last pass's tile are handled by earlier passes whose tiles
-// include those bits; they write a partial product that the last pass reads.
+// bits above the last pass's tile are handled by earlier passes (register
+// hypercube passes for single-qubit flips, tile passes whose tiles include the
+// pattern's bits) that write a partial product the last pass reads, or by the
+// last pass itself reading the partner u[g ^ x] from memory (stream groups).
 // The last pass tiles the low tb bits contiguously, adds the diagonal from
 // split tables (popcount parity folded per tile), and fuses the integrator's
 // stage update (a fixed linear combination of H u with up to four streamed
@@ -260,8 +262,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
       }
     }
     gco[g] = (R)c;
-    // tile-local flip mask; bit 31 marks a group whose coefficient depends on g
-    gxl[g] = gr.xl | (gr.plain ? 0u : 0x80000000u);
+    // tile-local flip mask; bit 31 marks a group whose coefficient depends on
+    // g, bit 30 one whose partner lies outside the tile (read from memory)
+    gxl[g] = gr.xl | (gr.plain ? 0u : 0x80000000u) | ((gr.x & ~tmask) ? 0x40000000u : 0u);
   }
   for (int t = tid; t < a.nterms; t += kThreads) {
     const DevTerm tt = a.terms[t];
@@ -331,6 +334,43 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
     }
     for (int k = 0; k < a.ng; ++k) {
       const uint32_t gx = gxl[k];
+      if (gx & 0x40000000u) {
+        // partner outside the tile: a second coalesced stream of the source
+        // (the tiles of other workgroups, mostly served from cache)
+        const DevGroup gr = a.groups[k];
+        V pv[EB];
+#pragma unroll
+        for (int u = 0; u < EB; ++u) pv[u] = ok[u] ? src[gidx[u] ^ gr.x] : V{0, 0};
+        if (!(gx >> 31)) {
+          const R c = gco[k];
+#pragma unroll
+          for (int u = 0; u < EB; ++u) {
+            hr[u] += c * pv[u].x;
+            hi[u] += c * pv[u].y;
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < EB; ++u) {
+            if (!ok[u]) continue;
+            const uint64_t src_idx = gidx[u] ^ gr.x;
+            R cr = 0, ci = 0;
+            for (int t = 0; t < gr.nt; ++t) {
+              const DevTerm tt = a.terms[gr.t0 + t];
+              R m = tm[gr.t0 + t];
+              if (__popcll(src_idx & tt.z) & 1) m = -m;
+              switch (tt.p & 3) {
+                case 0: cr += m; break;
+                case 1: ci += m; break;
+                case 2: cr -= m; break;
+                default: ci -= m; break;
+              }
+            }
+            hr[u] += cr * pv[u].x - ci * pv[u].y;
+            hi[u] += cr * pv[u].y + ci * pv[u].x;
+          }
+        }
+        continue;
+      }
       if (!(gx >> 31)) {
         const R c = gco[k];
 #pragma unroll

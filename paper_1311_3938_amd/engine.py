@@ -91,11 +91,11 @@ class Hamiltonian:
                 "n_groups": i.n_groups, "n_passes": list(i.n_passes),
                 "tile_bits": list(i.tile_bits)}
 
-    def set_tiling(self, dtype, tbf, tbh, lh, register_passes=1):
-        """register_passes: 0 none, 1 library's choice, 2 narrow, 3 wide (True = 1)."""
+    def set_tiling(self, dtype, tbf, tbh, lh, options=1):
+        """options: register passes 0 none, 1 library's choice, 2 narrow, 3 wide
+        (True = 1), plus 4 for stream groups in the last pass."""
         dt = L.C64 if dtype in (torch.complex64, L.C64) else L.C128
-        check(lib().aqc_ham_set_tiling(self._h, dt, int(tbf), int(tbh), int(lh),
-                                       int(register_passes)))
+        check(lib().aqc_ham_set_tiling(self._h, dt, int(tbf), int(tbh), int(lh), int(options)))
 
     def spectral_bounds(self, t0, t1):
         lo, hi = C.c_double(), C.c_double()

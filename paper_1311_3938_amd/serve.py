@@ -179,9 +179,10 @@ class Server:
         return time.perf_counter() - self.t_start
 
     def request_bytes(self, n):
-        # the state plus the predictor-corrector workspace (7 vectors for
-        # complex64 with compensation and a partial product)
-        return 8 * state_bytes(n, self.dtype)
+        # the state plus the predictor-corrector workspace (at most 8 vectors:
+        # y^p and its second buffer, four history vectors, the partial
+        # product of the high passes and the compensation part)
+        return 9 * state_bytes(n, self.dtype)
 
     def reserve(self, b):
         with self._mem:

@@ -172,3 +172,36 @@ def test_apply_register_hypercube_pass(eng, dt, regpass, n, monkeypatch):
     got = to_host(engine.apply(ctx, ham, 0.37, to_dev(psi, dt)))
     assert rel_err(got, want) < APPLY_TOL[dt]
     ham.free()
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("regpass,n", [("1", 20), ("0", 20), ("0", 14), ("3", 17)])
+def test_apply_stream_groups(eng, dt, regpass, n, monkeypatch):
+    """Flip patterns above the last tile applied by the last pass itself, which
+    reads the partner amplitudes from the source vector: pairs straddling the
+    tile, pairs and triples above it, and Y/Z mixes whose coefficient depends
+    on the basis state; with register passes on, the single-qubit flips stay
+    in them."""
+    engine, ctx = eng
+    monkeypatch.setenv("AQC_STREAM", "1")
+    monkeypatch.setenv("AQC_REGPASS", regpass)
+    rng = np.random.default_rng(3030 + n)
+    t = I.TermList(n)
+    for q in range(1, n + 1):
+        t.add({q: "X"}, rng.normal(), 0)
+        t.add({q: "Z"}, rng.normal(), 1)
+    for _ in range(10):
+        i, j, k = sorted(int(v) + 1 for v in rng.choice(n, 3, replace=False))
+        t.add({i: "X", j: "X"}, rng.normal(), 2)
+        t.add({i: "Y", k: "Z"}, rng.normal(), 0)
+        t.add({j: "X", k: "Y"}, rng.normal(), 1)
+        t.add({i: "X", j: "Y", k: "X"}, rng.normal(), 2)
+    inst = t.instance([I.SCHED_ONE_MINUS_S, I.SCHED_S, I.SCHED_S_ONE_MINUS_S], I.linear_path(1.0))
+    ham = engine.Hamiltonian(ctx, inst)
+    psi = I.random_state(n, rng)
+    want = sqh.apply_h(inst, 0.61, psi)
+    got = to_host(engine.apply(ctx, ham, 0.61, to_dev(psi, dt)))
+    assert rel_err(got, want) < APPLY_TOL[dt]
+    if regpass == "0":
+        assert ham.info()["n_passes"][0 if dt == "c64" else 1] == 1
+    ham.free()

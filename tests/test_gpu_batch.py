@@ -37,17 +37,20 @@ DEFAULT_TILING = {"c64": (13, 13, 4), "c128": (12, 12, 3)}
 @pytest.mark.parametrize("dt", ["c64", "c128"])
 @pytest.mark.parametrize("graph,reg", [(True, "auto"), (False, "auto"), (True, "mixed")])
 def test_batch_equals_alone_bitwise(eng, dt, graph, reg):
-    """reg = "mixed": the 16-qubit solve runs wide register passes and the
-    17-qubit one narrow ones, so one tick launches both kinds of levels."""
+    """reg = "mixed": the 16-qubit solve runs wide register passes with stream
+    groups in its last pass, the 17-qubit one narrow register passes and tile
+    high passes, the 14-qubit one a single pass with stream groups only, so one
+    tick launches every kind of level and both y^p buffering schemes."""
     engine, ctx = eng
     import torch
     tdt = torch.complex64 if dt == "c64" else torch.complex128
     mix = _mix()
     hams = [engine.Hamiltonian(ctx, inst) for inst, *_ in mix]
     if reg == "mixed":
+        opts = {14: 4, 16: 3 | 4, 17: 2}
         for j, (inst, *_r) in enumerate(mix):
-            if inst.n >= 16:
-                hams[j].set_tiling(tdt, *DEFAULT_TILING[dt], 3 if inst.n == 16 else 2)
+            if inst.n in opts:
+                hams[j].set_tiling(tdt, *DEFAULT_TILING[dt], opts[inst.n])
     psi0 = [I.random_state(inst.n, np.random.default_rng(50 + j)) for j, (inst, *_r) in enumerate(mix)]
     alone = []
     for j, (inst, t0, t1, K, sh) in enumerate(mix):

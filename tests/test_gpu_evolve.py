@@ -71,12 +71,21 @@ def test_evolve_ec3_window_matches_oracle(eng, method, dt):
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 @pytest.mark.parametrize("method", ["pc4", "rk4"])
-def test_evolve_two_pass_catalyst_matches_oracle(eng, method, dt):
-    """15 qubits: the product needs a high-bit pass plus the last pass."""
+@pytest.mark.parametrize("plan", ["tile", "stream", "stream_only"])
+def test_evolve_two_pass_catalyst_matches_oracle(eng, method, dt, plan, monkeypatch):
+    """15 qubits: flips above the last tile run in a high-bit pass ("tile"), or
+    as stream groups of the last pass beside a register pass ("stream"), or
+    all as stream groups in a single pass ("stream_only"); the stream plans
+    alternate two y^p buffers, which every RK4 stage and pc4 step exercises."""
     engine, ctx = eng
+    if plan != "tile":
+        monkeypatch.setenv("AQC_STREAM", "1")
+    if plan == "stream_only":
+        monkeypatch.setenv("AQC_REGPASS", "0")
     K, t0, t1, shift = 60, 1.0, 1.6, 6.0
     inst, ham, psi, st = _run(engine, ctx, "cat_15", dt, method, K, t0, t1, shift)
-    assert ham.info()["n_passes"][0 if dt == "c64" else 1] >= 2
+    npass = ham.info()["n_passes"][0 if dt == "c64" else 1]
+    assert npass == 1 if plan == "stream_only" else npass >= 2
     ref = _oracle_fixed("cat_15", method, K, t0, t1, shift)
     err = np.linalg.norm(to_host(psi) - ref)
     assert err < TOL[dt], err
