@@ -345,6 +345,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / peak,
             "traffic": measured_traffic(args),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel": "k_pass<last> (diagonal + low flips + fused stage update)",
             "avg_launch_ms": last_ms / max(last_n, 1),
             "algorithmic_bytes_per_launch": last_bytes / max(last_n, 1),
