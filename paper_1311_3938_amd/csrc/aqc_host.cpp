@@ -1914,7 +1914,10 @@ static aqc_status batch_rebuild(aqc_batch* b) {
     off = (off + 255) & ~(size_t)255;
     if (L.map.size() >= (size_t)INT32_MAX) return fail(AQC_ENOTSUP, "batch too large");
     HIPCHK(hipMalloc(&L.dmap, L.map.size() * sizeof(int2)));
-    HIPCHK(hipMemcpy(L.dmap, L.map.data(), L.map.size() * sizeof(int2), hipMemcpyHostToDevice));
+    // ordered before the batch's launches; L.map outlives the copy (the next
+    // rebuild synchronises the stream first)
+    HIPCHK(hipMemcpyAsync(L.dmap, L.map.data(), L.map.size() * sizeof(int2), hipMemcpyHostToDevice,
+                          b->bs));
   }
   b->args_bytes = off;
   const size_t group_bytes = off * kBatchGroup;
@@ -1995,6 +1998,37 @@ static void batch_fill_args(aqc_batch* b, char* buf) {
   }
 }
 
+// The same work as a graph: a copy node, then one kernel node per level and
+// tick in launch order.  Built node by node rather than by stream capture,
+// so threads that drive other batches (or torch) need not pause meanwhile.
+static aqc_status batch_build_graph(aqc_batch* b, const char* hbuf, int G, hipGraphExec_t* out) {
+  hipGraph_t gr = nullptr;
+  HIPCHK(hipGraphCreate(&gr, 0));
+  struct Guard {
+    hipGraph_t g;
+    ~Guard() { hipGraphDestroy(g); }
+  } guard{gr};
+  hipGraphNode_t prev = nullptr, nd = nullptr;
+  HIPCHK(hipGraphAddMemcpyNode1D(&nd, gr, nullptr, 0, b->dargs, hbuf, b->args_bytes * (size_t)G,
+                                 hipMemcpyHostToDevice));
+  prev = nd;
+  for (int g = 0; g < G; ++g) {
+    const char* dbase = b->dargs + b->args_bytes * (size_t)g;
+    for (auto& L : b->levels) {
+      const int64_t nb = (int64_t)L.map.size();
+      if (is_reg_level(L.kind))
+        HIPCHK(add_regpass_batch_node(gr, &nd, prev, reinterpret_cast<const RegPassArgs*>(dbase + L.arg_off),
+                                      L.dmap, nb, L.kind == 3 ? kWaveBits : 0, b->dtype));
+      else
+        HIPCHK(add_pass_batch_node(gr, &nd, prev, reinterpret_cast<const PassArgs*>(dbase + L.arg_off), L.dmap,
+                                   nb, L.kind == 2 ? 1 : 0, L.max_tb, b->dtype));
+      prev = nd;
+    }
+  }
+  HIPCHK(hipGraphInstantiate(out, gr, nullptr, nullptr, 0));
+  return AQC_OK;
+}
+
 // Copy G ticks of arguments and launch every level of each tick in order.
 static aqc_status batch_launch_group(aqc_batch* b, hipStream_t s, const char* hbuf, int G) {
   HIPCHK(hipMemcpyAsync(b->dargs, hbuf, b->args_bytes * (size_t)G, hipMemcpyHostToDevice, s));
@@ -2046,15 +2080,8 @@ extern "C" aqc_status aqc_batch_step(aqc_batch* b, int ticks, int* n_active) {
       auto key = std::make_pair(c, (int)G);
       auto it = b->gexec.find(key);
       if (it == b->gexec.end()) {
-        hipGraph_t gr = nullptr;
         hipGraphExec_t ex = nullptr;
-        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        const aqc_status rc = batch_launch_group(b, s, b->hargs[c], (int)G);
-        const hipError_t ec = hipStreamEndCapture(s, &gr);
-        if (rc != AQC_OK) return rc;
-        HIPCHK(ec);
-        HIPCHK(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
-        HIPCHK(hipGraphDestroy(gr));
+        STCHK(batch_build_graph(b, b->hargs[c], (int)G, &ex));
         it = b->gexec.emplace(key, ex).first;
       }
       HIPCHK(hipGraphLaunch(it->second, s));

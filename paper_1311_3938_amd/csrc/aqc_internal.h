@@ -127,6 +127,13 @@ hipError_t launch_regpass_batch(const RegPassArgs* args, const int2* bmap, int64
 hipError_t launch_pass_batch(const PassArgs* args, const int2* bmap, int64_t nblocks, int final_pass,
                              int max_tb, int dtype, hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, int dtype, int64_t nblocks, hipStream_t s);
+// the batched launches as graph nodes after `dep` (nullptr: a root node)
+hipError_t add_regpass_batch_node(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep,
+                                  const RegPassArgs* args, const int2* bmap, int64_t nblocks, int wb,
+                                  int dtype);
+hipError_t add_pass_batch_node(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep,
+                               const PassArgs* args, const int2* bmap, int64_t nblocks, int final_pass,
+                               int max_tb, int dtype);
 size_t pass_lds_bytes(int tb, int dtype);
 hipError_t prepare_kernels();
 

@@ -104,7 +104,8 @@ struct Lds {
   static constexpr int kGco = kLB + 8 * 128;                     // R gco[kMaxPassGroups]
   static constexpr int kGxl = kGco + 8 * kMaxPassGroups;         // u32 gxl[kMaxPassGroups]
   static constexpr int kTm = kGxl + 4 * kMaxPassGroups;          // R tm[kMaxPassTerms]
-  static constexpr int kTile = kTm + 8 * kMaxPassTerms;          // V tile[2^tb]
+  static constexpr int kTmd = kTm + 8 * kMaxPassTerms;           // double tmd[kMaxPassTerms]
+  static constexpr int kTile = kTmd + 8 * kMaxPassTerms;         // V tile[2^tb]
 };
 
 size_t pass_lds_bytes(int tb, int dtype) {
@@ -219,65 +220,96 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
   R* tm = reinterpret_cast<R*>(smem + Lds::kTm);
   V* tile = reinterpret_cast<V*>(smem + Lds::kTile);
 
+  double* tmd = reinterpret_cast<double*>(smem + Lds::kTmd);
+  static_assert(kMaxPassGroups <= kThreads && kMaxPassTerms <= kThreads,
+                "one group and one term per thread in the set-up");
+
   const int tid = threadIdx.x;
   const int tb = a.tb;
   const uint32_t ntile = 1u << tb;
   const uint64_t lowmask = (1ull << a.lbits) - 1ull;
   const uint64_t tmask = lowmask | a.hmask;
   const uint64_t base = FINAL ? ((uint64_t)bid << tb) : pdep64((uint64_t)bid, a.cmask);
+  const uint32_t E = ntile >= (uint32_t)kThreads ? ntile / kThreads : 1u;
+  const uint64_t edep_tid = FINAL ? (uint64_t)tid : pdep64((uint64_t)tid, tmask);
+  const V* accin = reinterpret_cast<const V*>(a.acc_in);
+  V* accout = reinterpret_cast<V*>(a.acc_out);
 
-  // ---- 1. the tile: every 16-byte chunk is loaded before any LDS write ------
+  // ---- 1. every global read of the set-up is issued before the first wait:
+  // the tile (16-byte chunks), the high pass's partial product, the group and
+  // term descriptors and the diagonal's per-tile tables, so their latencies
+  // overlap instead of adding up
   constexpr int VEC = 16 / (int)sizeof(V);            // elements per chunk
   constexpr int LOGV = VEC == 2 ? 1 : 0;
+  // chunks per thread held in registers: all of a 2^14 complex64 tile, half of
+  // a 2^13 complex128 tile (the rest is loaded after the first commit)
+  constexpr int MAXC = sizeof(R) == 4 ? 16 : 8;
   const uint32_t nchunks = ntile / VEC;
+  const int cpt = (int)(nchunks / kThreads);          // 0: tile smaller than one chunk per thread
   const V* src = reinterpret_cast<const V*>(a.src);
   // local element l = q*VEC with q = tid + kThreads*j: the tid part and the j
   // part occupy disjoint bits of l, so their deposits can be OR-ed.
   const uint64_t dep_tid = FINAL ? ((uint64_t)tid << LOGV) : pdep64((uint64_t)tid << LOGV, tmask);
-  switch (nchunks / kThreads) {
-    case 16: load_tile<16, FINAL, V>(src, tile, base, dep_tid, tmask, LOGV); break;
-    case 8: load_tile<8, FINAL, V>(src, tile, base, dep_tid, tmask, LOGV); break;
-    case 4: load_tile<4, FINAL, V>(src, tile, base, dep_tid, tmask, LOGV); break;
-    case 2: load_tile<2, FINAL, V>(src, tile, base, dep_tid, tmask, LOGV); break;
-    case 1: load_tile<1, FINAL, V>(src, tile, base, dep_tid, tmask, LOGV); break;
-    default:
-      // tiles smaller than one chunk per thread
-      if ((uint32_t)tid < nchunks)
-        *reinterpret_cast<uint4*>(tile + tid * VEC) =
-            *reinterpret_cast<const uint4*>(src + (base | dep_tid));
-      break;
+  u32x4 tv[MAXC];
+#pragma unroll
+  for (int j = 0; j < MAXC; ++j) {
+    if (j < cpt) {
+      const uint64_t jpart = (uint64_t)(kThreads * j) << LOGV;
+      const uint64_t g = base | dep_tid | (FINAL ? jpart : pdep64(jpart, tmask));
+      tv[j] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src + g));
+    }
   }
+  if (cpt == 0 && (uint32_t)tid < nchunks) tv[0] = *reinterpret_cast<const u32x4*>(src + (base | dep_tid));
+  // high passes: the partial product of the first elements (half a block for
+  // complex128, to stay within the registers of two workgroups per CU)
+  constexpr int PF = FINAL ? 1 : (sizeof(R) == 4 ? 8 : 4);
+  V apf[PF];
+#pragma unroll
+  for (int j = 0; j < PF; ++j) {
+    apf[j] = V{0, 0};
+    if (!FINAL && accin && (uint32_t)j < E && tid + kThreads * j < ntile)
+      apf[j] = ldnt(accin + (base | edep_tid | pdep64((uint64_t)kThreads * j, tmask)));
+  }
+  const bool hasg = tid < a.ng, hast = tid < a.nterms;
+  DevGroup gr{};
+  DevTerm tt{};
+  if (hasg) gr = a.groups[tid];
+  if (hast) tt = a.terms[tid];
+  if (FINAL) diag_setup_a<R>(a, (uint64_t)bid, a.f, lin, cps);
 
-  // ---- 2. per-workgroup coefficients --------------------------------------
+  // ---- 2. the tile into LDS; per-workgroup coefficients --------------------
+#pragma unroll
+  for (int j = 0; j < MAXC; ++j)
+    if (j < cpt) *reinterpret_cast<u32x4*>(tile + (tid + kThreads * j) * VEC) = tv[j];
+  if (cpt == 0 && (uint32_t)tid < nchunks) *reinterpret_cast<u32x4*>(tile + tid * VEC) = tv[0];
+  for (int j = MAXC; j < cpt; ++j) {
+    const uint64_t jpart = (uint64_t)(kThreads * j) << LOGV;
+    const uint64_t g = base | dep_tid | (FINAL ? jpart : pdep64(jpart, tmask));
+    *reinterpret_cast<u32x4*>(tile + (tid + kThreads * j) * VEC) =
+        __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src + g));
+  }
   if (tid < kMaxSched) fsh[tid] = a.f[tid];
   __syncthreads();
-  if (FINAL) diag_setup_a<R>(a, (uint64_t)bid, fsh, lin, cps);
-  for (int g = tid; g < a.ng; g += kThreads) {
-    const DevGroup gr = a.groups[g];
-    double c = 0.0;
-    if (gr.plain) {
-      for (int t = 0; t < gr.nt; ++t) {
-        const DevTerm tt = a.terms[gr.t0 + t];
-        c += tt.w * fsh[tt.sid];
-      }
-    }
-    gco[g] = (R)c;
-    // tile-local flip mask; bit 31 marks a group whose coefficient depends on
-    // g, bit 30 one whose partner lies outside the tile (read from memory)
-    gxl[g] = gr.xl | (gr.plain ? 0u : 0x80000000u) | ((gr.x & ~tmask) ? 0x40000000u : 0u);
-  }
-  for (int t = tid; t < a.nterms; t += kThreads) {
-    const DevTerm tt = a.terms[t];
-    tm[t] = (R)(tt.w * fsh[tt.sid]);
+  if (hast) {
+    const double v = tt.w * fsh[tt.sid];
+    tmd[tid] = v;
+    tm[tid] = (R)v;
   }
   __syncthreads();
+  if (hasg) {
+    double c = 0.0;
+    if (gr.plain)
+      for (int t = 0; t < gr.nt; ++t) c += tmd[gr.t0 + t];
+    gco[tid] = (R)c;
+    // tile-local flip mask; bit 31 marks a group whose coefficient depends on
+    // g, bit 30 one whose partner lies outside the tile (read from memory)
+    gxl[tid] = gr.xl | (gr.plain ? 0u : 0x80000000u) | ((gr.x & ~tmask) ? 0x40000000u : 0u);
+  }
   if (FINAL) diag_setup_b<R>(a, lin, LA, LB);
   __syncthreads();
 
   // ---- 3. products and epilogue --------------------------------------------
   const R cprime = FINAL ? (R)cps[0] : (R)0;
-  const V* accin = reinterpret_cast<const V*>(a.acc_in);
-  V* accout = reinterpret_cast<V*>(a.acc_out);
   const EpiDesc& e = a.epi;
   R c0[3], cu[3], ca[3][3], br[3], bi[3], sh[3], sl[3];
 #pragma unroll
@@ -294,14 +326,19 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
   const bool has_comp = FINAL && e.comp != nullptr;
   V* compv = reinterpret_cast<V*>(e.comp);
   double r0 = 0.0, r1 = 0.0, r2 = 0.0;
-  const uint32_t E = ntile >= (uint32_t)kThreads ? ntile / kThreads : 1u;
-  const uint64_t edep_tid = FINAL ? (uint64_t)tid : pdep64((uint64_t)tid, tmask);
   // Elements are processed in blocks of EB: H u for the whole block is kept in
   // registers while the flip groups are walked once (group-outer order), then
   // the stage update streams the block's other vectors in batches of U.
+  // High passes (E <= 32) unroll their NJB blocks so the prefetched partial
+  // product is indexed at compile time.
   constexpr int EB = FINAL ? 4 : 8;
+  constexpr int NJB = FINAL ? 1 : 4;
   constexpr int U = sizeof(R) == 4 ? 4 : 2;
-  for (uint32_t jb = 0; jb < E; jb += EB) {
+  for (uint32_t jb0 = 0; jb0 < E; jb0 += EB * NJB) {
+#pragma unroll
+  for (int qb = 0; qb < NJB; ++qb) {
+    const uint32_t jb = jb0 + qb * EB;
+    if (jb >= E) break;
     R hr[EB], hi[EB];
     V uv[EB];
     uint64_t gidx[EB];
@@ -317,7 +354,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
       hr[u] = 0;
       hi[u] = 0;
       if (!FINAL && ok[u] && accin) {
-        const V av = ldnt(accin + gidx[u]);
+        // jb0 == 0 whenever E <= EB * NJB, so qb * EB + u is the element index
+        const int jc = qb * EB + u;
+        const V av = (jc < PF && jb0 == 0) ? apf[jc < PF ? jc : 0] : ldnt(accin + gidx[u]);
         hr[u] = av.x;
         hi[u] = av.y;
       }
@@ -474,6 +513,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
         if (e.red_flags & 4) r2 += (double)uv[q].x * (double)hrr + (double)uv[q].y * (double)hii;
       }
     }
+  }
   }
   if (FINAL && e.red_flags) block_reduce3<kThreads>(r0, r1, r2, e.red_flags, rbuf, e.red, nblocks, bid);
 }
@@ -659,6 +699,51 @@ hipError_t launch_pass_batch(const PassArgs* args, const int2* bmap, int64_t nbl
     else hipLaunchKernelGGL((k_pass_batch<double, false>), grid, block, lds, s, args, bmap);
   }
   return hipGetLastError();
+}
+
+// Graph nodes of the batched kernels (graphs are built node by node, not by
+// stream capture, so other threads may use the device meanwhile).
+static hipError_t add_kernel_node(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep,
+                                  const void* fn, dim3 grid, dim3 block, size_t lds, void** params) {
+  hipKernelNodeParams p{};
+  p.func = const_cast<void*>(fn);
+  p.gridDim = grid;
+  p.blockDim = block;
+  p.sharedMemBytes = (unsigned int)lds;
+  p.kernelParams = params;
+  p.extra = nullptr;
+  return hipGraphAddKernelNode(node, g, dep ? &dep : nullptr, dep ? 1 : 0, &p);
+}
+
+hipError_t add_regpass_batch_node(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep,
+                                  const RegPassArgs* args, const int2* bmap, int64_t nblocks, int wb,
+                                  int dtype) {
+  if (wb != 0 && wb != kWaveBits) return hipErrorInvalidValue;
+  void* prm[] = {(void*)&args, (void*)&bmap};
+  const void* fn;
+  if (dtype == 0)
+    fn = wb ? reinterpret_cast<const void*>(&k_regpass_batch<float, kRegBitsC64, kWaveBits>)
+            : reinterpret_cast<const void*>(&k_regpass_batch<float, kRegBitsC64, 0>);
+  else
+    fn = wb ? reinterpret_cast<const void*>(&k_regpass_batch<double, kRegBitsC128, kWaveBits>)
+            : reinterpret_cast<const void*>(&k_regpass_batch<double, kRegBitsC128, 0>);
+  const int threads = wb ? RegShape<kWaveBits>::threads : RegShape<0>::threads;
+  return add_kernel_node(g, node, dep, fn, dim3((unsigned)nblocks), dim3(threads), 0, prm);
+}
+
+hipError_t add_pass_batch_node(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep,
+                               const PassArgs* args, const int2* bmap, int64_t nblocks, int final_pass,
+                               int max_tb, int dtype) {
+  void* prm[] = {(void*)&args, (void*)&bmap};
+  const void* fn;
+  if (dtype == 0)
+    fn = final_pass ? reinterpret_cast<const void*>(&k_pass_batch<float, true>)
+                    : reinterpret_cast<const void*>(&k_pass_batch<float, false>);
+  else
+    fn = final_pass ? reinterpret_cast<const void*>(&k_pass_batch<double, true>)
+                    : reinterpret_cast<const void*>(&k_pass_batch<double, false>);
+  return add_kernel_node(g, node, dep, fn, dim3((unsigned)nblocks), dim3(kThreads),
+                         pass_lds_bytes(max_tb, dtype), prm);
 }
 
 hipError_t launch_regpass(const RegPassArgs& a, int dtype, hipStream_t s) {

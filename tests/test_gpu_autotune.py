@@ -45,6 +45,8 @@ def test_set_tiling_rejects_bad_values():
     with pytest.raises(_lib.AqcError):
         ham.set_tiling(torch.complex64, 13, 6, 6)
     with pytest.raises(_lib.AqcError):
-        ham.set_tiling(torch.complex64, 13, 13, 4, 4)
+        ham.set_tiling(torch.complex64, 13, 13, 4, 8)
+    with pytest.raises(_lib.AqcError):
+        ham.set_tiling(torch.complex64, 13, 13, 4, -1)
     ham.free()
     ctx.close()
