@@ -87,8 +87,9 @@ def error_summary(dFs, reqs, res):
     and the largest ones with their size and step count."""
     order = sorted(range(len(dFs)), key=lambda i: -dFs[i])
     return {"n": len(dFs), "above_1e-6": sum(d > 1e-6 for d in dFs),
+            "max_steps": max(r.steps for r in res[:len(dFs)]),
             "worst": [{"rid": reqs[i].rid, "n": reqs[i].n, "steps": res[i].steps, "T": reqs[i].T,
-                       "dF": dFs[i]} for i in order[:5]]}
+                       "dF": dFs[i]} for i in order[:8]]}
 
 
 def run_batch_mode(args):

@@ -24,7 +24,9 @@ scheme out; the reading used here (and by the library) is:
     taken in windows of W steps; after each window the largest estimate decides:
     above ``atol`` the window is undone and the segment restarts from the
     window's first state with h/2; below atol/64 (after at least two windows at
-    this h) the next segment starts with 2h.  The step is never halved below
+    this h) the next segment starts with 2h.  An atol below the rounding floor
+    of the estimate is refused (the estimate of a tiny step is pure rounding,
+    or exactly zero, and the controller would creep along at that step).  The step is never halved below
     max(hmin, 1e-12 (t1 - t0)) and at most 60 windows in a row are undone: an
     estimate that stays above atol ends the run with an error.  Every restart re-runs the RK4
     bootstrap, since the multistep history needs equal spacing.  The last
@@ -146,12 +148,21 @@ def evolve_segments(ham, psi0, t0, t1, segments, shift=0.0, counter=None):
 
 
 def evolve_adaptive(ham, psi0, t0, t1, atol, h0, hmin=0.0, hmax=math.inf, window=8,
-                    shift=0.0, max_steps=10_000_000):
+                    shift=0.0, max_steps=10_000_000, unit_roundoff=2.0 ** -53):
     """Adaptive pc4 as described in the module docstring.
+
+    ``unit_roundoff`` is that of the arithmetic the estimate is formed in: the
+    estimate cannot resolve errors below floor = 4 (19/270) u ||psi0||, so an
+    atol below the floor is refused, and the step only grows when the estimate
+    is below max(atol/64, 8 floor).
 
     Returns (psi(t1), segments, counter); ``segments`` is the accepted
     (t_start, h, n_steps) list that ``evolve_segments`` replays.
     """
+    floor = 4.0 * MILNE * unit_roundoff * float(np.linalg.norm(psi0))
+    if atol < floor:
+        raise ValueError(f"atol {atol:g} below the precision floor {floor:g} of the estimate")
+    grow_below = max(atol / 64.0, 8.0 * floor)
     cnt = Counter()
     segments = []
     h = min(h0, hmax)
@@ -201,7 +212,7 @@ def evolve_adaptive(ham, psi0, t0, t1, atol, h0, hmin=0.0, hmax=math.inf, window
             break
         if cnt.steps > max_steps:
             raise RuntimeError("adaptive step limit reached")
-        if emax < atol / 64.0 and windows_at_h >= 2 and 2.0 * seg.h <= hmax:
+        if emax < grow_below and windows_at_h >= 2 and 2.0 * seg.h <= hmax:
             segments.append((seg.t_s, seg.h, seg.k))
             seg = Segment(ham, seg.y, seg.t(seg.k), 2.0 * seg.h, "pc4", shift, cnt)
             windows_at_h = 0

@@ -1595,6 +1595,21 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
     // of shrinking the step without bound
     const double h_floor = std::max(o->hmin, 1e-12 * (t1 - t0));
     int rejections_in_row = 0;
+    // the estimate of a step is formed from y^p and the new y in the state's
+    // precision, so it cannot resolve errors below this floor; a tiny step's
+    // estimate is pure rounding (or exactly zero) and the controller would
+    // creep along at that step, so an atol below the floor is refused, and the
+    // step only grows when the estimate is clearly above the floor
+    const double unit = dtype == AQC_C64 ? 0x1p-24 : 0x1p-53;
+    const double est_floor = 4.0 * kMilne * unit * std::sqrt(stats->norm2_initial);
+    if (o->atol < est_floor) {
+      char buf[200];
+      snprintf(buf, sizeof buf,
+               "adaptive step: atol %.3g is below the precision floor %.3g of the error estimate "
+               "for this dtype", o->atol, est_floor);
+      return fail(AQC_EUNSTABLE, buf);
+    }
+    const double grow_below = std::max(o->atol / 64.0, 8.0 * est_floor);
     while (rc == AQC_OK) {
       const double t_now = sg.ts + (double)sg.k * sg.h;
       const double left = t1 - t_now;
@@ -1655,7 +1670,7 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
         stats->h_last = sg.h;
         break;
       }
-      if (emax < o->atol / 64.0 && windows_at_h >= 2 && 2.0 * sg.h <= hmax) {
+      if (emax < grow_below && windows_at_h >= 2 && 2.0 * sg.h <= hmax) {
         record(sg);
         sg = new_seg(sg.ts + (double)sg.k * sg.h, 2.0 * sg.h);
         windows_at_h = 0;

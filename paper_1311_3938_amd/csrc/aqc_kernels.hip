@@ -15,6 +15,7 @@
 // vectors and u itself).
 #include <hip/hip_runtime.h>
 
+
 #include "aqc_internal.h"
 
 namespace aqc {
@@ -99,8 +100,8 @@ struct Lds {
   static constexpr int kLin = kF + 8 * kMaxSched;                // double lin[16]
   static constexpr int kC = kLin + 8 * 16;                       // double C'
   static constexpr int kRed = kC + 16;                           // double [3][NW]
-  static constexpr int kLA = kRed + 8 * 3 * (kThreads / 64);     // R LA[128]
-  static constexpr int kLB = kLA + 8 * 128;                      // R LB[128]
+  static constexpr int kLA = kRed + 8 * 3 * (kThreads / 64);     // double LA[128]
+  static constexpr int kLB = kLA + 8 * 128;                      // double LB[128]
   static constexpr int kGco = kLB + 8 * 128;                     // R gco[kMaxPassGroups]
   static constexpr int kGxl = kGco + 8 * kMaxPassGroups;         // u32 gxl[kMaxPassGroups]
   static constexpr int kTm = kGxl + 4 * kMaxPassGroups;          // R tm[kMaxPassTerms]
@@ -139,8 +140,7 @@ __device__ __forceinline__ void diag_setup_a(const PassArgs& a, uint64_t hi, con
   }
 }
 
-template <typename R>
-__device__ __forceinline__ void diag_setup_b(const PassArgs& a, const double* lin, R* LA, R* LB) {
+__device__ __forceinline__ void diag_setup_b(const PassArgs& a, const double* lin, double* LA, double* LB) {
   const int tid = threadIdx.x;
   const int tb = a.tb;
   const int na = tb < 7 ? tb : 7;
@@ -150,59 +150,36 @@ __device__ __forceinline__ void diag_setup_b(const PassArgs& a, const double* li
     if (tid < (1 << na)) {
       for (int i = 0; i < na; ++i) v += ((tid >> i) & 1) ? -lin[i] : lin[i];
     }
-    LA[tid] = (R)v;
+    LA[tid] = v;
   } else if (tid < 256) {
     const int b = tid - 128;
     double v = 0.0;
     if (b < (1 << nb)) {
       for (int i = 0; i < nb; ++i) v += ((b >> i) & 1) ? -lin[7 + i] : lin[7 + i];
     }
-    LB[b] = (R)v;
+    LB[b] = v;
   }
 }
 
-// Diagonal energy of the tile element with low bits lo and global index g.
-template <typename R>
-__device__ __forceinline__ R diag_value(const PassArgs& a, uint32_t lo, uint64_t g, R cprime,
-                                        const R* LA, const R* LB, const double* fsh) {
-  R d = cprime + LA[lo & 127u] + LB[lo >> 7];
+// Diagonal energy of the tile element with low bits lo and global index g,
+// always in float64 (a handful of adds per amplitude): the per-tile constant
+// and the sign tables nearly cancel for a centred shift, so summing them in
+// float32 would put a rounding error of the size of the spectrum into every
+// diagonal value.
+__device__ __forceinline__ double diag_value(const PassArgs& a, uint32_t lo, uint64_t g, double cprime,
+                                             const double* LA, const double* LB, const double* fsh) {
+  double d = cprime + LA[lo & 127u] + LB[lo >> 7];
   const int64_t ntile = (int64_t)1 << a.tb;
 #pragma unroll
   for (int s = 0; s < kMaxTabSched; ++s) {
-    if (s < a.dg.ntab) {
-      // the product is formed in float64 and rounded once, so the float32
-      // kernel carries no fixed rounding of the table entries
-      d += (R)(fsh[a.dg.tab_sid[s]] * a.dg.TAB64[(int64_t)s * ntile + lo]);
-    }
+    if (s < a.dg.ntab) d += fsh[a.dg.tab_sid[s]] * a.dg.TAB64[(int64_t)s * ntile + lo];
   }
   for (int k = 0; k < a.dg.nres; ++k) {
     const DevTerm t = a.dg.res[k];
-    const R m = (R)(t.w * fsh[t.sid]);
+    const double m = t.w * fsh[t.sid];
     d += (__popcll(g & t.z) & 1) ? -m : m;
   }
   return d;
-}
-
-// Load CPT 16-byte chunks per thread of a tile into LDS: chunk q = tid +
-// kThreads*j holds local elements q*VEC ...; all loads are issued before the
-// first LDS write so their latencies overlap.
-template <int CPT, bool FINAL, typename V>
-__device__ __forceinline__ void load_tile(const V* src, V* tile, uint64_t base, uint64_t dep_tid,
-                                          uint64_t tmask, int logv) {
-  constexpr int VEC = 16 / (int)sizeof(V);
-  uint64_t g[CPT];
-#pragma unroll
-  for (int j = 0; j < CPT; ++j) {
-    const uint64_t jpart = (uint64_t)(kThreads * j) << logv;
-    g[j] = base | dep_tid | (FINAL ? jpart : pdep64(jpart, tmask));
-  }
-  u32x4 v[CPT];
-#pragma unroll
-  for (int j = 0; j < CPT; ++j)
-    v[j] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src + g[j]));
-#pragma unroll
-  for (int j = 0; j < CPT; ++j)
-    *reinterpret_cast<u32x4*>(tile + (threadIdx.x + kThreads * j) * VEC) = v[j];
 }
 
 template <typename R, bool FINAL>
@@ -213,8 +190,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
   double* lin = reinterpret_cast<double*>(smem + Lds::kLin);
   double* cps = reinterpret_cast<double*>(smem + Lds::kC);
   double* rbuf = reinterpret_cast<double*>(smem + Lds::kRed);
-  R* LA = reinterpret_cast<R*>(smem + Lds::kLA);
-  R* LB = reinterpret_cast<R*>(smem + Lds::kLB);
+  double* LA = reinterpret_cast<double*>(smem + Lds::kLA);
+  double* LB = reinterpret_cast<double*>(smem + Lds::kLB);
   R* gco = reinterpret_cast<R*>(smem + Lds::kGco);
   uint32_t* gxl = reinterpret_cast<uint32_t*>(smem + Lds::kGxl);
   R* tm = reinterpret_cast<R*>(smem + Lds::kTm);
@@ -305,24 +282,12 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
     // g, bit 30 one whose partner lies outside the tile (read from memory)
     gxl[tid] = gr.xl | (gr.plain ? 0u : 0x80000000u) | ((gr.x & ~tmask) ? 0x40000000u : 0u);
   }
-  if (FINAL) diag_setup_b<R>(a, lin, LA, LB);
+  if (FINAL) diag_setup_b(a, lin, LA, LB);
   __syncthreads();
 
   // ---- 3. products and epilogue --------------------------------------------
-  const R cprime = FINAL ? (R)cps[0] : (R)0;
+  const double cprime = FINAL ? cps[0] : 0.0;
   const EpiDesc& e = a.epi;
-  R c0[3], cu[3], ca[3][3], br[3], bi[3], sh[3], sl[3];
-#pragma unroll
-  for (int o = 0; o < 3; ++o) {
-    c0[o] = (R)e.c0[o];
-    cu[o] = (R)e.cu[o];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) ca[o][i] = (R)e.a[o][i];
-    br[o] = (R)e.br[o];
-    bi[o] = (R)e.bi[o];
-    sh[o] = (R)e.scale[o];
-    sl[o] = (R)(e.scale[o] - (double)sh[o]);   // zero in float64 kernels
-  }
   const bool has_comp = FINAL && e.comp != nullptr;
   V* compv = reinterpret_cast<V*>(e.comp);
   double r0 = 0.0, r1 = 0.0, r2 = 0.0;
@@ -333,42 +298,52 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
   // product is indexed at compile time.
   constexpr int EB = FINAL ? 4 : 8;
   constexpr int NJB = FINAL ? 1 : 4;
+  // elements per batch of the stage update (streamed loads in flight)
   constexpr int U = sizeof(R) == 4 ? 4 : 2;
   for (uint32_t jb0 = 0; jb0 < E; jb0 += EB * NJB) {
 #pragma unroll
   for (int qb = 0; qb < NJB; ++qb) {
     const uint32_t jb = jb0 + qb * EB;
     if (jb >= E) break;
+    // complex64: hr/hi sum the flip groups only; their terms are small next
+    // to the diagonal term, which the last pass adds in float64 at the end, so
+    // the float32 partial sums never carry the diagonal's magnitude.
+    // complex128 starts the sums with the diagonal term.
+    constexpr bool kDiagLate = sizeof(R) == 4;
+    // element u of the block: tile index tid + kThreads (jb + u); its global
+    // index and tile value are recomputed / re-read from LDS where needed
+    // rather than held in registers
+    auto gidx_of = [&](int u) -> uint64_t {
+      const uint64_t jpart = (uint64_t)kThreads * (jb + u);
+      return base | edep_tid | (FINAL ? jpart : pdep64(jpart, tmask));
+    };
+    auto tile_of = [&](int u) -> V { return tile[tid + kThreads * (jb + u)]; };
     R hr[EB], hi[EB];
-    V uv[EB];
-    uint64_t gidx[EB];
     bool ok[EB];
 #pragma unroll
     for (int u = 0; u < EB; ++u) {
       const uint32_t j = jb + u;
       const uint32_t l = tid + kThreads * j;
       ok[u] = (j < E) && (l < ntile);
-      const uint64_t jpart = (uint64_t)kThreads * j;
-      gidx[u] = base | edep_tid | (FINAL ? jpart : pdep64(jpart, tmask));
-      uv[u] = ok[u] ? tile[l] : V{0, 0};
       hr[u] = 0;
       hi[u] = 0;
       if (!FINAL && ok[u] && accin) {
         // jb0 == 0 whenever E <= EB * NJB, so qb * EB + u is the element index
         const int jc = qb * EB + u;
-        const V av = (jc < PF && jb0 == 0) ? apf[jc < PF ? jc : 0] : ldnt(accin + gidx[u]);
+        const V av = (jc < PF && jb0 == 0) ? apf[jc < PF ? jc : 0] : ldnt(accin + gidx_of(u));
         hr[u] = av.x;
         hi[u] = av.y;
       }
     }
-    if (FINAL) {
+    if (FINAL && !kDiagLate) {
 #pragma unroll
       for (int u = 0; u < EB; ++u) {
         if (!ok[u]) continue;
         const uint32_t l = tid + kThreads * (jb + u);
-        const R d = diag_value<R>(a, l, gidx[u], cprime, LA, LB, fsh);
-        hr[u] = d * uv[u].x;
-        hi[u] = d * uv[u].y;
+        const double d = diag_value(a, l, gidx_of(u), cprime, LA, LB, fsh);
+        const V uu = tile_of(u);
+        hr[u] = (R)(d * (double)uu.x);
+        hi[u] = (R)(d * (double)uu.y);
       }
     }
     for (int k = 0; k < a.ng; ++k) {
@@ -379,7 +354,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
         const DevGroup gr = a.groups[k];
         V pv[EB];
 #pragma unroll
-        for (int u = 0; u < EB; ++u) pv[u] = ok[u] ? src[gidx[u] ^ gr.x] : V{0, 0};
+        for (int u = 0; u < EB; ++u) pv[u] = ok[u] ? src[gidx_of(u) ^ gr.x] : V{0, 0};
         if (!(gx >> 31)) {
           const R c = gco[k];
 #pragma unroll
@@ -391,7 +366,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
 #pragma unroll
           for (int u = 0; u < EB; ++u) {
             if (!ok[u]) continue;
-            const uint64_t src_idx = gidx[u] ^ gr.x;
+            const uint64_t src_idx = gidx_of(u) ^ gr.x;
             R cr = 0, ci = 0;
             for (int t = 0; t < gr.nt; ++t) {
               const DevTerm tt = a.terms[gr.t0 + t];
@@ -426,7 +401,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
         for (int u = 0; u < EB; ++u) {
           if (!ok[u]) continue;
           const uint32_t l = tid + kThreads * (jb + u);
-          const uint64_t src_idx = gidx[u] ^ gr.x;
+          const uint64_t src_idx = gidx_of(u) ^ gr.x;
           R cr = 0, ci = 0;
           for (int t = 0; t < gr.nt; ++t) {
             const DevTerm tt = a.terms[gr.t0 + t];
@@ -448,7 +423,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
     if (!FINAL) {
 #pragma unroll
       for (int u = 0; u < EB; ++u)
-        if (ok[u]) stnt(accout + gidx[u], V{hr[u], hi[u]});
+        if (ok[u]) stnt(accout + gidx_of(u), V{hr[u], hi[u]});
       continue;
     }
 #pragma unroll
@@ -462,37 +437,48 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
 #pragma unroll
         for (int i = 0; i < 4; ++i) xin[u][i] = V{0, 0};
         if (!ok[q]) continue;
-        if (accin) ain[u] = ldnt(accin + gidx[q]);
+        const uint64_t gq = gidx_of(q);
+        if (accin) ain[u] = ldnt(accin + gq);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          if (e.in[i]) xin[u][i] = ldnt(reinterpret_cast<const V*>(e.in[i]) + gidx[q]);
-        if (has_comp) lo[u] = ldnt(compv + gidx[q]);
+          if (e.in[i]) xin[u][i] = ldnt(reinterpret_cast<const V*>(e.in[i]) + gq);
+        if (has_comp) lo[u] = ldnt(compv + gq);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int q = u0 + u;
         if (!ok[q]) continue;
-        const uint64_t g = gidx[q];
-        const R hrr = hr[q] + ain[u].x, hii = hi[q] + ain[u].y;
+        const uint64_t g = gidx_of(q);
+        const V uq = tile_of(q);
+        // H u = diagonal term + flip sum + partial product of the high passes,
+        // the (large) diagonal term added in float64 with one rounding
+        R hrr = hr[q] + ain[u].x, hii = hi[q] + ain[u].y;
+        if (kDiagLate) {
+          const uint32_t l = tid + kThreads * (jb + q);
+          const double d = diag_value(a, l, g, cprime, LA, LB, fsh);
+          hrr = (R)(d * (double)uq.x + (double)hrr);
+          hii = (R)(d * (double)uq.y + (double)hii);
+        }
 #pragma unroll
         for (int o = 0; o < 3; ++o) {
           if (!e.out[o]) continue;
-          // increment: scale * (sum a x + b Hv), scale as a float-float pair
-          R ir = br[o] * hrr - bi[o] * hii;
-          R ii = br[o] * hii + bi[o] * hrr;
+          R ir = (R)e.br[o] * hrr - (R)e.bi[o] * hii;
+          R ii = (R)e.br[o] * hii + (R)e.bi[o] * hrr;
 #pragma unroll
           for (int i = 0; i < 3; ++i) {
-            ir += ca[o][i] * xin[u][i + 1].x;
-            ii += ca[o][i] * xin[u][i + 1].y;
+            ir += (R)e.a[o][i] * xin[u][i + 1].x;
+            ii += (R)e.a[o][i] * xin[u][i + 1].y;
           }
-          R vr = sh[o] * ir + sl[o] * ir;
-          R vi = sh[o] * ii + sl[o] * ii;
+          // increment: scale * (sum a x + b Hv), scale as a float-float pair
+          const R shh = (R)e.scale[o], sll = (R)(e.scale[o] - (double)shh);
+          R vr = shh * ir + sll * ir;
+          R vi = shh * ii + sll * ii;
           if (e.comp_flags & (1 << o)) {
             vr += lo[u].x;
             vi += lo[u].y;
           }
-          const R bre = c0[o] * xin[u][0].x + cu[o] * uv[q].x;
-          const R bim = c0[o] * xin[u][0].y + cu[o] * uv[q].y;
+          const R bre = (R)e.c0[o] * xin[u][0].x + (R)e.cu[o] * uq.x;
+          const R bim = (R)e.c0[o] * xin[u][0].y + (R)e.cu[o] * uq.y;
           const R sr = bre + vr, si = bim + vi;
           if (o == 0 && (e.comp_flags & 8)) {
             // two-sum: the rounding error of bre + vr goes to the low part
@@ -505,12 +491,12 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
           if (o == 0) {
             if (e.red_flags & 1) r0 += (double)sr * (double)sr + (double)si * (double)si;
             if (e.red_flags & 2) {
-              const double dr = (double)sr - (double)uv[q].x, di = (double)si - (double)uv[q].y;
+              const double dr = (double)sr - (double)uq.x, di = (double)si - (double)uq.y;
               r1 += dr * dr + di * di;
             }
           }
         }
-        if (e.red_flags & 4) r2 += (double)uv[q].x * (double)hrr + (double)uv[q].y * (double)hii;
+        if (e.red_flags & 4) r2 += (double)uq.x * (double)hrr + (double)uq.y * (double)hii;
       }
     }
   }
@@ -914,7 +900,7 @@ __device__ __forceinline__ void diag_tile_setup(const PassArgs& a, double* fsh, 
   __syncthreads();
   diag_setup_a<double>(a, (uint64_t)blockIdx.x, fsh, lin, cps);
   __syncthreads();
-  diag_setup_b<double>(a, lin, LA, LB);
+  diag_setup_b(a, lin, LA, LB);
   __syncthreads();
 }
 
@@ -926,7 +912,7 @@ __global__ __launch_bounds__(kThreads) void k_diag_minmax(const PassArgs a, doub
   const uint64_t base = (uint64_t)blockIdx.x << a.tb;
   double mn = INFINITY, mx = -INFINITY;
   for (uint32_t l = threadIdx.x; l < ntile; l += kThreads) {
-    const double d = diag_value<double>(a, l, base + l, cps[0], LA, LB, fsh);
+    const double d = diag_value(a, l, base + l, cps[0], LA, LB, fsh);
     mn = fmin(mn, d);
     mx = fmax(mx, d);
   }
@@ -968,7 +954,7 @@ __global__ __launch_bounds__(kThreads) void k_diag_mass(const PassArgs a, const 
   const uint64_t base = (uint64_t)blockIdx.x << a.tb;
   double r = 0.0;
   for (uint32_t l = threadIdx.x; l < ntile; l += kThreads) {
-    const double d = diag_value<double>(a, l, base + l, cps[0], LA, LB, fsh);
+    const double d = diag_value(a, l, base + l, cps[0], LA, LB, fsh);
     if (d <= thr) {
       const V v = psi[base + l];
       r += (double)v.x * (double)v.x + (double)v.y * (double)v.y;

@@ -194,7 +194,13 @@ def test_planted_mistakes_are_caught(monkeypatch):
 
 
 def test_adaptive_refuses_unreachable_tolerance():
-    """An estimate that cannot fall below atol ends the run (no endless halving)."""
+    """An atol below the rounding floor of the estimate is refused up front; an
+    estimate that still cannot fall below atol (here: a floor declared finer
+    than the float64 arithmetic really is) ends the run after a bounded number
+    of halvings instead of halving forever."""
     inst, rng = _random_td_instance(3, 91)
+    psi0 = I.random_state(3, rng)
+    with pytest.raises(ValueError):
+        integrate.evolve_adaptive(inst, psi0, 0.0, 2.0, atol=1e-30, h0=0.1)
     with pytest.raises(RuntimeError):
-        integrate.evolve_adaptive(inst, I.random_state(3, rng), 0.0, 2.0, atol=1e-30, h0=0.1)
+        integrate.evolve_adaptive(inst, psi0, 0.0, 2.0, atol=1e-30, h0=0.1, unit_roundoff=2.0 ** -120)
