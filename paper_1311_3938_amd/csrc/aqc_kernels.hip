@@ -57,6 +57,18 @@ __device__ __forceinline__ uint64_t pdep64(uint64_t v, uint64_t mask) {
   return r;
 }
 
+// The bits of mask above its k lowest set bits.
+__device__ __forceinline__ uint64_t mask_above(uint64_t mask, int k) {
+  for (int i = 0; i < k && mask; ++i) mask &= mask - 1ull;
+  return mask;
+}
+
+// Successor of x among the subsets of m in increasing order: pdep(j + 1, m)
+// from pdep(j, m) in three operations.
+__device__ __forceinline__ uint64_t next_subset(uint64_t x, uint64_t m) {
+  return ((x | ~m) + 1ull) & m;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -227,25 +239,42 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
   // local element l = q*VEC with q = tid + kThreads*j: the tid part and the j
   // part occupy disjoint bits of l, so their deposits can be OR-ed.
   const uint64_t dep_tid = FINAL ? ((uint64_t)tid << LOGV) : pdep64((uint64_t)tid << LOGV, tmask);
+  // chunk j sits at pdep((kThreads j) << LOGV, tmask), element j at
+  // pdep(kThreads j, tmask): successive subsets of the tile mask above its
+  // lowest 9 + LOGV (9) bits, enumerated incrementally (uniform, scalar)
+  static_assert(kThreads == 512, "offset enumeration assumes 2^9 threads");
+  const uint64_t cmask_hi = mask_above(tmask, 9 + LOGV);
+  const uint64_t emask_hi = mask_above(tmask, 9);
+  // (the last pass's tile is contiguous: constant offsets)
   u32x4 tv[MAXC];
+  uint64_t co = 0;
 #pragma unroll
   for (int j = 0; j < MAXC; ++j) {
     if (j < cpt) {
-      const uint64_t jpart = (uint64_t)(kThreads * j) << LOGV;
-      const uint64_t g = base | dep_tid | (FINAL ? jpart : pdep64(jpart, tmask));
-      tv[j] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src + g));
+      if constexpr (FINAL) {
+        const uint64_t jpart = (uint64_t)(kThreads * j) << LOGV;
+        tv[j] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src + (base | dep_tid | jpart)));
+      } else {
+        tv[j] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src + (base | dep_tid | co)));
+        co = next_subset(co, cmask_hi);
+      }
     }
   }
   if (cpt == 0 && (uint32_t)tid < nchunks) tv[0] = *reinterpret_cast<const u32x4*>(src + (base | dep_tid));
-  // high passes: the partial product of the first elements (half a block for
-  // complex128, to stay within the registers of two workgroups per CU)
-  constexpr int PF = FINAL ? 1 : (sizeof(R) == 4 ? 8 : 4);
+  // high passes: the partial product of the first elements, all of them
+  // for a complex64 tile of 2^13, so no load waits behind the pass's stores
+  // (loads and stores share one counter); complex128 half a block
+  constexpr int PF = FINAL ? 1 : (sizeof(R) == 4 ? 16 : 4);
   V apf[PF];
+  {
+    uint64_t eo = 0;
 #pragma unroll
-  for (int j = 0; j < PF; ++j) {
-    apf[j] = V{0, 0};
-    if (!FINAL && accin && (uint32_t)j < E && tid + kThreads * j < ntile)
-      apf[j] = ldnt(accin + (base | edep_tid | pdep64((uint64_t)kThreads * j, tmask)));
+    for (int j = 0; j < PF; ++j) {
+      apf[j] = V{0, 0};
+      if (!FINAL && accin && (uint32_t)j < E && tid + kThreads * j < ntile)
+        apf[j] = ldnt(accin + (base | edep_tid | eo));
+      eo = next_subset(eo, emask_hi);
+    }
   }
   const bool hasg = tid < a.ng, hast = tid < a.nterms;
   DevGroup gr{};
@@ -260,10 +289,10 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
     if (j < cpt) *reinterpret_cast<u32x4*>(tile + (tid + kThreads * j) * VEC) = tv[j];
   if (cpt == 0 && (uint32_t)tid < nchunks) *reinterpret_cast<u32x4*>(tile + tid * VEC) = tv[0];
   for (int j = MAXC; j < cpt; ++j) {
-    const uint64_t jpart = (uint64_t)(kThreads * j) << LOGV;
-    const uint64_t g = base | dep_tid | (FINAL ? jpart : pdep64(jpart, tmask));
+    const uint64_t off = FINAL ? ((uint64_t)(kThreads * j) << LOGV) : co;
     *reinterpret_cast<u32x4*>(tile + (tid + kThreads * j) * VEC) =
-        __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src + g));
+        __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src + (base | dep_tid | off)));
+    co = next_subset(co, cmask_hi);
   }
   if (tid < kMaxSched) fsh[tid] = a.f[tid];
   __syncthreads();
@@ -300,11 +329,21 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
   constexpr int NJB = FINAL ? 1 : 4;
   // elements per batch of the stage update (streamed loads in flight)
   constexpr int U = sizeof(R) == 4 ? 4 : 2;
+  uint64_t eo_run = 0;   // offset of element jb (blocks run in ascending order)
   for (uint32_t jb0 = 0; jb0 < E; jb0 += EB * NJB) {
 #pragma unroll
   for (int qb = 0; qb < NJB; ++qb) {
     const uint32_t jb = jb0 + qb * EB;
     if (jb >= E) break;
+    // high passes: offsets of the block's elements, enumerated in order
+    uint64_t eou[FINAL ? 1 : EB];
+    if constexpr (!FINAL) {
+#pragma unroll
+      for (int u = 0; u < EB; ++u) {
+        eou[u] = eo_run;
+        eo_run = next_subset(eo_run, emask_hi);
+      }
+    }
     // complex64: hr/hi sum the flip groups only; their terms are small next
     // to the diagonal term, which the last pass adds in float64 at the end, so
     // the float32 partial sums never carry the diagonal's magnitude.
@@ -314,8 +353,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
     // index and tile value are recomputed / re-read from LDS where needed
     // rather than held in registers
     auto gidx_of = [&](int u) -> uint64_t {
-      const uint64_t jpart = (uint64_t)kThreads * (jb + u);
-      return base | edep_tid | (FINAL ? jpart : pdep64(jpart, tmask));
+      if constexpr (FINAL) return base | edep_tid | ((uint64_t)kThreads * (jb + u));
+      else return base | edep_tid | eou[u];
     };
     auto tile_of = [&](int u) -> V { return tile[tid + kThreads * (jb + u)]; };
     R hr[EB], hi[EB];
@@ -522,6 +561,17 @@ __global__ __launch_bounds__(kThreads) void k_pass_batch(const PassArgs* __restr
   pass_body<R, FINAL>(a, m.y, (int64_t)1 << (a.n - a.tb), smem);
 }
 
+// The complex64 high pass of the batch, held to 128 VGPRs (two workgroups of
+// 512 threads per CU).
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_pass_batch_high_c64(
+    const PassArgs* __restrict__ args, const int2* __restrict__ bmap) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int2 m = bmap[blockIdx.x];
+  if (m.x < 0) return;
+  const PassArgs& a = args[m.x];
+  pass_body<float, false>(a, m.y, (int64_t)1 << (a.n - a.tb), smem);
+}
+
 // High-qubit flips on a hypercube held in registers: lane = bits 0..5 (64
 // contiguous amplitudes per load instruction), registers = the 2^RB vertices of
 // the hypercube over bits [hb, hb + RB).  A flip of bit hb + b pairs vertex v
@@ -679,7 +729,7 @@ hipError_t launch_pass_batch(const PassArgs* args, const int2* bmap, int64_t nbl
   dim3 grid((unsigned)nblocks), block(kThreads);
   if (dtype == 0) {
     if (final_pass) hipLaunchKernelGGL((k_pass_batch<float, true>), grid, block, lds, s, args, bmap);
-    else hipLaunchKernelGGL((k_pass_batch<float, false>), grid, block, lds, s, args, bmap);
+    else hipLaunchKernelGGL(k_pass_batch_high_c64, grid, block, lds, s, args, bmap);
   } else {
     if (final_pass) hipLaunchKernelGGL((k_pass_batch<double, true>), grid, block, lds, s, args, bmap);
     else hipLaunchKernelGGL((k_pass_batch<double, false>), grid, block, lds, s, args, bmap);
@@ -724,7 +774,7 @@ hipError_t add_pass_batch_node(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_
   const void* fn;
   if (dtype == 0)
     fn = final_pass ? reinterpret_cast<const void*>(&k_pass_batch<float, true>)
-                    : reinterpret_cast<const void*>(&k_pass_batch<float, false>);
+                    : reinterpret_cast<const void*>(&k_pass_batch_high_c64);
   else
     fn = final_pass ? reinterpret_cast<const void*>(&k_pass_batch<double, true>)
                     : reinterpret_cast<const void*>(&k_pass_batch<double, false>);
@@ -758,7 +808,10 @@ static hipError_t set_lds_attr() {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass<R, FINAL>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass_batch<R, FINAL>),
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass_batch<R, FINAL>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess || sizeof(R) != 4 || FINAL) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass_batch_high_c64),
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
