@@ -107,6 +107,12 @@ def run_batch_mode(args):
                        size_classes=((34, args.instances),), ticks=args.ticks, graph=True,
                        autotune=not args.no_autotune, progress=8)
     log(f"batch: {len(reqs)} solves, n in [{min(r.n for r in reqs)}, {max(r.n for r in reqs)}]")
+    tune_s = 0.0
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        kinds = serve.warm_plans(reqs)
+        tune_s = time.perf_counter() - t0
+        log(f"autotuned {kinds} kinds of problem by batch tick time in {tune_s:.1f} s")
     t0 = time.perf_counter()
     res, wall = srv.run(reqs)
     amp_steps = sum((1 << r.n) * r.steps for r in res)
@@ -126,6 +132,7 @@ def run_batch_mode(args):
                                "T 10..100, pc4, graph-captured batch ticks",
                    "solves": len(res)},
         "amp_updates_per_s": amp_steps / wall,
+        "autotune_s_before_timing": tune_s,
         "baseline_plain_c128_sequential": {
             "solves": len(sub), "seconds": seq_time, "solves_per_s": len(sub) / seq_time,
             "batched_solves_per_s_on_same": None},
@@ -153,6 +160,12 @@ def run_serve_mode(args):
                        autotune=not args.no_autotune, progress=8)
     log(f"serve: {len(reqs)} requests at {args.qps} qps, n in "
         f"[{min(r.n for r in reqs)}, {max(r.n for r in reqs)}]")
+    tune_s = 0.0
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        kinds = serve.warm_plans(reqs)
+        tune_s = time.perf_counter() - t0
+        log(f"autotuned {kinds} kinds of problem by batch tick time in {tune_s:.1f} s")
     res, wall = srv.run(reqs)
     srv.close()
     lat = [r.latency for r in res]
@@ -170,6 +183,7 @@ def run_serve_mode(args):
                                "EC3/SK, linear or catalysed, T 10..100; continuous batching",
                    "requests": len(res), "qps": args.qps},
         "latency_s": {"p50": serve.percentile(lat, 50), "p99": serve.percentile(lat, 99)},
+        "autotune_s_before_timing": tune_s,
         "baseline_plain_c128_sequential": {
             "solves_per_s": len(reqs) / sum(s[0] for s in seq),
             "latency_s": {"p50": serve.percentile(seq_lat, 50), "p99": serve.percentile(seq_lat, 99)}},

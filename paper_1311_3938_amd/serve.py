@@ -64,6 +64,43 @@ class Result:
         return self.finished - self.arrival
 
 
+def choose_plan(ctx, ham, inst, dtype, autotune=False, wide_register_passes=True):
+    """The pass plan a served solve runs: the plan tuned by batch tick time
+    (cached per kind of problem), or else the default tiling with wide register
+    passes when asked.  In a batch the workgroups of all solves fill the GPU
+    together, so wide passes (fewer passes, fewer bytes) win even where a
+    single small solve would not fill it.  A solve run alone with the same
+    plan gives the same result bit for bit."""
+    from . import autotune as at
+    if autotune:
+        return at.tune_cached(ctx, ham, inst, dtype, batch=True)[0]
+    tiling = at.default_tiling(dtype)
+    if wide_register_passes:
+        tiling = (*tiling[:3], (tiling[3] & 4) | 3)
+        ham.set_tiling(dtype, *tiling)
+    return tiling
+
+
+def warm_plans(requests, dtype=torch.complex64, device=0):
+    """Tune (by batch tick time) every kind of problem among the requests once,
+    so admissions find the plan in the tuning cache; returns the number of
+    kinds tuned."""
+    from . import autotune as at
+    ctx = engine.Context(device)
+    seen = set()
+    dt = engine.dtype_code(torch.empty(0, dtype=dtype))
+    for req in requests:
+        key = at.structure_key(req.inst, dt)
+        if key in seen:
+            continue
+        seen.add(key)
+        ham = engine.Hamiltonian(ctx, req.inst)
+        at.tune_cached(ctx, ham, req.inst, dtype, batch=True)
+        ham.free()
+    ctx.close()
+    return len(seen)
+
+
 def solve_plan(ctx, ham, T):
     """Step count and shift of a full solve on [0, T]: centred shift, h rho = 0.1."""
     lo, hi = ham.spectral_bounds(0.0, T)
@@ -123,9 +160,7 @@ class _Class:
     def _admit(self, req, need):
         srv = self.server
         ham = engine.Hamiltonian(self.ctx, req.inst)
-        if srv.autotune:
-            from . import autotune
-            autotune.tune_cached(self.ctx, ham, req.inst, srv.dtype)
+        choose_plan(self.ctx, ham, req.inst, srv.dtype, srv.autotune, srv.wide_register_passes)
         K, shift = solve_plan(self.ctx, ham, req.T)
         N = 1 << req.n
         psi = torch.full((N,), 1.0 / math.sqrt(N), dtype=srv.dtype, device=srv.device)
@@ -156,7 +191,7 @@ class Server:
 
     def __init__(self, device=0, dtype=torch.complex64, hbm_budget_bytes=200e9,
                  size_classes=((20, 256), (34, 8)), ticks=8, graph=True, keep_states=False,
-                 autotune=False, progress=0):
+                 autotune=False, progress=0, wide_register_passes=True):
         self.device = torch.device("cuda", device)
         self.dtype = dtype
         self.budget = float(hbm_budget_bytes)
@@ -165,6 +200,7 @@ class Server:
         self.graph = graph
         self.keep_states = keep_states
         self.autotune = autotune
+        self.wide_register_passes = wide_register_passes
         self.progress = progress     # print a line every `progress` results (0: quiet)
         self.n_admitted = 0
         self._last_report = 0.0

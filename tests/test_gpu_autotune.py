@@ -50,3 +50,29 @@ def test_set_tiling_rejects_bad_values():
         ham.set_tiling(torch.complex64, 13, 13, 4, -1)
     ham.free()
     ctx.close()
+
+
+def test_batch_autotune_picks_by_tick_time_and_caches(tmp_path):
+    """Tuning by the tick time of a batch of replicas: the choice is one of the
+    candidates, is applied (the tuned plan is still exact), and is cached
+    under its own key beside the single-solve choice."""
+    import torch
+    from paper_1311_3938_amd import autotune, engine
+    ctx = engine.Context(0)
+    inst = I.workload_batch_member(3, n_lo=16, n_hi=16)
+    ham = engine.Hamiltonian(ctx, inst)
+    path = str(tmp_path / "tune.json")
+    best, s_per_tick, fresh = autotune.tune_cached(ctx, ham, inst, torch.complex64, path=path, batch=True)
+    assert fresh and s_per_tick > 0
+    assert tuple(best) in [tuple(c) for c in autotune.BATCH_CANDIDATES[0]]
+    key = list(json.load(open(path)).keys())[0]
+    assert key.startswith("batch|")
+    psi = I.random_state(16, np.random.default_rng(2))
+    got = to_host(engine.apply(ctx, ham, 3.0, to_dev(psi, "c64")))
+    assert rel_err(got, sqh.apply_h(inst, 3.0, psi)) < 5e-6
+    ham2 = engine.Hamiltonian(ctx, inst)
+    best2, _, fresh2 = autotune.tune_cached(ctx, ham2, inst, torch.complex64, path=path, batch=True)
+    assert not fresh2 and tuple(best2) == tuple(best)
+    ham.free()
+    ham2.free()
+    ctx.close()

@@ -32,6 +32,7 @@ def test_served_results_equal_alone():
     for r, q in zip(res, reqs):
         assert r.finished >= r.admitted >= r.arrival - 1e-9
         ham = engine.Hamiltonian(ctx, q.inst)
+        serve.choose_plan(ctx, ham, q.inst, torch.complex64)
         K, shift = serve.solve_plan(ctx, ham, q.T)
         assert r.steps == K
         N = 1 << q.n
@@ -91,6 +92,7 @@ def test_two_classes_build_graphs_concurrently():
     ctx = engine.Context(0)
     for r, q in zip(res, reqs):
         ham = engine.Hamiltonian(ctx, q.inst)
+        serve.choose_plan(ctx, ham, q.inst, torch.complex64)
         K, shift = serve.solve_plan(ctx, ham, q.T)
         N = 1 << q.n
         psi = torch.full((N,), 1.0 / math.sqrt(N), dtype=torch.complex64, device="cuda")
