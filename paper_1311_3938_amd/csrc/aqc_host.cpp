@@ -798,12 +798,14 @@ static aqc_status run_matvec(aqc_ctx* ctx, const aqc_ham* h, int dtype, double t
       // algorithmic traffic: the tile source once, each streamed input and
       // output once, the partial product in and out
       int nvec = 1 + (a.acc_in ? 1 : 0) + (a.acc_out ? 1 : 0);
+      int nlo = 0;
       if (ps.final_pass) {
         for (int i = 0; i < 4; ++i) nvec += a.epi.in[i] ? 1 : 0;
         for (int i = 0; i < 3; ++i) nvec += a.epi.out[i] ? 1 : 0;
-        if (a.epi.comp) nvec += (a.epi.comp_flags & 8) ? 2 : 1;  // y_lo read (and written)
+        if (a.epi.comp) nlo = (a.epi.comp_flags & 8) ? 2 : 1;  // y_lo read (and written)
       }
-      ctx->prof_bytes[r.kind] += (double)nvec * (double)((size_t)1 << h->n) * (dtype == 0 ? 8.0 : 16.0);
+      ctx->prof_bytes[r.kind] += ((double)nvec * (dtype == 0 ? 8.0 : 16.0) + 4.0 * nlo) *
+                                 (double)((size_t)1 << h->n);
       if (ctx->prof_pending.size() >= 4096) STCHK(prof_drain(ctx));
     } else {
       HIPCHK(launch_pass(a, dtype, nb, ctx->stream));
@@ -1410,6 +1412,12 @@ struct Evolver {
   }
 };
 
+// Bytes of the low part of a compensated complex64 state: a bfloat16 pair per
+// amplitude, rounded up to keep what follows aligned.
+static size_t comp_bytes(const aqc_ham* h) {
+  return ((((size_t)1 << h->n) * 4) + 255) & ~(size_t)255;
+}
+
 // Lay out the solve vectors in a workspace: y^p, four history vectors (pc4) or
 // one accumulator (rk4), the partial product when the plan has high passes,
 // the second y^p buffer when the last pass has stream groups, and the low part
@@ -1443,7 +1451,7 @@ aqc_status carve_workspace(const aqc_ham* h, int dtype, int method, bool compens
   v->ycomp = nullptr;
   if (dtype == AQC_C64 && compensated) {
     v->ycomp = *w;
-    *w += vb;
+    *w += comp_bytes(h);
   }
   return AQC_OK;
 }
@@ -1462,9 +1470,8 @@ extern "C" size_t aqc_evolve_workspace_bytes(const aqc_ham* h, int dtype, const 
   if (stream) nv += 1;
   const bool adaptive = o && o->n_steps == 0 && o->n_replay <= 0 && method == AQC_METHOD_PC4;
   const bool comp = dtype == AQC_C64 && (!o || o->compensated != 0);
-  if (comp) nv += 1;
-  if (adaptive) nv += comp ? 2 : 1;
-  return nv * vb + 256;
+  if (adaptive) nv += 1;
+  return nv * vb + (comp ? (adaptive ? 2 : 1) * comp_bytes(h) : 0) + 256;
 }
 
 extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int dtype, double t0,
@@ -1517,13 +1524,13 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
   ev.ckpt = nullptr;
   ev.ckpt_lo = nullptr;
   const bool comp = ev.v.ycomp != nullptr;
-  if (comp) HIPCHK(launch_zero(ev.v.ycomp, ev.vb, ctx->stream));
+  if (comp) HIPCHK(launch_zero(ev.v.ycomp, comp_bytes(h), ctx->stream));
   if (adaptive) {
     ev.ckpt = w;
     w += ev.vb;
     if (comp) {
       ev.ckpt_lo = w;
-      w += ev.vb;
+      w += comp_bytes(h);
     }
   }
   ev.nb_last = last_nblocks(h, dtype);
@@ -1628,7 +1635,7 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
       rc = guard(sg.h);
       if (rc != AQC_OK) break;
       HIPCHK(launch_copy(ev.ckpt, ev.v.y, dtype, ev.N, ctx->stream));
-      if (ev.ckpt_lo) HIPCHK(launch_copy(ev.ckpt_lo, ev.v.ycomp, dtype, ev.N, ctx->stream));
+      if (ev.ckpt_lo) HIPCHK(hipMemcpyAsync(ev.ckpt_lo, ev.v.ycomp, (size_t)ev.N * 4, hipMemcpyDeviceToDevice, ctx->stream));
       const SegStepper before = sg;
       const int64_t steps_before = stats->steps;
       int ne = 0;
@@ -1644,7 +1651,7 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
         if (sg.h / 2.0 < h_floor || ++rejections_in_row > 60) {
           stats->t_reached = before.ts + (double)before.k * before.h;
           HIPCHK(launch_copy(ev.v.y, ev.ckpt, dtype, ev.N, ctx->stream));
-          if (ev.ckpt_lo) HIPCHK(launch_copy(ev.v.ycomp, ev.ckpt_lo, dtype, ev.N, ctx->stream));
+          if (ev.ckpt_lo) HIPCHK(hipMemcpyAsync(ev.v.ycomp, ev.ckpt_lo, (size_t)ev.N * 4, hipMemcpyDeviceToDevice, ctx->stream));
           char buf[200];
           snprintf(buf, sizeof buf,
                    "adaptive step: error estimate %.3g stays above atol %.3g down to h = %.3g "
@@ -1655,7 +1662,7 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
         stats->rejected += (stats->steps - steps_before);
         stats->steps = steps_before;
         HIPCHK(launch_copy(ev.v.y, ev.ckpt, dtype, ev.N, ctx->stream));
-        if (ev.ckpt_lo) HIPCHK(launch_copy(ev.v.ycomp, ev.ckpt_lo, dtype, ev.N, ctx->stream));
+        if (ev.ckpt_lo) HIPCHK(hipMemcpyAsync(ev.v.ycomp, ev.ckpt_lo, (size_t)ev.N * 4, hipMemcpyDeviceToDevice, ctx->stream));
         record(before);
         sg = new_seg(before.ts + (double)before.k * before.h, before.h / 2.0);
         windows_at_h = 0;
@@ -1843,7 +1850,7 @@ extern "C" aqc_status aqc_batch_admit(aqc_batch* b, const aqc_ham* h, void* psi,
   sl.h = h;
   char* w = reinterpret_cast<char*>(ws);
   STCHK(carve_workspace(h, b->dtype, AQC_METHOD_PC4, true, psi, &w, &sl.v));
-  if (sl.v.ycomp) HIPCHK(launch_zero(sl.v.ycomp, vec_bytes(h, b->dtype), b->ctx->stream));
+  if (sl.v.ycomp) HIPCHK(launch_zero(sl.v.ycomp, comp_bytes(h), b->ctx->stream));
   sl.sg.method = AQC_METHOD_PC4;
   sl.sg.ts = t0;
   sl.sg.h = (t1 - t0) / (double)n_steps;

@@ -41,6 +41,19 @@ __device__ __forceinline__ void stnt(double2* p, double2 v) {
   __builtin_nontemporal_store(f64x2{v.x, v.y}, reinterpret_cast<f64x2*>(p));
 }
 
+// The low part of a compensated complex64 state is stored as a pair of
+// bfloat16 (4 bytes per amplitude): it is the rounding residual of the float32
+// high part, so 8 mantissa bits leave an error of 2^-9 of a residual per step.
+__device__ __forceinline__ uint32_t bf16_bits(float f) {  // round to nearest even
+  const uint32_t u = __float_as_uint(f);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ uint32_t pack_bf16x2(float re, float im) {
+  return bf16_bits(re) | (bf16_bits(im) << 16);
+}
+__device__ __forceinline__ float bf16_lo(uint32_t p) { return __uint_as_float(p << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t p) { return __uint_as_float(p & 0xFFFF0000u); }
+
 template <typename R> struct CT2;
 template <> struct CT2<float> { using V = float2; };
 template <> struct CT2<double> { using V = double2; };
@@ -318,7 +331,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
   const double cprime = FINAL ? cps[0] : 0.0;
   const EpiDesc& e = a.epi;
   const bool has_comp = FINAL && e.comp != nullptr;
-  V* compv = reinterpret_cast<V*>(e.comp);
+  uint32_t* compv = reinterpret_cast<uint32_t*>(e.comp);   // bfloat16 pairs
   double r0 = 0.0, r1 = 0.0, r2 = 0.0;
   // Elements are processed in blocks of EB: H u for the whole block is kept in
   // registers while the flip groups are walked once (group-outer order), then
@@ -481,7 +494,10 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
 #pragma unroll
         for (int i = 0; i < 4; ++i)
           if (e.in[i]) xin[u][i] = ldnt(reinterpret_cast<const V*>(e.in[i]) + gq);
-        if (has_comp) lo[u] = ldnt(compv + gq);
+        if (has_comp) {
+          const uint32_t p = __builtin_nontemporal_load(compv + gq);
+          lo[u] = V{(R)bf16_lo(p), (R)bf16_hi(p)};
+        }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -524,7 +540,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
             const R tr = sr - bre, ti = si - bim;
             const R er = (bre - (sr - tr)) + (vr - tr);
             const R ei = (bim - (si - ti)) + (vi - ti);
-            stnt(compv + g, V{er, ei});
+            __builtin_nontemporal_store(pack_bf16x2((float)er, (float)ei), compv + g);
           }
           stnt(reinterpret_cast<V*>(e.out[o]) + g, V{sr, si});
           if (o == 0) {
