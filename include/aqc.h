@@ -182,11 +182,13 @@ typedef struct {
   double* record;       /* host, record_cap x (t_start, h, n_steps), or NULL  */
   int32_t record_cap;
   int32_t compensated;  /* AQC_C64: 1 (recommended) keeps the state as a
-                           float32 pair hi + lo updated by exact two-sums, so
+                           pair hi + lo updated by exact two-sums, hi in the
+                           caller's complex64 psi and lo (the rounding
+                           residual) as a bfloat16 pair in the workspace, so
                            rounding of the stored state does not accumulate
-                           (one more vector of workspace, two more vector
-                           passes per step); 0 stores y in complex64 only.
-                           Ignored for AQC_C128.                              */
+                           (half a state vector of workspace and of traffic
+                           read and written per step); 0 stores y in
+                           complex64 only.  Ignored for AQC_C128.             */
 } aqc_evolve_opts;
 
 typedef struct {
@@ -206,8 +208,9 @@ typedef struct {
 
 /* Bytes of device workspace aqc_evolve needs for this Hamiltonian and dtype:
  * 5 state vectors for pc4, 2 for rk4, one more when H|psi> takes several
- * tile passes, one more for a compensated complex64 state, and one (two when
- * compensated) for the adaptive controller's checkpoint.                   */
+ * tile passes, one more when the last pass has stream groups (a second y^p),
+ * half a vector for a compensated complex64 state, and for the adaptive
+ * controller's checkpoint one vector (and half a vector when compensated).  */
 size_t aqc_evolve_workspace_bytes(const aqc_ham* ham, int dtype, const aqc_evolve_opts* opts);
 
 /* aqc_evolve: psi holds psi(t0) on entry and psi(t1) on return (in place).
