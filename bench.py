@@ -76,8 +76,9 @@ def measured_traffic(args):
         return None
     if rec.get("kernel_source_sha") != kernel_source_hash():
         return None
-    if (rec.get("n"), rec.get("window"), rec.get("dtype"), rec.get("method")) != (
-            args.n, args.window, args.dtype, args.method):
+    chained = args.method == "pc4" and not args.no_carry
+    if (rec.get("n"), rec.get("window"), rec.get("dtype"), rec.get("method"), rec.get("chained")) != (
+            args.n, args.window, args.dtype, args.method, chained):
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -263,6 +264,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the complex128 comparison of the first window")
+    ap.add_argument("--no-carry", action="store_true",
+                    help="restart the multistep history in every bench step")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB copy (for scaling hardware byte counters)")
     ap.add_argument("--mode", choices=["single", "batch", "serve", "adaptive"], default="single")
@@ -307,20 +310,26 @@ def main():
         f"rho={rho:.3f} K_total={k_total} h={h:.6g} window={W}")
 
     psi = torch.full((N,), 1.0 / math.sqrt(N), dtype=tdt, device="cuda")
-    opts = dict(method=args.method, n_steps=W, shift="center", check_every=W,
+    # one shift for the whole path: the centre of its spectral enclosure
+    opts = dict(method=args.method, n_steps=W, shift=0.5 * (lo + hi), check_every=W,
                 norm_tol=1e-2, stab_limit=0.2155)
     o, _, _ = engine.evolve_opts(**opts)
     ws = engine.workspace(ctx, engine.evolve_workspace_bytes(ham, engine.dtype_code(psi), o))
 
     n_windows_total = k_total // W
+    # consecutive windows form one chain of pc4 calls (the multistep history
+    # carries over); the chain restarts from |+> when the path is done
+    carry = engine.new_carry() if (args.method == "pc4" and not args.no_carry) else None
 
     def bench_step(i):
         w = i % n_windows_total
         if w == 0 and i > 0:
             psi.fill_(1.0 / math.sqrt(N))
+            if carry is not None:
+                carry.valid = 0
         t_a, t_b = w * W * h, (w + 1) * W * h
-        st, _ = engine.evolve(ctx, ham, psi, t_a, t_b, ws=ws, **opts)
-        mass, emin = engine.ground_mass(ctx, ham, T, psi)
+        st, _ = engine.evolve(ctx, ham, psi, t_a, t_b, ws=ws, carry=carry, **opts)
+        mass, emin = engine.ground_mass(ctx, ham, T, psi)   # |psi|^2: the frame phase does not matter
         return st, mass
 
     for i in range(args.warmup):
@@ -364,6 +373,7 @@ def main():
                         f"sin^2 path, T={T:g}; {args.method} with centred shift, "
                         f"{args.dtype} state, fp64 reductions",
             "n_qubits": n, "integration_steps_per_step": W, "h": h, "k_total": k_total,
+            "windows_chained": carry is not None,
             "tile_passes_per_matvec": info["n_passes"][0 if args.dtype == "c64" else 1],
         },
         "roofline": {

@@ -165,6 +165,36 @@ aqc_status aqc_apply(aqc_ctx* ctx, const aqc_ham* ham, double t, const void* psi
 #define AQC_SHIFT_VALUE  0 /* subtract opts.shift from H                     */
 #define AQC_SHIFT_CENTER 1 /* subtract the midpoint of the spectral enclosure */
 
+/* A chain of fixed-step pc4 calls (aqc_evolve_opts.carry).  The multistep
+ * method needs the history of its last steps (Sec. II.B); a call that starts
+ * from a plain state rebuilds it with three RK4 steps.  With a carry, each call
+ * of a chain continues the previous call's grid and history instead, so a
+ * long evolution done in pieces performs exactly the steps of one call.
+ * Fill valid = 0 to start a chain; the call fills the rest.  A call with
+ * valid = 1 must use the same Hamiltonian, dtype, psi and workspace (whose
+ * history vectors the caller leaves untouched), t0 = the previous t1 and the
+ * same step; it keeps the chain's shift whatever opts.shift_mode says.
+ * Within a chain psi is left in the frame of the shifted Hamiltonian: after a
+ * call, psi(t1) = phase * psi (phase_re + i phase_im), a unit factor the
+ * caller applies when it needs the state itself (|psi|^2 and the fidelity of
+ * Sec. III.B do not depend on it).  EINVAL when a continued call does not
+ * match its chain.                                                           */
+typedef struct {
+  int32_t valid;        /* 0: start a chain; 1: continue it                   */
+  int32_t sub;          /* internal position in the step                      */
+  int32_t ypc;          /* internal: current y^p buffer                       */
+  int32_t dtype;
+  int64_t k;            /* steps taken since t_start                          */
+  double t_start;       /* grid of the chain: t_start + k h                   */
+  double h;
+  double shift;         /* the chain's shift                                  */
+  double t_ref;         /* frame reference: psi = exp(i shift (t - t_ref)) psi(t) */
+  const void* ham;
+  const void* psi;
+  const void* workspace;
+  double phase_re, phase_im;  /* out: psi(t1) = phase * psi                  */
+} aqc_pc4_carry;
+
 typedef struct {
   int32_t method;       /* AQC_METHOD_*                                       */
   int32_t n_steps;      /* > 0: fixed steps h = (t1-t0)/n_steps; 0: adaptive  */
@@ -189,6 +219,8 @@ typedef struct {
                            (half a state vector of workspace and of traffic
                            read and written per step); 0 stores y in
                            complex64 only.  Ignored for AQC_C128.             */
+  aqc_pc4_carry* carry; /* fixed-step pc4 only: continue / start a chain, or
+                           NULL for a self-contained call                     */
 } aqc_evolve_opts;
 
 typedef struct {

@@ -39,6 +39,13 @@ class HamInfo(C.Structure):
                 ("spec_lo", C.c_double), ("spec_hi", C.c_double)]
 
 
+class Pc4Carry(C.Structure):
+    _fields_ = [("valid", C.c_int32), ("sub", C.c_int32), ("ypc", C.c_int32), ("dtype", C.c_int32),
+                ("k", C.c_int64), ("t_start", C.c_double), ("h", C.c_double), ("shift", C.c_double),
+                ("t_ref", C.c_double), ("ham", C.c_void_p), ("psi", C.c_void_p),
+                ("workspace", C.c_void_p), ("phase_re", C.c_double), ("phase_im", C.c_double)]
+
+
 class EvolveOpts(C.Structure):
     _fields_ = [("method", C.c_int32), ("n_steps", C.c_int32), ("shift_mode", C.c_int32),
                 ("check_every", C.c_int32), ("shift", C.c_double), ("norm_tol", C.c_double),
@@ -46,7 +53,7 @@ class EvolveOpts(C.Structure):
                 ("hmin", C.c_double), ("hmax", C.c_double), ("window", C.c_int32),
                 ("n_replay", C.c_int32), ("replay", C.POINTER(C.c_double)),
                 ("record", C.POINTER(C.c_double)), ("record_cap", C.c_int32),
-                ("compensated", C.c_int32)]
+                ("compensated", C.c_int32), ("carry", C.POINTER(Pc4Carry))]
 
 
 class EvolveStats(C.Structure):

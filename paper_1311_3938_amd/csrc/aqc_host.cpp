@@ -1497,6 +1497,22 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
   if (!ws || ws_bytes < need)
     return fail(AQC_ENOMEM, "aqc_evolve: workspace needs " + std::to_string(need) + " bytes");
   if (!aligned16(ws)) return fail(AQC_EINVAL, "aqc_evolve: workspace must be 16-byte aligned");
+  aqc_pc4_carry* cy = o->carry;
+  const bool resume = cy && cy->valid;
+  if (cy) {
+    if (o->method != AQC_METHOD_PC4 || adaptive || replay)
+      return fail(AQC_EINVAL, "aqc_evolve: a carry needs fixed-step pc4");
+    if (resume) {
+      const double hh = (t1 - t0) / o->n_steps;
+      const double tnow = cy->t_start + (double)cy->k * cy->h;
+      if (cy->ham != h || cy->psi != psi || cy->workspace != ws || cy->dtype != dtype ||
+          !(std::fabs(hh - cy->h) <= 1e-12 * std::fabs(cy->h)) ||
+          !(std::fabs(t0 - tnow) <= 1e-9 * std::max(1.0, std::fabs(tnow))) || cy->sub < 0 ||
+          cy->sub > 4 || cy->k < 1)
+        return fail(AQC_EINVAL, "aqc_evolve: the call does not continue its carry's chain "
+                                "(same Hamiltonian, state, workspace, dtype and step; t0 = previous t1)");
+    }
+  }
 
   std::memset(stats, 0, sizeof(*stats));
   stats->status_step = -1;
@@ -1504,9 +1520,9 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
   aqc_ham* hm = const_cast<aqc_ham*>(h);
   // shift and stability guard
   double lo = 0, hi = 0;
-  const bool need_enc = o->shift_mode == AQC_SHIFT_CENTER || o->stab_limit > 0.0;
+  const bool need_enc = (o->shift_mode == AQC_SHIFT_CENTER && !resume) || o->stab_limit > 0.0;
   if (need_enc) STCHK(aqc_spectral_bounds(ctx, hm, t0, t1, &lo, &hi));
-  double shift = o->shift_mode == AQC_SHIFT_CENTER ? 0.5 * (lo + hi) : o->shift;
+  double shift = resume ? cy->shift : o->shift_mode == AQC_SHIFT_CENTER ? 0.5 * (lo + hi) : o->shift;
   if (!std::isfinite(shift)) return fail(AQC_EINVAL, "aqc_evolve: shift not finite");
   stats->shift_used = shift;
   stats->rho = need_enc ? std::max(hi - shift, shift - lo) : NAN;
@@ -1524,7 +1540,8 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
   ev.ckpt = nullptr;
   ev.ckpt_lo = nullptr;
   const bool comp = ev.v.ycomp != nullptr;
-  if (comp) HIPCHK(launch_zero(ev.v.ycomp, comp_bytes(h), ctx->stream));
+  // a continued chain keeps the low part of its state
+  if (comp && !resume) HIPCHK(launch_zero(ev.v.ycomp, comp_bytes(h), ctx->stream));
   if (adaptive) {
     ev.ckpt = w;
     w += ev.vb;
@@ -1569,7 +1586,43 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
   };
 
   aqc_status rc = AQC_OK;
-  if (!adaptive) {
+  if (cy) {
+    // a chain of fixed-step pc4 calls: continue the grid and the history; the
+    // last step of every call forms the prediction for the next one
+    SegStepper sg = new_seg(t0, (t1 - t0) / o->n_steps);
+    if (resume) {
+      sg.ts = cy->t_start;
+      sg.h = cy->h;
+      sg.k = cy->k;
+      sg.sub = cy->sub;
+      sg.ypc = cy->ypc;
+    }
+    STCHK(guard(sg.h));
+    rc = ev.advance(sg, o->n_steps, true, false, nullptr);
+    stats->h_last = sg.h;
+    record(sg);
+    if (rc == AQC_OK) {
+      if (!resume) {
+        cy->t_ref = t0;
+        cy->shift = shift;
+        cy->ham = h;
+        cy->psi = psi;
+        cy->workspace = ws;
+        cy->dtype = dtype;
+      }
+      cy->valid = 1;
+      cy->t_start = sg.ts;
+      cy->h = sg.h;
+      cy->k = sg.k;
+      cy->sub = sg.sub;
+      cy->ypc = sg.ypc;
+      const double ph = -cy->shift * (t1 - cy->t_ref);
+      cy->phase_re = std::cos(ph);
+      cy->phase_im = std::sin(ph);
+    } else {
+      cy->valid = 0;
+    }
+  } else if (!adaptive) {
     std::vector<std::tuple<double, double, int64_t>> list;
     if (replay) {
       for (int i = 0; i < o->n_replay; ++i) {
@@ -1692,7 +1745,7 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
     std::memcpy(o->record, segs.data(), m * sizeof(double));
   }
   if (rc != AQC_OK) return rc;
-  if (shift != 0.0) {
+  if (shift != 0.0 && !cy) {
     const double ph = -shift * (t1 - t0);
     HIPCHK(launch_scale(psi, dtype, ev.N, std::cos(ph), std::sin(ph), ctx->stream));
   }

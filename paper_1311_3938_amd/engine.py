@@ -181,11 +181,21 @@ def evolve_workspace_bytes(ham, dtype, opts):
     return lib().aqc_evolve_workspace_bytes(ham.handle, dtype, C.byref(opts))
 
 
+def new_carry():
+    """A fresh chain for consecutive fixed-step pc4 calls (aqc_pc4_carry)."""
+    return L.Pc4Carry()
+
+
 def evolve(ctx: Context, ham: Hamiltonian, psi: torch.Tensor, t0: float, t1: float, ws=None,
-           **kw):
-    """Evolve psi in place from t0 to t1.  Returns (stats dict, recorded segments)."""
+           carry=None, **kw):
+    """Evolve psi in place from t0 to t1.  Returns (stats dict, recorded segments).
+    carry (from new_carry()): continue a chain of fixed-step pc4 calls; psi is
+    then left in the shifted frame, psi(t1) = complex(carry.phase_re,
+    carry.phase_im) * psi, and the same workspace tensor must be passed again."""
     dt = _check_state(ctx, ham.n, psi)
     opts, keep, rec = evolve_opts(**kw)
+    if carry is not None:
+        opts.carry = C.pointer(carry)
     need = evolve_workspace_bytes(ham, dt, opts)
     if ws is None or ws.numel() < need:
         ws = workspace(ctx, need)

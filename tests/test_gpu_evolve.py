@@ -189,3 +189,52 @@ def test_adaptive_below_precision_floor_fails_fast(eng):
     assert ei.value.status == _lib.AQC_EUNSTABLE
     assert "precision floor" in str(ei.value)
     ham.free()
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("key", ["ec3_12", "cat_15"])
+def test_carry_chain_equals_one_call(eng, dt, key, monkeypatch):
+    """Fixed-step pc4 in pieces with a carry performs exactly the steps of one
+    call: the pieces split inside the RK4 bootstrap (after 2 steps), at its end
+    (3, where the first evaluation of the multistep part is pending) and in the
+    predictor-corrector part.  A chain's step is fixed by its first call, so a
+    chain [2, 38] and a chain [2, 1, 7, 30] run on the same grid and must agree
+    bit for bit; once the phase is applied both match a self-contained call
+    (whose step (t1 - t0)/40 may differ from the chain's in the last bit).  The
+    15-qubit plan uses stream groups, so the two alternating y^p buffers are
+    carried too."""
+    engine, ctx = eng
+    import torch
+    from paper_1311_3938_amd import _lib
+    if key == "cat_15":
+        monkeypatch.setenv("AQC_STREAM", "1")
+    inst, psi0 = _PROBLEMS[key]()
+    ham = engine.Hamiltonian(ctx, inst)
+    K, t0, t1, shift = 40, 0.5, 0.5 + 40 * 0.004, 9.0
+    h = (t1 - t0) / K
+    kw = dict(method="pc4", shift=shift)
+    ref = to_dev(psi0, dt)
+    engine.evolve(ctx, ham, ref, t0, t1, n_steps=K, **kw)
+    one = to_dev(psi0, dt)
+    c1 = engine.new_carry()
+    opts, _, _ = engine.evolve_opts(n_steps=K, **kw)
+    ws1 = engine.workspace(ctx, engine.evolve_workspace_bytes(ham, engine.dtype_code(one), opts))
+    for a, b, k in ((t0, t0 + 2 * h, 2), (t0 + 2 * h, t1, K - 2)):
+        engine.evolve(ctx, ham, one, a, b, ws=ws1, carry=c1, n_steps=k, **kw)
+    pieces = [2, 1, 7, K - 10]
+    chain = to_dev(psi0, dt)
+    ws2 = engine.workspace(ctx, ws1.numel())
+    c2 = engine.new_carry()
+    ta = t0
+    for k in pieces:
+        engine.evolve(ctx, ham, chain, ta, ta + k * h, ws=ws2, carry=c2, n_steps=k, **kw)
+        ta += k * h
+    assert c2.k == K and c1.k == K
+    assert torch.equal(one, chain)
+    phase = complex(c2.phase_re, c2.phase_im)
+    got = to_host(chain) * phase
+    assert np.linalg.norm(got - to_host(ref)) < (1e-12 if dt == "c128" else 1e-6)
+    # a call that does not continue its chain is refused
+    with pytest.raises(_lib.AqcError):
+        engine.evolve(ctx, ham, chain, ta + h, ta + 2 * h, ws=ws2, carry=c2, n_steps=1, **kw)
+    ham.free()

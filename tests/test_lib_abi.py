@@ -37,9 +37,11 @@ def test_struct_layouts_match_c(tmp_path):
     prog = tmp_path / "sz.c"
     prog.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "aqc.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(aqc_sched), sizeof(aqc_path),"
-        " sizeof(aqc_evolve_opts), sizeof(aqc_evolve_stats), sizeof(aqc_ham_info_t),"
-        " offsetof(aqc_evolve_opts, replay), offsetof(aqc_evolve_stats, t_reached)); return 0;}\n")
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(aqc_sched),"
+        " sizeof(aqc_path), sizeof(aqc_evolve_opts), sizeof(aqc_evolve_stats), sizeof(aqc_ham_info_t),"
+        " offsetof(aqc_evolve_opts, replay), offsetof(aqc_evolve_stats, t_reached),"
+        " offsetof(aqc_evolve_opts, carry), sizeof(aqc_pc4_carry), offsetof(aqc_pc4_carry, phase_re));"
+        " return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)],
                    check=True)
@@ -47,7 +49,8 @@ def test_struct_layouts_match_c(tmp_path):
                                           check=True).stdout.split()]
     want = [C.sizeof(_lib.Sched), C.sizeof(_lib.Path), C.sizeof(_lib.EvolveOpts),
             C.sizeof(_lib.EvolveStats), C.sizeof(_lib.HamInfo), _lib.EvolveOpts.replay.offset,
-            _lib.EvolveStats.t_reached.offset]
+            _lib.EvolveStats.t_reached.offset, _lib.EvolveOpts.carry.offset, C.sizeof(_lib.Pc4Carry),
+            _lib.Pc4Carry.phase_re.offset]
     assert got == want
 
 
