@@ -252,6 +252,87 @@ def run_adaptive_mode(args):
     print(json.dumps(res), flush=True)
 
 
+def run_paths_mode(args):
+    """The three paths of Sec. IV.A (straight line, nonlinear, clause-by-clause)
+    from H^xy to an EC3 H_f at n qubits, started in a Dicke state: fixed-step
+    pc4 windows per path, with the kernel times of each."""
+    import numpy as np
+    import torch
+    from paper_1311_3938_amd import engine
+    from paper_1311_3938_amd import instances as I
+    n = args.n_paths
+    m = int(round(0.8 * n))
+    T = 20.0
+    N = 1 << n
+    W = args.window
+    weight = n // 3
+    dicke = torch.from_numpy(I.dicke_state(n, weight, dtype=np.complex64)).to("cuda")
+    ctx = engine.Context(0)
+    out = {}
+    for kind in ("linear", "nonlinear", "cbc"):
+        inst = I.workload_ec3_paths(n=n, m=m, T=T, kind=kind, seed=I.seed_for(5))
+        ham = engine.Hamiltonian(ctx, inst)
+        lo, hi = ham.spectral_bounds(0.0, T)
+        rho = 0.5 * (hi - lo)
+        K = int(math.ceil(T * rho / 0.1))
+        h = T / K
+        psi = dicke.clone()
+        opts = dict(method="pc4", n_steps=W, shift=0.5 * (lo + hi), check_every=W, norm_tol=1e-2,
+                    stab_limit=0.2155)
+        o, _, _ = engine.evolve_opts(**opts)
+        ws = engine.workspace(ctx, engine.evolve_workspace_bytes(ham, engine.dtype_code(psi), o))
+        carry = engine.new_carry()
+        # the middle of the path, where every clause ramp of the cbc path is on
+        t_a = 0.5 * T - 0.5 * (args.steps + args.warmup) * W * h
+        for i in range(args.warmup):
+            engine.evolve(ctx, ham, psi, t_a, t_a + W * h, ws=ws, carry=carry, **opts)
+            t_a += W * h
+        engine.profile_enable(ctx, True)
+        engine.profile_reset(ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = 0
+        for i in range(args.steps):
+            st, _ = engine.evolve(ctx, ham, psi, t_a, t_a + W * h, ws=ws, carry=carry, **opts)
+            t_a += W * h
+            steps += st["steps"]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = engine.profile_read(ctx)
+        engine.profile_enable(ctx, False)
+        last_ms, last_n, last_b = prof["last_pass"]
+        high_ms, high_n, high_b = prof["high_pass"]
+        info = ham.info()
+        out[kind] = {
+            "amp_updates_per_s": N * steps / el, "ms_per_integration_step": 1e3 * el / steps,
+            "K_path": K, "h": h, "n_terms": inst.n_terms, "n_schedules": len(inst.scheds),
+            "tile_passes_per_matvec": info["n_passes"][0],
+            "last_pass": {"avg_ms": last_ms / max(last_n, 1),
+                          "GBps": last_b / (last_ms * 1e-3) / 1e9 if last_ms > 0 else None},
+            "high_passes": {"launches_per_step": high_n / max(steps, 1),
+                            "avg_ms": high_ms / max(high_n, 1),
+                            "GBps": high_b / (high_ms * 1e-3) / 1e9 if high_ms > 0 else None},
+            "bytes_per_amp_step": (last_b + high_b) / max(steps, 1) / N,
+            "hbm_frac_whole_step": (last_b + high_b) / el / 8.0e12,
+            "norm": engine.norm2(ctx, psi),
+        }
+        log(f"{kind}: {out[kind]}")
+        del ws, psi
+        ham.free()
+        torch.cuda.empty_cache()
+    lin = out["linear"]
+    res = {
+        "metric": "amp-updates/s", "value": lin["amp_updates_per_s"], "unit": "amp-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": lin["ms_per_integration_step"] * W, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": f"EC3 n={n}, m={m}, H^xy start (Dicke weight {weight}), T={T:g}, "
+                               f"pc4 windows of {W} steps in the middle of each path"},
+        "paths": out,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,7 +349,9 @@ def main():
                     help="restart the multistep history in every bench step")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB copy (for scaling hardware byte counters)")
-    ap.add_argument("--mode", choices=["single", "batch", "serve", "adaptive"], default="single")
+    ap.add_argument("--mode", choices=["single", "batch", "serve", "adaptive", "paths"],
+                    default="single")
+    ap.add_argument("--n-paths", type=int, default=26, help="qubits of the paths mode")
     ap.add_argument("--atol", type=float, default=1e-9)
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--baseline-subset", type=int, default=16)
@@ -288,6 +371,8 @@ def main():
         return run_serve_mode(args)
     if args.mode == "adaptive":
         return run_adaptive_mode(args)
+    if args.mode == "paths":
+        return run_paths_mode(args)
 
     import torch
     from paper_1311_3938_amd import engine

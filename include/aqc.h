@@ -59,12 +59,19 @@ typedef enum {
   AQC_SCHED_CONST  = 0,  /* f = 1                                            */
   AQC_SCHED_POLY_S = 1,  /* f = sum_{d<=degree} coef[d] s^d on s_lo <= s < s_hi
                             (s <= s_hi when hi_closed), 0 outside             */
-  AQC_SCHED_TRIG_T = 2   /* f = amp * cos(omega t + phase)                   */
+  AQC_SCHED_TRIG_T = 2,  /* f = amp * cos(omega t + phase)                   */
+  AQC_SCHED_PWL_S  = 3   /* piecewise linear in s through the knots
+                            (s_i, v_i) = (coef[2i], coef[2i+1]), i = 0..degree
+                            (degree 0..3, s_i nondecreasing): f = v_0 for
+                            s < s_0, v_degree for s >= s_degree, linear in
+                            between; at a repeated knot the later value holds.
+                            One such ramp per clause expresses the
+                            clause-by-clause path, eq. (cbc)-(kpath).         */
 } aqc_sched_kind;
 
 typedef struct {
   int32_t kind;       /* aqc_sched_kind                                      */
-  int32_t degree;     /* POLY_S: 0..7                                         */
+  int32_t degree;     /* POLY_S: 0..7; PWL_S: knots - 1, 0..3                 */
   int32_t hi_closed;  /* POLY_S: 1 => the window includes s_hi               */
   int32_t reserved;
   double coef[8];
@@ -103,7 +110,7 @@ const char* aqc_version(void);
  * are copied; the caller keeps ownership.  Terms with equal (x, z, sched_id)
  * are merged; terms with x = 0 form the diagonal, the others are grouped by
  * their flip pattern x.  Errors: EINVAL for n_qubits < 1, masks >= 2^n,
- * non-finite weights, a sched_id outside [0, n_sched), n_sched > 16, bad
+ * non-finite weights, a sched_id outside [0, n_sched), n_sched > 32, bad
  * schedule or path data; ENOTSUP for n_qubits > 34.  The compiled tables live
  * in library-owned device memory (small: O(terms + 2^(n-13) n) entries) until
  * aqc_ham_free.  The context's stream is used for uploads.                  */

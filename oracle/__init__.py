@@ -12,5 +12,6 @@ Modules
   * ``integrate``    classical RK4 and the one-evaluation 4th-order
                      predictor-corrector (Sec. II.B), fixed and adaptive steps
   * ``observables``  norm, overlap, energy, ground-state fidelity (Sec. III.B)
+  * ``subspace``     states and evolution within one Hamming weight (Sec. III.A)
 """
-from . import sqh, integrate, observables  # noqa: F401
+from . import sqh, integrate, observables, subspace  # noqa: F401

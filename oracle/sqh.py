@@ -59,6 +59,17 @@ def schedule_value(sched, t, path):
         return val
     if kind == "trig_t":
         return sched["amp"] * math.cos(sched["omega"] * t + sched["phase"])
+    if kind == "pwl_s":
+        # linear interpolation in s between knots (s_i, v_i), constant outside;
+        # the ramps of the clause-by-clause path, eq. (kpath)
+        s = path_s(path, t)
+        knots = sched["knots"]
+        if s < knots[0][0]:
+            return float(knots[0][1])
+        for (a, va), (b, vb) in zip(knots[:-1], knots[1:]):
+            if a <= s < b:
+                return va + (vb - va) * (s - a) / (b - a)
+        return float(knots[-1][1])
     raise ValueError(f"unknown schedule {kind!r}")
 
 

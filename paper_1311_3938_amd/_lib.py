@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(HERE, "libaqc.so")
 
 AQC_OK, AQC_EINVAL, AQC_ENOMEM, AQC_EDEVICE, AQC_EUNSTABLE, AQC_ENOTSUP, AQC_EBUSY = 0, -1, -2, -3, -4, -5, -6
 C64, C128 = 0, 1
-SCHED_CONST, SCHED_POLY_S, SCHED_TRIG_T = 0, 1, 2
+SCHED_CONST, SCHED_POLY_S, SCHED_TRIG_T, SCHED_PWL_S = 0, 1, 2, 3
 PATH_LINEAR, PATH_SIN2 = 0, 1
 METHOD_PC4, METHOD_RK4 = 0, 1
 SHIFT_VALUE, SHIFT_CENTER = 0, 1
@@ -157,6 +157,14 @@ def make_sched(spec):
         s.s_lo = spec.get("s_lo", -math.inf)
         s.s_hi = spec.get("s_hi", math.inf)
         s.hi_closed = 1 if spec.get("hi_closed", False) else 0
+    elif k == "pwl_s":
+        s.kind = SCHED_PWL_S
+        knots = [(float(a), float(v)) for a, v in spec["knots"]]
+        if not 1 <= len(knots) <= 4:
+            raise ValueError("pwl_s needs 1..4 knots")
+        s.degree = len(knots) - 1
+        for i, (a, v) in enumerate(knots):
+            s.coef[2 * i], s.coef[2 * i + 1] = a, v
     elif k == "trig_t":
         s.kind = SCHED_TRIG_T
         s.amp, s.omega, s.phase = spec["amp"], spec["omega"], spec.get("phase", 0.0)

@@ -203,6 +203,17 @@ static double sched_value(const aqc_sched& s, const aqc_path& p, double t) {
       }
       return v;
     }
+    case AQC_SCHED_PWL_S: {
+      const double x = path_s(p, t);
+      const double* k = s.coef;   // (s_i, v_i) pairs
+      if (x < k[0]) return k[1];
+      for (int i = 0; i < s.degree; ++i) {
+        // here x >= s_i; the first knot above x bounds its segment
+        if (x < k[2 * i + 2])
+          return k[2 * i + 1] + (k[2 * i + 3] - k[2 * i + 1]) * (x - k[2 * i]) / (k[2 * i + 2] - k[2 * i]);
+      }
+      return k[2 * s.degree + 1];
+    }
     default:
       return s.amp * std::cos(s.omega * t + s.phase);
   }
@@ -310,13 +321,21 @@ extern "C" aqc_status aqc_build_hamiltonian(aqc_ctx* ctx, int n, int64_t n_terms
   if (n_terms > 0 && (!xm || !zm || !w || !sid))
     return fail(AQC_EINVAL, "aqc_build_hamiltonian: NULL term array");
   if (n_sched < 1 || n_sched > kMaxSched || !scheds)
-    return fail(AQC_EINVAL, "aqc_build_hamiltonian: need 1..16 schedules");
+    return fail(AQC_EINVAL, "aqc_build_hamiltonian: need 1..32 schedules");
   if (!path || !(path->T > 0.0) || !std::isfinite(path->T) ||
       (path->kind != AQC_PATH_LINEAR && path->kind != AQC_PATH_SIN2))
     return fail(AQC_EINVAL, "aqc_build_hamiltonian: bad path");
   for (int s = 0; s < n_sched; ++s) {
     const aqc_sched& sc = scheds[s];
-    if (sc.kind < 0 || sc.kind > 2) return fail(AQC_EINVAL, "aqc_build_hamiltonian: bad schedule kind");
+    if (sc.kind < 0 || sc.kind > 3) return fail(AQC_EINVAL, "aqc_build_hamiltonian: bad schedule kind");
+    if (sc.kind == AQC_SCHED_PWL_S) {
+      if (sc.degree < 0 || sc.degree > 3) return fail(AQC_EINVAL, "aqc_build_hamiltonian: 1..4 knots");
+      for (int d = 0; d < 2 * (sc.degree + 1); ++d)
+        if (!std::isfinite(sc.coef[d])) return fail(AQC_EINVAL, "aqc_build_hamiltonian: non-finite knot");
+      for (int d = 0; d < sc.degree; ++d)
+        if (sc.coef[2 * d + 2] < sc.coef[2 * d])
+          return fail(AQC_EINVAL, "aqc_build_hamiltonian: knots must not decrease in s");
+    }
     if (sc.kind == AQC_SCHED_POLY_S) {
       if (sc.degree < 0 || sc.degree > 7) return fail(AQC_EINVAL, "aqc_build_hamiltonian: poly degree");
       for (int d = 0; d <= sc.degree; ++d)

@@ -121,7 +121,7 @@ __device__ __forceinline__ void block_reduce3(double r0, double r1, double r2, i
 
 // LDS layout of a tile workgroup (offsets in bytes, 16-byte aligned pieces).
 struct Lds {
-  static constexpr int kF = 0;                                   // double f[16]
+  static constexpr int kF = 0;                                   // double f[kMaxSched]
   static constexpr int kLin = kF + 8 * kMaxSched;                // double lin[16]
   static constexpr int kC = kLin + 8 * 16;                       // double C'
   static constexpr int kRed = kC + 16;                           // double [3][NW]

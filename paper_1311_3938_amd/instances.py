@@ -43,6 +43,15 @@ def poly_s(coef, s_lo=-INF, s_hi=INF, hi_closed=False):
             "s_hi": float(s_hi), "hi_closed": bool(hi_closed)}
 
 
+def pwl_s(knots):
+    """Piecewise-linear schedule in s through up to 4 knots (s_i, v_i), s_i
+    nondecreasing; v_0 below the first knot, the last value from the last on."""
+    knots = [(float(a), float(v)) for a, v in knots]
+    if not 1 <= len(knots) <= 4 or any(b[0] < a[0] for a, b in zip(knots, knots[1:])):
+        raise ValueError("pwl_s: 1..4 knots with nondecreasing s")
+    return {"kind": "pwl_s", "knots": knots}
+
+
 def trig_t(amp, omega, phase=0.0):
     return {"kind": "trig_t", "amp": float(amp), "omega": float(omega), "phase": float(phase)}
 
@@ -242,18 +251,36 @@ def xx_catalyst(n, n_pairs, rng):
 def xy_initial_terms(n, clauses, omega=1.0):
     """H^xy = 3 m Omega 1 - Omega sum_{i<j} (n_ij/2)(sigma^x_i sigma^x_j + sigma^y_i sigma^y_j)
     (eq. (Hixy))."""
-    nij = {}
-    for c in clauses:
-        for a in range(3):
-            for b in range(a + 1, 3):
-                p = (min(c[a], c[b]), max(c[a], c[b]))
-                nij[p] = nij.get(p, 0) + 1
+    nij = clause_pair_counts(clauses)
     t = TermList(n)
     t.add({}, 3.0 * len(clauses) * omega, 0)
     for (i, j) in sorted(nij):
         t.add({i: "X", j: "X"}, -omega * nij[(i, j)] / 2.0, 0)
         t.add({i: "Y", j: "Y"}, -omega * nij[(i, j)] / 2.0, 0)
     return t
+
+
+def xyz_initial_terms(n, clauses, omega=1.0):
+    """H^xyz = Omega sum_{i<j} (n_ij/2)(1 - sigma_i . sigma_j), the Heisenberg
+    ferromagnet on the clause graph (eq. (Hixyz))."""
+    nij = clause_pair_counts(clauses)
+    t = TermList(n)
+    t.add({}, omega * sum(nij.values()) / 2.0, 0)
+    for (i, j) in sorted(nij):
+        for a in "XYZ":
+            t.add({i: a, j: a}, -omega * nij[(i, j)] / 2.0, 0)
+    return t
+
+
+def clause_pair_counts(clauses):
+    """n_ij: the number of clauses that contain both bits i < j."""
+    nij = {}
+    for c in clauses:
+        for a in range(3):
+            for b in range(a + 1, 3):
+                p = (min(c[a], c[b]), max(c[a], c[b]))
+                nij[p] = nij.get(p, 0) + 1
+    return nij
 
 
 def tfim_terms(n, omega=1.0):
@@ -281,6 +308,78 @@ def interpolated(n, h_i: TermList, h_f: TermList, path, h_c: TermList | None = N
         t.extend(h_c, sid=2)
         scheds.append(SCHED_S_ONE_MINUS_S)
     return t.instance(scheds, path, meta)
+
+
+def clause_ramp(c, m):
+    """The weight of clause c (1-based) of m in H_d(s) of eq. (kpath), as a
+    function of s: 0 until s = (c-1)/m, rising to 1 at c/m (the secondary
+    interpolation s_c = m s - c + 1 that switches it on), 1 until (m-1)/m, then
+    falling to 0 at s = 1 (the last window's (1 - s_m) H_{m-1}, since H_m = 0).
+    Windows are half open, so at a joint s = k/m only one window counts; the
+    ramp is continuous there.  Clause m never enters H_d."""
+    if not 1 <= c < m:
+        raise ValueError("clause_ramp: 1 <= c < m")
+    return pwl_s([((c - 1) / m, 0.0), (c / m, 1.0), ((m - 1) / m, 1.0), (1.0, 0.0)])
+
+
+def clause_by_clause(n, clauses, path, h_i=None, omega=1.0, meta=None):
+    """H(s) = (1 - s) H_i + s H_f + H_d(s), eq. (cbc)-(kpath): the clauses are
+    switched on one after the other in stored order; H_i defaults to H^xy."""
+    m = len(clauses)
+    if m + 1 > 32:
+        raise ValueError("clause_by_clause: at most 31 clauses (one schedule each)")
+    t = TermList(n)
+    t.extend(h_i if h_i is not None else xy_initial_terms(n, clauses, omega), sid=0)
+    t.extend(ec3_terms(n, clauses, omega), sid=1)
+    scheds = [SCHED_ONE_MINUS_S, SCHED_S]
+    for c in range(1, m):
+        t.extend(ec3_terms(n, [clauses[c - 1]], omega), sid=len(scheds))
+        scheds.append(clause_ramp(c, m))
+    return t.instance(scheds, path, meta)
+
+
+def clause_graph_components(n, clauses):
+    """Connected components of the graph on bits 1..n whose edges join bits
+    that share a clause."""
+    parent = list(range(n + 1))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    for c in clauses:
+        for q in c[1:]:
+            ra, rb = find(c[0]), find(q)
+            if ra != rb:
+                parent[ra] = rb
+    return len({find(q) for q in range(1, n + 1)})
+
+
+def removable_clause(n, clauses):
+    """Index of the first clause (stored order) whose removal leaves the clause
+    graph as connected as before (Sec. IV.A.1 removes only such clauses)."""
+    base = clause_graph_components(n, clauses)
+    for k in range(len(clauses)):
+        if clause_graph_components(n, clauses[:k] + clauses[k + 1:]) == base:
+            return k
+    raise ValueError("no clause can be removed without splitting the clause graph")
+
+
+def nonlinear_path(n, clauses, path, alpha=8.0, removed=None, h_i=None, omega=1.0, meta=None):
+    """H(s) = (1 - s) H_i + s H_f + alpha s (1 - s) H_{m-1}, eq. (nlpath), with
+    H_{m-1} = H_f without one clause (removable_clause by default); H_i
+    defaults to H^xy."""
+    k = removable_clause(n, clauses) if removed is None else int(removed)
+    reduced = clauses[:k] + clauses[k + 1:]
+    t = TermList(n)
+    t.extend(h_i if h_i is not None else xy_initial_terms(n, clauses, omega), sid=0)
+    t.extend(ec3_terms(n, clauses, omega), sid=1)
+    t.extend(ec3_terms(n, reduced, omega), sid=2)
+    meta = dict(meta or {})
+    meta["removed"] = k
+    return t.instance([SCHED_ONE_MINUS_S, SCHED_S, poly_s([0.0, alpha, -alpha])], path, meta)
 
 
 def random_terms(n, k, rng, max_weight_ops=None, n_sched=1):
@@ -359,6 +458,23 @@ def workload_sk_sin2(n=30, T=30.0, seed=seed_for(2)):
     inst = interpolated(n, transverse_terms(n), sk_terms(n, J, h), sin2_path(T),
                         meta={"kind": "sk", "T": T, "seed": seed})
     return inst
+
+
+def workload_ec3_paths(n=13, m=10, T=20.0, kind="cbc", seed=seed_for(5)):
+    """The paths of Sec. IV.A between H^xy and an EC3 H_f: "linear" (eq. (aqc)),
+    "nonlinear" (eq. (nlpath), alpha = 8) or "cbc" (eq. (cbc)-(kpath)); s = t/T.
+    The same seed gives the same clauses for every kind."""
+    rng = np.random.default_rng(seed)
+    clauses = ec3_random_clauses(n, m, rng)
+    meta = {"kind": "ec3-" + kind, "clauses": clauses, "T": T, "seed": seed}
+    path = linear_path(T)
+    if kind == "linear":
+        return interpolated(n, xy_initial_terms(n, clauses), ec3_terms(n, clauses), path, meta=meta)
+    if kind == "nonlinear":
+        return nonlinear_path(n, clauses, path, meta=meta)
+    if kind == "cbc":
+        return clause_by_clause(n, clauses, path, meta=meta)
+    raise ValueError(kind)
 
 
 def workload_batch_member(i, n_lo=14, n_hi=22, config=3):

@@ -33,6 +33,9 @@ def sched_value(sched, t, path):
         return 1.0
     if sched["kind"] == "trig_t":
         return sched["amp"] * np.cos(sched["omega"] * t + sched["phase"])
+    if sched["kind"] == "pwl_s":
+        xs, vs = zip(*sched["knots"])
+        return float(np.interp(s, xs, vs))
     hi_ok = s <= sched["s_hi"] if sched.get("hi_closed") else s < sched["s_hi"]
     if not (s >= sched["s_lo"] and hi_ok):
         return 0.0

@@ -2,7 +2,7 @@
 import numpy as np
 import torch
 
-TOL = {  # spec parity bars: ||dpsi|| and |dF|
+TOL = {  # parity bars on ||dpsi|| and |dF| (the stated accuracy targets)
     "c64": 1e-6,
     "c128": 1e-10,
 }
