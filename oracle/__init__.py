@@ -13,5 +13,6 @@ Modules
                      predictor-corrector (Sec. II.B), fixed and adaptive steps
   * ``observables``  norm, overlap, energy, ground-state fidelity (Sec. III.B)
   * ``subspace``     states and evolution within one Hamming weight (Sec. III.A)
+  * ``spectrum``     lowest eigenvalues and the gap of H(t) (Sec. IV.B)
 """
-from . import sqh, integrate, observables, subspace  # noqa: F401
+from . import sqh, integrate, observables, subspace, spectrum  # noqa: F401
