@@ -333,6 +333,192 @@ def run_paths_mode(args):
     print(json.dumps(res), flush=True)
 
 
+def run_sector_mode(args):
+    """The paths of Sec. IV.A in one Hamming-weight sector (Sec. III.A.2-3):
+    EC3 with m = round(0.8 n) clauses from H^xy, the C(n, w) states of weight
+    w only, from their Dicke state; chained pc4 windows in the middle of each
+    path, timed with the library's kernel timers."""
+    import torch
+    from paper_1311_3938_amd import engine
+    from paper_1311_3938_amd import instances as I
+    n = args.n_sector
+    w = args.w_sector if args.w_sector >= 0 else n // 2
+    m = int(round(0.8 * n))
+    T = 20.0
+    W = args.window
+    ctx = engine.Context(0)
+    tdt = torch.complex64 if args.dtype == "c64" else torch.complex128
+    out = {}
+    for kind in args.sector_paths.split(","):
+        inst = I.workload_ec3_paths(n=n, m=m, T=T, kind=kind, seed=I.seed_for(5))
+        ham = engine.Hamiltonian(ctx, inst)
+        sec = engine.Sector(ctx, ham, w)
+        D = sec.dim
+        t_b = time.perf_counter()
+        lo, hi = sec.spectral_bounds(0.0, T)
+        bounds_s = time.perf_counter() - t_b
+        rho = 0.5 * (hi - lo)
+        K = int(math.ceil(T * rho / 0.1))
+        h = T / K
+        log(f"{kind}: n={n} w={w} dim={D} enclosure=[{lo:.3f},{hi:.3f}] ({bounds_s:.2f} s) K={K}")
+        psi = sec.dicke(tdt)
+        opts = dict(method="pc4", n_steps=W, shift=0.5 * (lo + hi), check_every=W, norm_tol=1e-2,
+                    stab_limit=0.2155)
+        o, _, _ = engine.evolve_opts(**opts)
+        ws = engine.workspace(ctx, engine.evolve_workspace_bytes(sec, engine.dtype_code(psi), o))
+        carry = engine.new_carry()
+        t_a = 0.5 * T - 0.5 * (args.steps + args.warmup) * W * h
+        for i in range(args.warmup):
+            engine.evolve(ctx, sec, psi, t_a, t_a + W * h, ws=ws, carry=carry, **opts)
+            t_a += W * h
+            log(f"{kind}: warmup window {i} done")
+        engine.profile_enable(ctx, True)
+        engine.profile_reset(ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = 0
+        for i in range(args.steps):
+            st, _ = engine.evolve(ctx, sec, psi, t_a, t_a + W * h, ws=ws, carry=carry, **opts)
+            t_a += W * h
+            steps += st["steps"]
+            log(f"{kind}: window {i} done")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = engine.profile_read(ctx)
+        engine.profile_enable(ctx, False)
+        k_ms, k_n, k_b = prof["last_pass"]
+        out[kind] = {
+            "dim": D, "full_space_amplitudes": 1 << n,
+            "sector_amp_updates_per_s": D * steps / el,
+            "ms_per_integration_step": 1e3 * el / steps,
+            "K_path": K, "h": h, "enclosure": [lo, hi], "enclosure_seconds": bounds_s,
+            "kernel": {"avg_ms": k_ms / max(k_n, 1),
+                       "algorithmic_GBps": k_b / (k_ms * 1e-3) / 1e9 if k_ms > 0 else None,
+                       "bytes_per_amp": k_b / max(k_n, 1) / D},
+            "norm2": engine.norm2(ctx, psi),
+            "workspace_GiB": ws.numel() / 2 ** 30,
+        }
+        log(f"{kind}: {out[kind]}")
+        del ws, psi
+        sec.free()
+        ham.free()
+        torch.cuda.empty_cache()
+    first = out[next(iter(out))]
+    res = {
+        "metric": "amp-updates/s", "value": first["sector_amp_updates_per_s"], "unit": "amp-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": first["ms_per_integration_step"] * W, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": f"EC3 n={n}, m={m}, H^xy start, Hamming-weight sector w={w} "
+                               f"(C({n},{w}) amplitudes), T={T:g}, pc4 windows of {W} steps"},
+        "sector": out,
+    }
+    print(json.dumps(res), flush=True)
+
+
+def run_gap_mode(args):
+    """Gap curve E_1(s) - E_0(s) of a path of Sec. IV.A (the analysis behind
+    the paper's bottom panels): the two lowest levels by aqc_lowest_eigs at
+    evenly spaced s, in the Hamming-weight sector of the Dicke start (or the
+    full space with --w-sector -2)."""
+    import numpy as np
+    import torch
+    from paper_1311_3938_amd import engine
+    from paper_1311_3938_amd import instances as I
+    n = args.n_gap
+    m = int(round(0.8 * n))
+    w = args.w_sector if args.w_sector >= 0 else n // 3
+    ctx = engine.Context(0)
+    inst = I.workload_ec3_paths(n=n, m=m, T=1.0, kind=args.gap_path, seed=I.seed_for(5))
+    ham = engine.Hamiltonian(ctx, inst)
+    op = ham if args.w_sector == -2 else engine.Sector(ctx, ham, w)
+    dtype = torch.complex128 if args.dtype == "c128" else torch.complex64
+    tol = 1e-10 if args.dtype == "c128" else 1e-5
+    pts = []
+    ws = None
+    t_all = time.perf_counter()
+    for i in range(args.gap_points):
+        s_ = (i + 0.5) / args.gap_points
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, res, nmv = engine.lowest_eigs(ctx, op, s_, k=2, dtype=dtype, tol=tol, max_basis=24,
+                                          max_matvecs=20000)
+        el = time.perf_counter() - t0
+        pts.append({"s": s_, "E0": ev[0], "E1": ev[1], "gap": ev[1] - ev[0], "matvecs": nmv,
+                    "seconds": el, "resid": res.tolist()})
+        log(f"s={s_:.3f}: E0={ev[0]:.6f} gap={ev[1] - ev[0]:.6f} ({nmv} products, {el:.2f} s)")
+    wall = time.perf_counter() - t_all
+    dim = op.dim
+    mv = sum(p["matvecs"] for p in pts)
+    gmin = min(pts, key=lambda p: p["gap"])
+    res_ = {
+        "metric": "gap points/s", "value": len(pts) / wall, "unit": "points/s", "n_gpus": 1,
+        "steps": len(pts), "warmup": 0, "ms_per_step": 1e3 * wall / len(pts), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": f"EC3 n={n}, m={m}, {args.gap_path} path from H^xy, "
+                               + (f"sector w={w} ({dim} states)" if op is not ham else f"full space ({dim})")
+                               + f", {len(pts)} values of s"},
+        "products": mv, "products_per_s": mv / wall, "amp_products_per_s": mv * dim / wall,
+        "min_gap": {"s": gmin["s"], "gap": gmin["gap"]}, "points": pts,
+    }
+    print(json.dumps(res_), flush=True)
+
+
+def run_tsearch_mode(args):
+    """Successful runtimes T_s (E(T_s) = 1/2, Sec. III.B) of hard instances
+    with a unique solution (Sec. II.D) for the X and XY algorithms, each round
+    of the bracket-and-bisect search solved as one batch (the methodology of
+    the paper's runtime-scaling figure, on synthetic instances)."""
+    import numpy as np
+    import torch
+    from paper_1311_3938_amd import engine, tsearch
+    from paper_1311_3938_amd import instances as I
+    ctx = engine.Context(0)
+    sizes = [int(v) for v in args.ts_sizes.split(",")]
+    out = {}
+    t_all = time.perf_counter()
+    n_solves = 0
+    for alg in args.ts_algorithms.split(","):
+        for n in sizes:
+            insts = [I.workload_usa(n, i, alg) for i in range(args.ts_instances)]
+            states = []
+            for inst in insts:
+                if alg == "x":
+                    states.append(I.plus_state(n))
+                    continue
+                ham = engine.Hamiltonian(ctx, inst)
+                sec = engine.Sector(ctx, ham, inst.meta["weight"])
+                g = torch.empty(sec.dim, dtype=torch.complex128, device="cuda")
+                engine.lowest_eigs(ctx, sec, 0.0, k=1, max_basis=16, tol=1e-10, ground=g)
+                states.append(sec.expand(g))
+                sec.free()
+                ham.free()
+            t0 = time.perf_counter()
+            S = tsearch.find_ts(ctx, insts, states, T0=4.0, rel=args.ts_rel, dtype=torch.complex64,
+                                log=log)
+            el = time.perf_counter() - t0
+            ts = [s.T_s for s in S]
+            ns = sum(len(s.evals) for s in S)
+            n_solves += ns
+            out[f"{alg}-{n}"] = {"T_s_median": float(np.nanmedian(ts)),
+                                 "T_s_quartiles": [float(np.nanpercentile(ts, 25)),
+                                                   float(np.nanpercentile(ts, 75))],
+                                 "T_s": ts, "solves": ns, "seconds": el,
+                                 "m": [len(i.meta["clauses"]) for i in insts]}
+            log(f"{alg} n={n}: median T_s {out[f'{alg}-{n}']['T_s_median']:.3g}, {ns} solves in {el:.1f} s")
+    wall = time.perf_counter() - t_all
+    res = {
+        "metric": "solves/s", "value": n_solves / wall, "unit": "solves/s", "n_gpus": 1, "steps": n_solves,
+        "warmup": 0, "ms_per_step": 1e3 * wall / max(n_solves, 1), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": f"T_s search, hard EC3 instances with a unique solution, n in {sizes}, "
+                               f"{args.ts_instances} per size, algorithms {args.ts_algorithms}, "
+                               f"bracket ratio {1 + args.ts_rel:g}"},
+        "runs": out,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -349,8 +535,19 @@ def main():
                     help="restart the multistep history in every bench step")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB copy (for scaling hardware byte counters)")
-    ap.add_argument("--mode", choices=["single", "batch", "serve", "adaptive", "paths"],
-                    default="single")
+    ap.add_argument("--mode", choices=["single", "batch", "serve", "adaptive", "paths", "sector", "gap",
+                                       "tsearch"], default="single")
+    ap.add_argument("--ts-sizes", default="10,12,14")
+    ap.add_argument("--ts-instances", type=int, default=8)
+    ap.add_argument("--ts-algorithms", default="x,xy")
+    ap.add_argument("--ts-rel", type=float, default=0.05)
+    ap.add_argument("--n-gap", type=int, default=20)
+    ap.add_argument("--gap-path", default="cbc")
+    ap.add_argument("--gap-points", type=int, default=21)
+    ap.add_argument("--n-sector", type=int, default=34, help="qubits of the sector mode")
+    ap.add_argument("--w-sector", type=int, default=-1,
+                    help="weight of the sector (default n/2, gap mode n/3; -2: full space)")
+    ap.add_argument("--sector-paths", default="linear,cbc")
     ap.add_argument("--n-paths", type=int, default=26, help="qubits of the paths mode")
     ap.add_argument("--atol", type=float, default=1e-9)
     ap.add_argument("--instances", type=int, default=512)
@@ -373,6 +570,12 @@ def main():
         return run_adaptive_mode(args)
     if args.mode == "paths":
         return run_paths_mode(args)
+    if args.mode == "sector":
+        return run_sector_mode(args)
+    if args.mode == "gap":
+        return run_gap_mode(args)
+    if args.mode == "tsearch":
+        return run_tsearch_mode(args)
 
     import torch
     from paper_1311_3938_amd import engine

@@ -287,6 +287,76 @@ aqc_status aqc_ground_mass(aqc_ctx* ctx, const aqc_ham* ham, double t, const voi
  * aqc_apply.                                                                */
 aqc_status aqc_energy(aqc_ctx* ctx, const aqc_ham* ham, double t, const void* psi,
                       int dtype, void* workspace, size_t ws_bytes, double* out);
+/* aqc_norm2 and aqc_overlap on states of `len` amplitudes (sector states).  */
+aqc_status aqc_norm2_len(aqc_ctx* ctx, const void* psi, int dtype, int64_t len, double* out);
+aqc_status aqc_overlap_len(aqc_ctx* ctx, const void* phi, const void* psi, int dtype,
+                           int64_t len, double* re, double* im);
+
+/* ---- Hamming-weight sectors (Sec. III.A.2-3, eq. (Sigmaz)) ---------------- */
+/* H^xyz (eq. (Hixyz)), H^xy (eq. (Hixy)) and a diagonal H_f commute with
+ * Sigma^z, so the number w of 1-bits of the basis states is conserved and a
+ * solve started in the sector of weight w (e.g. from eq. (initstate)) never
+ * leaves it.  aqc_sector_create restricts `ham` to that sector: a state of the
+ * result holds the C(n, w) amplitudes of the weight-w basis states in
+ * increasing order of z, i.e. amplitude r belongs to the z whose set bits
+ * p_0 < p_1 < ... have sum_k C(p_k, k + 1) = r.  The result is an aqc_ham
+ * accepted, on such states, by aqc_apply, aqc_apply_workspace_bytes,
+ * aqc_evolve (every method and option, pc4 chains included),
+ * aqc_evolve_workspace_bytes, aqc_energy, aqc_ground_mass (mass on the lowest
+ * diagonal energies within the sector) and aqc_spectral_bounds (enclosure of
+ * the sector's spectrum); not by aqc_batch_admit (AQC_ENOTSUP) or
+ * aqc_ham_set_tiling (AQC_EINVAL); free it with aqc_ham_free.  It copies what
+ * it needs: `ham` may be freed first.
+ * Requirements, else AQC_EINVAL: 0 <= weight <= n; every off-diagonal term
+ * flips exactly two bits, and for each such pair and schedule the summed
+ * coefficient vanishes on the states whose two bits are equal (checked
+ * exactly over the terms' Z bits, at most 16 besides the pair, else
+ * AQC_ENOTSUP).  n <= 34 and at most 1024 pair terms (AQC_ENOTSUP).
+ * Device tables: a few tens of KB, allocated here.                          */
+aqc_status aqc_sector_create(aqc_ctx* ctx, const aqc_ham* ham, int weight, aqc_ham** out);
+/* amplitudes of a state of `ham`: 2^n, or C(n, w) for a sector            */
+int64_t aqc_ham_dim(const aqc_ham* ham);
+/* the sector's weight, or -1 for a full-space Hamiltonian                  */
+int aqc_ham_sector_weight(const aqc_ham* ham);
+/* psi_full (2^n amplitudes, caller-owned device memory) = psi_s placed at
+ * its basis states, zero elsewhere; the two must not overlap.              */
+aqc_status aqc_sector_expand(aqc_ctx* ctx, const aqc_ham* sector, const void* psi_s,
+                             void* psi_full, int dtype);
+/* psi (C(n, w) amplitudes) = the balanced superposition of eq. (initstate),
+ * every amplitude C(n, w)^{-1/2}.                                          */
+aqc_status aqc_sector_dicke(aqc_ctx* ctx, const aqc_ham* sector, void* psi, int dtype);
+
+/* ---- lowest eigenvalues (Sec. IV.B) ---------------------------------------- */
+/* The n_eig (1..8) smallest eigenvalues of H(t) (a full-space Hamiltonian or
+ * a sector), for the lower spectrum and the gap E_1 - E_0 along a path that
+ * the paper computes with ARPACK.  Thick-restart Lanczos with full
+ * reorthogonalisation (classical Gram-Schmidt twice) in a basis of
+ * max_basis (n_eig + 2 .. 48, at most the dimension) vectors; each restart
+ * keeps min(max_basis - 2, max(n_eig + 4, 2 n_eig)) Ritz vectors.  Products,
+ * dot products and updates run on the device (float64 sums); the projected
+ * matrix is diagonalised on the host.  Converged when every residual
+ * ||H x_i - theta_i x_i|| <= tol * max(1, |theta_i|); complex64 bases reach
+ * about 1e-6 relative, complex128 about 1e-13.  A level of multiplicity > 1
+ * may be reported once: one Krylov sequence sees one vector of each
+ * eigenspace (exactly so for a diagonal H).
+ * start: a device state (copied, normalised) or NULL for a fixed
+ * pseudo-random start.  workspace: aqc_lowest_eigs_workspace_bytes; the
+ * caller owns it.  Outputs: evals[n_eig] ascending, resid[n_eig], *matvecs,
+ * and, when ground_out is not NULL, the normalised Ritz vector of evals[0]
+ * (a device state of the Hamiltonian's dimension, e.g. the ground state of
+ * H^xy in a sector that starts the XY algorithm, Sec. III.A.3).
+ * AQC_EUNSTABLE when max_matvecs products did not converge (the outputs then
+ * hold the last Ritz values); AQC_EINVAL on bad sizes or a zero start.      */
+aqc_status aqc_lowest_eigs(aqc_ctx* ctx, const aqc_ham* ham, double t, int dtype, int n_eig,
+                           int max_basis, int max_matvecs, double tol, const void* start,
+                           void* workspace, size_t ws_bytes, double* evals, double* resid,
+                           int* matvecs, void* ground_out);
+size_t aqc_lowest_eigs_workspace_bytes(const aqc_ham* ham, int dtype, int max_basis);
+/* Host-only: eigenvalues (ascending, w[n]) and optionally eigenvectors
+ * (columns of z, interleaved re/im, row-major n x n) of a Hermitian matrix a
+ * (interleaved re/im, row-major n x n, n <= 512) by cyclic Jacobi rotations;
+ * the solver of the projected Lanczos problem.  Needs no device.            */
+aqc_status aqc_hermitian_eigh(int n, const double* a, double* w, double* z);
 
 /* ---- batches of solves ------------------------------------------------------ */
 /* A batch advances many independent fixed-step predictor-corrector solves

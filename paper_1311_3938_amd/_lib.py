@@ -113,6 +113,17 @@ SIGNATURES = {
     "aqc_batch_poll": (I32, [P, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int)]),
     "aqc_batch_retire": (I32, [P, C.c_int, C.POINTER(EvolveStats)]),
     "aqc_batch_info": (I32, [P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(I64)]),
+    "aqc_norm2_len": (I32, [P, P, C.c_int, I64, C.POINTER(D)]),
+    "aqc_overlap_len": (I32, [P, P, P, C.c_int, I64, C.POINTER(D), C.POINTER(D)]),
+    "aqc_sector_create": (I32, [P, P, C.c_int, C.POINTER(P)]),
+    "aqc_ham_dim": (I64, [P]),
+    "aqc_ham_sector_weight": (C.c_int, [P]),
+    "aqc_sector_expand": (I32, [P, P, P, P, C.c_int]),
+    "aqc_sector_dicke": (I32, [P, P, P, C.c_int]),
+    "aqc_lowest_eigs": (I32, [P, P, D, C.c_int, C.c_int, C.c_int, C.c_int, D, P, P, SZ,
+                              C.POINTER(D), C.POINTER(D), C.POINTER(C.c_int), P]),
+    "aqc_lowest_eigs_workspace_bytes": (SZ, [P, C.c_int, C.c_int]),
+    "aqc_hermitian_eigh": (I32, [C.c_int, C.POINTER(D), C.POINTER(D), C.POINTER(D)]),
     "aqc_profile_enable": (I32, [P, C.c_int]),
     "aqc_profile_reset": (I32, [P]),
     "aqc_profile_read": (I32, [P, C.c_int, C.POINTER(D), C.POINTER(I64), C.POINTER(D)]),

@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
+#include <numeric>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -279,6 +281,11 @@ struct aqc_ham {
   // diagonal minimum and maximum per schedule (spectral enclosure)
   bool have_minmax = false;
   std::vector<double> dmin, dmax;  // per schedule
+  // amplitudes of a state: 2^n, or C(n, w) for a Hamming-weight sector
+  int64_t dim = 0;
+  int sector_w = -1;             // weight of a sector (aqc_sector_create), else -1
+  SectorDev sd{};                // a sector's device tables
+  std::vector<void*> sec_bufs;   // and their allocations
 };
 
 static void free_plan(Plan& p) {
@@ -301,6 +308,7 @@ extern "C" aqc_status aqc_ham_free(aqc_ham* h) {
   hipDeviceSynchronize();
   free_plan(h->plans[0]);
   free_plan(h->plans[1]);
+  for (void* b : h->sec_bufs) hipFree(b);
   delete h;
   return AQC_OK;
 }
@@ -360,6 +368,7 @@ extern "C" aqc_status aqc_build_hamiltonian(aqc_ctx* ctx, int n, int64_t n_terms
   }
   std::unique_ptr<aqc_ham> h(new aqc_ham());
   h->n = n;
+  h->dim = (int64_t)1 << n;
   h->device = ctx->device;
   h->scheds.assign(scheds, scheds + n_sched);
   h->path = *path;
@@ -698,6 +707,15 @@ static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& 
 static aqc_status build_plan(aqc_ham* h, int dtype, hipStream_t s) {
   Plan& p = h->plans[dtype];
   if (p.built) return AQC_OK;
+  if (h->sector_w >= 0) {
+    // one kernel per product; it reads partners anywhere in its source, so
+    // y^p is double-buffered like a last pass with stream groups
+    p.passes.assign(1, Pass());
+    p.passes[0].final_pass = true;
+    p.has_stream = true;
+    p.built = true;
+    return AQC_OK;
+  }
   HIPCHK(hipSetDevice(h->device));
   std::vector<Pass> passes;
   int tbf = 0;
@@ -759,8 +777,12 @@ static void fill_reg_coefs(RegPassArgs& ra, const aqc_ham* h, const Pass& ps, co
 
 // (H(t) - shift) u, with the last pass's epilogue `epi`.  hbuf: one vector when
 // the plan has high passes.
+static aqc_status run_sector_matvec(aqc_ctx* ctx, const aqc_ham* h, int dtype, double t,
+                                    double shift, const void* u, const EpiDesc& epi);
+
 static aqc_status run_matvec(aqc_ctx* ctx, const aqc_ham* h, int dtype, double t, double shift,
                              const void* u, void* hbuf, const EpiDesc& epi) {
+  if (h->sector_w >= 0) return run_sector_matvec(ctx, h, dtype, t, shift, u, epi);
   const Plan& p = h->plans[dtype];
   const Coefs c = coefs_at(h, t);
   const int np = (int)p.passes.size();
@@ -834,6 +856,7 @@ static aqc_status run_matvec(aqc_ctx* ctx, const aqc_ham* h, int dtype, double t
 }
 
 static int64_t last_nblocks(const aqc_ham* h, int dtype) {
+  if (h->sector_w >= 0) return sector_blocks(h->dim);
   return (int64_t)1 << (h->n - h->plans[dtype].tbf);
 }
 
@@ -861,7 +884,7 @@ static aqc_status check_common(aqc_ctx* ctx, const aqc_ham* h, int dtype) {
 }
 
 static size_t vec_bytes(const aqc_ham* h, int dtype) {
-  return ((size_t)1 << h->n) * (dtype == AQC_C64 ? 8 : 16);
+  return (size_t)h->dim * (dtype == AQC_C64 ? 8 : 16);
 }
 
 static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
@@ -885,6 +908,7 @@ extern "C" aqc_status aqc_ham_info(const aqc_ham* h, aqc_ham_info_t* out) {
 extern "C" aqc_status aqc_ham_set_tiling(aqc_ham* h, int dtype, int tbf, int tbh, int lh,
                                          int options) {
   if (!h) return fail(AQC_EINVAL, "aqc_ham_set_tiling: ham is NULL");
+  if (h->sector_w >= 0) return fail(AQC_EINVAL, "aqc_ham_set_tiling: a sector has no tile plan");
   if (dtype != AQC_C64 && dtype != AQC_C128) return fail(AQC_ENOTSUP, "aqc_ham_set_tiling: dtype");
   const int maxtb = dtype == 0 ? 14 : 13;
   if (tbf < 1 || tbf > maxtb || tbh < 2 || tbh > maxtb || lh < 1 || lh >= tbh)
@@ -920,6 +944,11 @@ extern "C" aqc_status aqc_ham_set_tiling(aqc_ham* h, int dtype, int tbf, int tbh
 // Number of passes of the plan and whether its last pass has stream groups
 // (from the built plan, else from a layout computed on the host).
 static aqc_status plan_shape(const aqc_ham* h, int dtype, size_t* np, bool* stream) {
+  if (h->sector_w >= 0) {
+    *np = 1;
+    *stream = true;
+    return AQC_OK;
+  }
   const Plan& p = h->plans[dtype];
   if (p.built) {
     *np = p.passes.size();
@@ -997,14 +1026,46 @@ static aqc_status check_state(aqc_ctx* ctx, const void* psi, int dtype, int n) {
   return AQC_OK;
 }
 
+static aqc_status norm2_len(aqc_ctx* ctx, const void* psi, int dtype, int64_t len, double* out) {
+  STCHK(ensure_parts(ctx, 16384));
+  int64_t nb = 0;
+  HIPCHK(launch_norm2(psi, dtype, len, ctx->parts, &nb, ctx->stream));
+  HIPCHK(launch_reduce_sum(ctx->parts, nb, 1, ctx->dres, ctx->stream));
+  return read_results(ctx, 1, out);
+}
+
 extern "C" aqc_status aqc_norm2(aqc_ctx* ctx, const void* psi, int dtype, int n, double* out) {
   STCHK(check_state(ctx, psi, dtype, n));
   if (!out) return fail(AQC_EINVAL, "aqc_norm2: out is NULL");
-  STCHK(ensure_parts(ctx, 16384));
-  int64_t nb = 0;
-  HIPCHK(launch_norm2(psi, dtype, (int64_t)1 << n, ctx->parts, &nb, ctx->stream));
-  HIPCHK(launch_reduce_sum(ctx->parts, nb, 1, ctx->dres, ctx->stream));
-  return read_results(ctx, 1, out);
+  return norm2_len(ctx, psi, dtype, (int64_t)1 << n, out);
+}
+
+static aqc_status check_len(aqc_ctx* ctx, const void* psi, int dtype, int64_t len) {
+  if (!ctx) return fail(AQC_EINVAL, "ctx is NULL");
+  if (!psi) return fail(AQC_EINVAL, "state pointer is NULL");
+  if (dtype != 0 && dtype != 1) return fail(AQC_ENOTSUP, "dtype must be C64 or C128");
+  if (len < 1) return fail(AQC_EINVAL, "length < 1");
+  if (!aligned16(psi)) return fail(AQC_EINVAL, "state must be 16-byte aligned");
+  HIPCHK(hipSetDevice(ctx->device));
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_norm2_len(aqc_ctx* ctx, const void* psi, int dtype, int64_t len,
+                                    double* out) {
+  STCHK(check_len(ctx, psi, dtype, len));
+  if (!out) return fail(AQC_EINVAL, "aqc_norm2_len: out is NULL");
+  return norm2_len(ctx, psi, dtype, len, out);
+}
+
+static aqc_status overlap_len(aqc_ctx* ctx, const void* phi, const void* psi, int dtype, int64_t len,
+                              double* re, double* im);
+
+extern "C" aqc_status aqc_overlap_len(aqc_ctx* ctx, const void* phi, const void* psi, int dtype,
+                                      int64_t len, double* re, double* im) {
+  STCHK(check_len(ctx, psi, dtype, len));
+  STCHK(check_len(ctx, phi, dtype, len));
+  if (!re || !im) return fail(AQC_EINVAL, "aqc_overlap_len: NULL output");
+  return overlap_len(ctx, phi, psi, dtype, len, re, im);
 }
 
 extern "C" aqc_status aqc_overlap(aqc_ctx* ctx, const void* phi, const void* psi, int dtype, int n,
@@ -1012,9 +1073,14 @@ extern "C" aqc_status aqc_overlap(aqc_ctx* ctx, const void* phi, const void* psi
   STCHK(check_state(ctx, psi, dtype, n));
   STCHK(check_state(ctx, phi, dtype, n));
   if (!re || !im) return fail(AQC_EINVAL, "aqc_overlap: NULL output");
+  return overlap_len(ctx, phi, psi, dtype, (int64_t)1 << n, re, im);
+}
+
+static aqc_status overlap_len(aqc_ctx* ctx, const void* phi, const void* psi, int dtype, int64_t len,
+                              double* re, double* im) {
   STCHK(ensure_parts(ctx, 2 * 16384));
   int64_t nb = 0;
-  HIPCHK(launch_overlap(phi, psi, dtype, (int64_t)1 << n, ctx->parts, &nb, ctx->stream));
+  HIPCHK(launch_overlap(phi, psi, dtype, len, ctx->parts, &nb, ctx->stream));
   HIPCHK(launch_reduce_sum(ctx->parts, nb, 2, ctx->dres, ctx->stream));
   double r[2];
   STCHK(read_results(ctx, 2, r));
@@ -1075,8 +1141,12 @@ static void diag_args(PassArgs& a, const aqc_ham* h, const Plan& p, const double
   a.dg = p.dg;
 }
 
+static aqc_status sector_diag_minmax(aqc_ctx* ctx, const aqc_ham* h, const double* f,
+                                     double dconst, double* mn, double* mx);
+
 static aqc_status diag_minmax(aqc_ctx* ctx, const aqc_ham* h, const Plan& p, const double* f,
                               double dconst, double* mn, double* mx) {
+  if (h->sector_w >= 0) return sector_diag_minmax(ctx, h, f, dconst, mn, mx);
   PassArgs a;
   diag_args(a, h, p, f, dconst);
   const int64_t nb = (int64_t)1 << (h->n - p.tbf);
@@ -1108,6 +1178,20 @@ extern "C" aqc_status aqc_ground_mass(aqc_ctx* ctx, const aqc_ham* h, double t, 
   double mn, mx;
   STCHK(diag_minmax(ctx, h, p, c.f, c.ident, &mn, &mx));
   const double thr = mn + rel_tol * std::max(1.0, std::fabs(mn));
+  if (h->sector_w >= 0) {
+    SectorArgs sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.s = h->sd;
+    for (int i = 0; i < kMaxSched; ++i) sa.f[i] = c.f[i];
+    sa.dconst = c.ident;
+    const int64_t nb = sector_blocks(h->dim);
+    STCHK(ensure_parts(ctx, (size_t)nb));
+    HIPCHK(launch_sector_diag(sa, 1, thr, psi, dtype, ctx->parts, ctx->stream));
+    HIPCHK(launch_reduce_sum(ctx->parts, nb, 1, ctx->dres, ctx->stream));
+    STCHK(read_results(ctx, 1, mass));
+    *e_min = mn;
+    return AQC_OK;
+  }
   PassArgs a;
   diag_args(a, h, p, c.f, c.ident);
   a.src = psi;
@@ -1185,6 +1269,494 @@ extern "C" aqc_status aqc_spectral_bounds(aqc_ctx* ctx, const aqc_ham* hc, doubl
   }
   *lo = a;
   *hi = b;
+  return AQC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Hamming-weight sectors (Sec. III.A.2-3)
+// ---------------------------------------------------------------------------
+static uint64_t binom64(int p, int k) {
+  if (k < 0 || p < 0 || k > p) return 0;
+  uint64_t r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (uint64_t)(p - k + i) / (uint64_t)i;
+  return r;
+}
+
+// Does the flip group g map every basis state of one weight to states of the
+// same weight?  Its flips change two bits i, j; the weight is kept when they
+// differ, and where they are equal the group's coefficient must vanish, for
+// each schedule separately (the schedules are independent functions of t).
+static aqc_status check_group_keeps_weight(const GroupH& g, int n_sched) {
+  if (popc(g.x) != 2)
+    return fail(AQC_EINVAL, "aqc_sector_create: a term flips other than two bits, so it changes "
+                            "the Hamming weight");
+  uint64_t u = 0;
+  double wsum = 0.0;
+  for (const HTerm& t : g.terms) {
+    u |= t.z;
+    wsum += std::fabs(t.w);
+  }
+  u &= ~g.x;
+  if (popc(u) > 16) return fail(AQC_ENOTSUP, "aqc_sector_create: a pair term's Z string is too long to check");
+  for (int s = 0; s < n_sched; ++s) {
+    for (int both = 0; both < 2; ++both) {
+      uint64_t sub = 0;
+      do {
+        const uint64_t y = sub | (both ? g.x : 0ull);
+        const uint64_t src = y ^ g.x;
+        double cr = 0.0, ci = 0.0;
+        for (const HTerm& t : g.terms) {
+          if (t.sid != s) continue;
+          double m = (popc(src & t.z) & 1) ? -t.w : t.w;
+          switch (popc(t.x & t.z) & 3) {
+            case 0: cr += m; break;
+            case 1: ci += m; break;
+            case 2: cr -= m; break;
+            default: ci -= m; break;
+          }
+        }
+        if (std::hypot(cr, ci) > 1e-12 * std::max(1.0, wsum))
+          return fail(AQC_EINVAL, "aqc_sector_create: a pair term connects states of different "
+                                  "Hamming weight");
+        sub = (sub - u) & u;  // next subset of u
+      } while (sub != 0);
+    }
+  }
+  return AQC_OK;
+}
+
+template <typename T>
+static aqc_status sector_upload(aqc_ham* h, const std::vector<T>& v, const T** dst) {
+  *dst = nullptr;
+  if (v.empty()) return AQC_OK;
+  void* d = nullptr;
+  HIPCHK(hipMalloc(&d, v.size() * sizeof(T)));
+  h->sec_bufs.push_back(d);
+  HIPCHK(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  *dst = reinterpret_cast<const T*>(d);
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_sector_create(aqc_ctx* ctx, const aqc_ham* src, int weight, aqc_ham** out) {
+  if (!ctx || !src || !out) return fail(AQC_EINVAL, "aqc_sector_create: NULL argument");
+  *out = nullptr;
+  if (src->sector_w >= 0) return fail(AQC_EINVAL, "aqc_sector_create: already a sector");
+  if (src->device != ctx->device) return fail(AQC_EINVAL, "aqc_sector_create: ham built for another device");
+  const int n = src->n;
+  if (n > kSecMaxN) return fail(AQC_ENOTSUP, "aqc_sector_create: at most 34 qubits");
+  if (weight < 0 || weight > n) return fail(AQC_EINVAL, "aqc_sector_create: weight outside 0..n");
+  for (const GroupH& g : src->groups) STCHK(check_group_keeps_weight(g, (int)src->scheds.size()));
+  HIPCHK(hipSetDevice(ctx->device));
+  std::unique_ptr<aqc_ham> h(new aqc_ham());
+  h->n = n;
+  h->device = src->device;
+  h->scheds = src->scheds;
+  h->path = src->path;
+  h->terms = src->terms;
+  h->diag = src->diag;
+  h->ident = src->ident;
+  h->groups = src->groups;
+  h->sector_w = weight;
+  h->dim = (int64_t)binom64(n, weight);
+  SectorDev& sd = h->sd;
+  sd.n = n;
+  sd.w = weight;
+  sd.zero_bits = weight > n - weight ? 1 : 0;
+  sd.nch = (n + 3) / 4;
+  sd.dim = h->dim;
+  std::vector<uint32_t> binom(kSecBinom * kSecBinom, 0u);
+  for (int p = 0; p < kSecBinom; ++p)
+    for (int k = 0; k < kSecBinom; ++k) binom[p * kSecBinom + k] = (uint32_t)binom64(p, k);
+  // rank part of chunk c holding `nib` when `cnt` 1-bits lie below it:
+  // sum over its set bits b (local order j) of C(4c + b, cnt + j + 1)
+  const int w1 = weight + 1;
+  std::vector<uint32_t> rtab((size_t)sd.nch * 16 * w1, 0u);
+  for (int c = 0; c < sd.nch; ++c)
+    for (int nib = 0; nib < 16; ++nib)
+      for (int cnt = 0; cnt <= weight; ++cnt) {
+        if (cnt + popc((uint64_t)nib) > weight) continue;
+        uint64_t v = 0;
+        int j = 0;
+        bool valid = true;
+        for (int b = 0; b < 4; ++b) {
+          if (!((nib >> b) & 1)) continue;
+          if (4 * c + b >= n) valid = false;
+          v += binom64(4 * c + b, cnt + j + 1);
+          ++j;
+        }
+        if (valid && v <= 0xFFFFFFFFull) rtab[((size_t)c * 16 + nib) * w1 + cnt] = (uint32_t)v;
+      }
+  std::vector<SecHop> hops;
+  std::vector<DevTerm> hterms;
+  for (const GroupH& g : src->groups) {
+    SecHop hp{g.x, (int32_t)hterms.size(), (int32_t)g.terms.size()};
+    for (const HTerm& t : g.terms) hterms.push_back(DevTerm{t.z, t.w, t.sid, popc(t.x & t.z) & 3});
+    hops.push_back(hp);
+  }
+  if (hterms.size() > (size_t)kSecMaxHopTerms)
+    return fail(AQC_ENOTSUP, "aqc_sector_create: more than 1024 pair terms");
+  std::map<uint64_t, std::vector<HTerm>> bymask;
+  std::vector<DevTerm> res;
+  for (const HTerm& t : src->diag) {
+    if (popc(t.z) <= 2) bymask[t.z].push_back(t);
+    else res.push_back(DevTerm{t.z, t.w, t.sid, 0});
+  }
+  std::vector<SecMask> masks;
+  std::vector<DevTerm> mterms;
+  for (auto& kv : bymask) {
+    const uint64_t z = kv.first;
+    const int p = __builtin_ctzll(z);
+    const uint64_t rest = z & (z - 1);
+    SecMask m{p, rest ? __builtin_ctzll(rest) : -1, (int32_t)mterms.size(), (int32_t)kv.second.size()};
+    for (const HTerm& t : kv.second) mterms.push_back(DevTerm{t.z, t.w, t.sid, 0});
+    masks.push_back(m);
+  }
+  sd.nhops = (int)hops.size();
+  sd.nhterms = (int)hterms.size();
+  sd.nmasks = (int)masks.size();
+  sd.nres = (int)res.size();
+  STCHK(sector_upload(h.get(), binom, &sd.binom));
+  STCHK(sector_upload(h.get(), rtab, &sd.rtab));
+  STCHK(sector_upload(h.get(), hops, &sd.hops));
+  STCHK(sector_upload(h.get(), hterms, &sd.hterms));
+  STCHK(sector_upload(h.get(), masks, &sd.masks));
+  STCHK(sector_upload(h.get(), mterms, &sd.mterms));
+  STCHK(sector_upload(h.get(), res, &sd.res));
+  *out = h.release();
+  return AQC_OK;
+}
+
+extern "C" int64_t aqc_ham_dim(const aqc_ham* h) { return h ? h->dim : 0; }
+
+extern "C" int aqc_ham_sector_weight(const aqc_ham* h) { return h ? h->sector_w : -1; }
+
+static aqc_status run_sector_matvec(aqc_ctx* ctx, const aqc_ham* h, int dtype, double t,
+                                    double shift, const void* u, const EpiDesc& epi) {
+  SectorArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.s = h->sd;
+  a.src = u;
+  const Coefs c = coefs_at(h, t);
+  for (int i = 0; i < kMaxSched; ++i) a.f[i] = c.f[i];
+  a.dconst = c.ident - shift;
+  a.epi = epi;
+  if (ctx->prof_on) {
+    aqc_ctx::Rec r;
+    r.kind = AQC_PROF_LAST_PASS;
+    STCHK(prof_event(ctx, &r.a));
+    STCHK(prof_event(ctx, &r.b));
+    HIPCHK(hipEventRecord(r.a, ctx->stream));
+    HIPCHK(launch_sector_matvec(a, dtype, ctx->stream));
+    HIPCHK(hipEventRecord(r.b, ctx->stream));
+    ctx->prof_pending.push_back(r);
+    int nvec = 1;
+    for (int i = 0; i < 4; ++i) nvec += epi.in[i] ? 1 : 0;
+    for (int i = 0; i < 3; ++i) nvec += epi.out[i] ? 1 : 0;
+    const int nlo = epi.comp ? ((epi.comp_flags & 8) ? 2 : 1) : 0;
+    ctx->prof_bytes[r.kind] += ((double)nvec * (dtype == 0 ? 8.0 : 16.0) + 4.0 * nlo) * (double)h->dim;
+    if (ctx->prof_pending.size() >= 4096) STCHK(prof_drain(ctx));
+    return AQC_OK;
+  }
+  HIPCHK(launch_sector_matvec(a, dtype, ctx->stream));
+  return AQC_OK;
+}
+
+static aqc_status sector_diag_minmax(aqc_ctx* ctx, const aqc_ham* h, const double* f,
+                                     double dconst, double* mn, double* mx) {
+  SectorArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.s = h->sd;
+  for (int i = 0; i < kMaxSched; ++i) a.f[i] = f[i];
+  a.dconst = dconst;
+  const int64_t nb = sector_blocks(h->dim);
+  STCHK(ensure_parts(ctx, 2 * (size_t)nb));
+  HIPCHK(launch_sector_diag(a, 0, 0.0, nullptr, 1, ctx->parts, ctx->stream));
+  std::vector<double> host(2 * nb);
+  HIPCHK(hipMemcpyAsync(host.data(), ctx->parts, 2 * nb * sizeof(double), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  double a0 = INFINITY, b0 = -INFINITY;
+  for (int64_t i = 0; i < nb; ++i) {
+    a0 = std::min(a0, host[i]);
+    b0 = std::max(b0, host[nb + i]);
+  }
+  *mn = a0;
+  *mx = b0;
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_sector_expand(aqc_ctx* ctx, const aqc_ham* sector, const void* psi_s,
+                                        void* psi_full, int dtype) {
+  if (!ctx || !sector || !psi_s || !psi_full) return fail(AQC_EINVAL, "aqc_sector_expand: NULL argument");
+  if (sector->sector_w < 0) return fail(AQC_EINVAL, "aqc_sector_expand: not a sector");
+  if (dtype != AQC_C64 && dtype != AQC_C128) return fail(AQC_ENOTSUP, "aqc_sector_expand: dtype");
+  if (!aligned16(psi_s) || !aligned16(psi_full)) return fail(AQC_EINVAL, "aqc_sector_expand: alignment");
+  if (psi_s == psi_full) return fail(AQC_EINVAL, "aqc_sector_expand: the two states must differ");
+  HIPCHK(hipSetDevice(ctx->device));
+  const size_t full_bytes = ((size_t)1 << sector->n) * (dtype == AQC_C64 ? 8 : 16);
+  HIPCHK(launch_zero(psi_full, full_bytes, ctx->stream));
+  HIPCHK(launch_sector_expand(sector->sd, psi_s, psi_full, dtype, ctx->stream));
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_sector_dicke(aqc_ctx* ctx, const aqc_ham* sector, void* psi, int dtype) {
+  if (!ctx || !sector || !psi) return fail(AQC_EINVAL, "aqc_sector_dicke: NULL argument");
+  if (sector->sector_w < 0) return fail(AQC_EINVAL, "aqc_sector_dicke: not a sector");
+  if (dtype != AQC_C64 && dtype != AQC_C128) return fail(AQC_ENOTSUP, "aqc_sector_dicke: dtype");
+  if (!aligned16(psi)) return fail(AQC_EINVAL, "aqc_sector_dicke: alignment");
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(launch_fill(psi, dtype, sector->dim, 1.0 / std::sqrt((double)sector->dim), 0.0, ctx->stream));
+  return AQC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Lowest eigenvalues of H(t) (Sec. IV.B): thick-restart Lanczos with full
+// reorthogonalisation.  The product, the dot products and the updates run on
+// the device; the projected matrix (at most 48 x 48) is diagonalised here.
+// ---------------------------------------------------------------------------
+using cd = std::complex<double>;
+
+// Cyclic Jacobi for a Hermitian matrix (row-major, n x n): each step makes
+// a_pq real with a phase on column q, then zeroes it with a plane rotation.
+// Eigenvalues ascending into w, eigenvectors as the columns of Z.
+static void hermitian_jacobi(int n, std::vector<cd> A, std::vector<double>& w, std::vector<cd>& Z) {
+  Z.assign((size_t)n * n, cd(0.0, 0.0));
+  for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
+  for (int i = 0; i < n; ++i) A[(size_t)i * n + i] = cd(A[(size_t)i * n + i].real(), 0.0);
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int p = 0; p < n; ++p) {
+      diag += std::norm(A[(size_t)p * n + p]);
+      for (int q = p + 1; q < n; ++q) off += std::norm(A[(size_t)p * n + q]);
+    }
+    if (off <= 1e-32 * std::max(diag, 1e-300)) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const cd apq = A[(size_t)p * n + q];
+        const double r = std::abs(apq);
+        if (r == 0.0) continue;
+        const cd ph = apq / r;  // e^{i phi}
+        const double app = A[(size_t)p * n + p].real(), aqq = A[(size_t)q * n + q].real();
+        const double theta = (aqq - app) / (2.0 * r);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        // U = diag(1, e^{-i phi}) [[c, s], [-s, c]] on (p, q)
+        const cd upp = c, upq = s, uqp = -s * std::conj(ph), uqq = c * std::conj(ph);
+        for (int k = 0; k < n; ++k) {  // A <- A U
+          const cd akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+          A[(size_t)k * n + p] = akp * upp + akq * uqp;
+          A[(size_t)k * n + q] = akp * upq + akq * uqq;
+        }
+        for (int k = 0; k < n; ++k) {  // A <- U^H A
+          const cd apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+          A[(size_t)p * n + k] = std::conj(upp) * apk + std::conj(uqp) * aqk;
+          A[(size_t)q * n + k] = std::conj(upq) * apk + std::conj(uqq) * aqk;
+        }
+        A[(size_t)p * n + q] = A[(size_t)q * n + p] = 0.0;
+        A[(size_t)p * n + p] = A[(size_t)p * n + p].real();
+        A[(size_t)q * n + q] = A[(size_t)q * n + q].real();
+        for (int k = 0; k < n; ++k) {  // Z <- Z U
+          const cd zkp = Z[(size_t)k * n + p], zkq = Z[(size_t)k * n + q];
+          Z[(size_t)k * n + p] = zkp * upp + zkq * uqp;
+          Z[(size_t)k * n + q] = zkp * upq + zkq * uqq;
+        }
+      }
+  }
+  std::vector<int> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+    return A[(size_t)a * n + a].real() < A[(size_t)b * n + b].real();
+  });
+  w.resize(n);
+  std::vector<cd> Zs((size_t)n * n);
+  for (int i = 0; i < n; ++i) {
+    w[i] = A[(size_t)idx[i] * n + idx[i]].real();
+    for (int k = 0; k < n; ++k) Zs[(size_t)k * n + i] = Z[(size_t)k * n + idx[i]];
+  }
+  Z.swap(Zs);
+}
+
+extern "C" aqc_status aqc_hermitian_eigh(int n, const double* a, double* w, double* z) {
+  if (n < 1 || n > 512 || !a || !w) return fail(AQC_EINVAL, "aqc_hermitian_eigh: bad argument");
+  std::vector<cd> A((size_t)n * n);
+  for (size_t i = 0; i < A.size(); ++i) A[i] = cd(a[2 * i], a[2 * i + 1]);
+  std::vector<double> ev;
+  std::vector<cd> Z;
+  hermitian_jacobi(n, A, ev, Z);
+  for (int i = 0; i < n; ++i) w[i] = ev[i];
+  if (z)
+    for (size_t i = 0; i < Z.size(); ++i) {
+      z[2 * i] = Z[i].real();
+      z[2 * i + 1] = Z[i].imag();
+    }
+  return AQC_OK;
+}
+
+namespace {
+struct LzLayout {
+  size_t vb, v, w, hbuf, coef, ymat, total;
+};
+LzLayout lz_layout(const aqc_ham* h, int dtype, int m) {
+  LzLayout L{};
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  L.vb = al(vec_bytes(h, dtype));
+  size_t np = 1;
+  bool stream = false;
+  plan_shape(h, dtype, &np, &stream);
+  size_t off = 0;
+  L.v = off;
+  off += (size_t)m * L.vb;
+  L.w = off;
+  off += L.vb;
+  L.hbuf = np > 1 ? off : (size_t)-1;
+  if (np > 1) off += L.vb;
+  L.coef = off;
+  off += al(3 * 2 * kLzMaxBasis * sizeof(double));
+  L.ymat = off;
+  off += al(2 * kLzMaxBasis * kLzMaxKeep * sizeof(double));
+  L.total = off;
+  return L;
+}
+}  // namespace
+
+extern "C" size_t aqc_lowest_eigs_workspace_bytes(const aqc_ham* h, int dtype, int max_basis) {
+  if (!h || (dtype != 0 && dtype != 1) || max_basis < 3 || max_basis > kLzMaxBasis) return 0;
+  return lz_layout(h, dtype, max_basis).total;
+}
+
+extern "C" aqc_status aqc_lowest_eigs(aqc_ctx* ctx, const aqc_ham* h, double t, int dtype, int n_eig,
+                                      int max_basis, int max_matvecs, double tol, const void* start,
+                                      void* ws, size_t ws_bytes, double* evals, double* resid,
+                                      int* matvecs, void* ground_out) {
+  STCHK(check_common(ctx, h, dtype));
+  if (!evals || !resid || !matvecs) return fail(AQC_EINVAL, "aqc_lowest_eigs: NULL output");
+  const int m = max_basis;
+  if (n_eig < 1 || n_eig > 8 || m < n_eig + 2 || m > kLzMaxBasis)
+    return fail(AQC_EINVAL, "aqc_lowest_eigs: need 1 <= n_eig <= 8 and n_eig + 2 <= max_basis <= 48");
+  if (!(tol > 0.0) || !std::isfinite(t) || max_matvecs < m)
+    return fail(AQC_EINVAL, "aqc_lowest_eigs: need tol > 0, finite t, max_matvecs >= max_basis");
+  if (!ws || !aligned16(ws) || (start && !aligned16(start)) || (ground_out && !aligned16(ground_out)))
+    return fail(AQC_EINVAL, "aqc_lowest_eigs: workspace/start must be 16-byte aligned device memory");
+  const LzLayout L = lz_layout(h, dtype, m);
+  if (ws_bytes < L.total) return fail(AQC_ENOMEM, "aqc_lowest_eigs: workspace too small");
+  const int64_t N = h->dim;
+  if (N < m) return fail(AQC_EINVAL, "aqc_lowest_eigs: max_basis exceeds the dimension");
+  char* base = reinterpret_cast<char*>(ws);
+  // basis vectors vb bytes apart (16-byte aligned); N amplitudes used in each
+  auto V = [&](int j) { return (void*)(base + L.v + (size_t)j * L.vb); };
+  void* w = base + L.w;
+  void* hbuf = L.hbuf == (size_t)-1 ? nullptr : base + L.hbuf;
+  double* coef = reinterpret_cast<double*>(base + L.coef);  // c1[2m], c2[2m], norm
+  double* ymat = reinterpret_cast<double*>(base + L.ymat);
+  const int64_t nb = lz_blocks(N);
+  STCHK(ensure_parts(ctx, (size_t)2 * m * nb + 16));
+  hipStream_t s = ctx->stream;
+  const int64_t stride = (int64_t)(L.vb / (dtype == 0 ? 8 : 16));  // amplitudes between basis vectors
+
+  // first vector: the given start or a fixed pseudo-random state, normalised
+  if (start) HIPCHK(launch_copy(V(0), start, dtype, N, s));
+  else HIPCHK(launch_random_fill(V(0), dtype, N, 0x5EEDull, s));
+  double n0;
+  STCHK(norm2_len(ctx, V(0), dtype, N, &n0));
+  if (!(n0 > 0.0) || !std::isfinite(n0)) return fail(AQC_EINVAL, "aqc_lowest_eigs: zero or non-finite start");
+  HIPCHK(launch_scale_copy(V(0), V(0), dtype, N, 1.0 / std::sqrt(n0), s));
+
+  std::vector<cd> T((size_t)m * m, cd(0.0, 0.0));
+  std::vector<double> host(4 * kLzMaxBasis + 2);
+  int keep = 0, nmv = 0;
+  const int kk = std::min(m - 2, std::max(n_eig + 4, 2 * n_eig));
+  std::vector<double> theta;
+  std::vector<cd> Y;
+  double beta = 0.0;
+  int m_eff = m;
+  bool converged = false;
+  while (true) {
+    m_eff = m;
+    bool invariant = false;
+    for (int j = keep; j < m; ++j) {
+      EpiDesc e = epi_zero();
+      e.out[0] = w;
+      e.scale[0] = 1.0;
+      e.br[0] = 1.0;
+      STCHK(run_matvec(ctx, h, dtype, t, 0.0, V(j), hbuf, e));
+      ++nmv;
+      // classical Gram-Schmidt twice against V_0..V_j
+      for (int pass = 0; pass < 2; ++pass) {
+        double* c = coef + pass * 2 * kLzMaxBasis;
+        HIPCHK(launch_multidot(V(0), stride, N, j + 1, w, dtype, ctx->parts, s));
+        HIPCHK(launch_reduce_sum(ctx->parts, nb, 2 * (j + 1), c, s));
+        HIPCHK(launch_multiaxpy(V(0), stride, N, j + 1, c, w, dtype, ctx->parts, s));
+      }
+      HIPCHK(launch_reduce_sum(ctx->parts, nb, 1, coef + 4 * kLzMaxBasis, s));
+      HIPCHK(hipMemcpyAsync(host.data(), coef, (4 * kLzMaxBasis + 1) * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int i = 0; i <= j; ++i) {
+        const cd ci(host[2 * i] + host[2 * kLzMaxBasis + 2 * i],
+                    host[2 * i + 1] + host[2 * kLzMaxBasis + 2 * i + 1]);
+        T[(size_t)i * m + j] = ci;
+        T[(size_t)j * m + i] = std::conj(ci);
+      }
+      T[(size_t)j * m + j] = cd(T[(size_t)j * m + j].real(), 0.0);
+      beta = std::sqrt(std::max(host[4 * kLzMaxBasis], 0.0));
+      double tnorm = 0.0;
+      for (int i = 0; i <= j; ++i) tnorm = std::max(tnorm, std::abs(T[(size_t)i * m + i]));
+      if (beta <= 1e-13 * std::max(1.0, tnorm)) {
+        // the Krylov space is exhausted: an invariant subspace
+        m_eff = j + 1;
+        invariant = true;
+        break;
+      }
+      if (j + 1 < m) HIPCHK(launch_scale_copy(V(j + 1), w, dtype, N, 1.0 / beta, s));
+    }
+    std::vector<cd> Tm((size_t)m_eff * m_eff);
+    for (int i = 0; i < m_eff; ++i)
+      for (int k = 0; k < m_eff; ++k) Tm[(size_t)i * m_eff + k] = T[(size_t)i * m + k];
+    hermitian_jacobi(m_eff, Tm, theta, Y);
+    const int ne = std::min(n_eig, m_eff);
+    converged = true;
+    for (int i = 0; i < ne; ++i) {
+      const double r = invariant ? 0.0 : beta * std::abs(Y[(size_t)(m_eff - 1) * m_eff + i]);
+      resid[i] = r;
+      evals[i] = theta[i];
+      if (r > tol * std::max(1.0, std::fabs(theta[i]))) converged = false;
+    }
+    for (int i = ne; i < n_eig; ++i) {
+      evals[i] = NAN;
+      resid[i] = NAN;
+    }
+    if (converged || invariant || nmv >= max_matvecs) break;
+    // thick restart: keep the kk lowest Ritz vectors, continue from the residual
+    std::vector<double> yh((size_t)2 * m * kk);
+    for (int j = 0; j < m; ++j)
+      for (int i = 0; i < kk; ++i) {
+        yh[2 * ((size_t)j * kk + i)] = Y[(size_t)j * m + i].real();
+        yh[2 * ((size_t)j * kk + i) + 1] = Y[(size_t)j * m + i].imag();
+      }
+    HIPCHK(hipMemcpyAsync(ymat, yh.data(), yh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_basis_transform(V(0), stride, N, m, kk, ymat, dtype, s));
+    HIPCHK(launch_scale_copy(V(kk), w, dtype, N, 1.0 / beta, s));
+    HIPCHK(hipStreamSynchronize(s));  // yh is freed at the end of this scope
+    std::fill(T.begin(), T.end(), cd(0.0, 0.0));
+    for (int i = 0; i < kk; ++i) T[(size_t)i * m + i] = theta[i];
+    keep = kk;
+  }
+  *matvecs = nmv;
+  if (ground_out) {
+    // the lowest Ritz vector sum_j V_j Y[j][0], normalised by construction
+    std::vector<double> y0((size_t)2 * m_eff);
+    for (int j = 0; j < m_eff; ++j) {
+      y0[2 * j] = Y[(size_t)j * m_eff].real();
+      y0[2 * j + 1] = Y[(size_t)j * m_eff].imag();
+    }
+    HIPCHK(hipMemcpyAsync(ymat, y0.data(), y0.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_basis_transform(V(0), stride, N, m_eff, 1, ymat, dtype, s));
+    HIPCHK(launch_copy(ground_out, V(0), dtype, N, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  if (!converged && nmv >= max_matvecs)
+    return fail(AQC_EUNSTABLE, "aqc_lowest_eigs: not converged within max_matvecs (values are the "
+                               "last Ritz values)");
   return AQC_OK;
 }
 
@@ -1434,7 +2006,7 @@ struct Evolver {
 // Bytes of the low part of a compensated complex64 state: a bfloat16 pair per
 // amplitude, rounded up to keep what follows aligned.
 static size_t comp_bytes(const aqc_ham* h) {
-  return ((((size_t)1 << h->n) * 4) + 255) & ~(size_t)255;
+  return ((size_t)h->dim * 4 + 255) & ~(size_t)255;
 }
 
 // Lay out the solve vectors in a workspace: y^p, four history vectors (pc4) or
@@ -1551,7 +2123,7 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
   ev.h = h;
   ev.dtype = dtype;
   ev.shift = shift;
-  ev.N = (int64_t)1 << h->n;
+  ev.N = h->dim;
   ev.vb = vec_bytes(h, dtype);
   ev.method = o->method;
   char* w = reinterpret_cast<char*>(ws);
@@ -1577,7 +2149,7 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
   ev.errbuf = ctx->dres + 8;  // up to 56 per-step estimates per window
   if (adaptive && o->window > 56) return fail(AQC_EINVAL, "aqc_evolve: window must be <= 56");
 
-  STCHK(aqc_norm2(ctx, psi, dtype, h->n, &stats->norm2_initial));
+  STCHK(norm2_len(ctx, psi, dtype, h->dim, &stats->norm2_initial));
   std::vector<double> segs;  // recorded (t_s, h, k)
   auto record = [&](const SegStepper& s) {
     if (s.k <= 0) return;
@@ -1768,7 +2340,7 @@ extern "C" aqc_status aqc_evolve(aqc_ctx* ctx, const aqc_ham* h, void* psi, int 
     const double ph = -shift * (t1 - t0);
     HIPCHK(launch_scale(psi, dtype, ev.N, std::cos(ph), std::sin(ph), ctx->stream));
   }
-  STCHK(aqc_norm2(ctx, psi, dtype, h->n, &stats->norm2_final));
+  STCHK(norm2_len(ctx, psi, dtype, h->dim, &stats->norm2_final));
   stats->t_reached = t1;
   return AQC_OK;
 }
@@ -1903,6 +2475,7 @@ extern "C" aqc_status aqc_batch_admit(aqc_batch* b, const aqc_ham* h, void* psi,
   if (!b || !slot) return fail(AQC_EINVAL, "aqc_batch_admit: NULL argument");
   *slot = -1;
   STCHK(check_common(b->ctx, h, b->dtype));
+  if (h->sector_w >= 0) return fail(AQC_ENOTSUP, "aqc_batch_admit: sectors are solved with aqc_evolve");
   if (!psi || !ws) return fail(AQC_EINVAL, "aqc_batch_admit: NULL state or workspace");
   if (!aligned16(psi) || !aligned16(ws)) return fail(AQC_EINVAL, "aqc_batch_admit: 16-byte alignment");
   if (!std::isfinite(t0) || !std::isfinite(t1) || !(t1 > t0) || n_steps < 1 || !std::isfinite(shift))

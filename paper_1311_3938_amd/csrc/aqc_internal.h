@@ -117,6 +117,52 @@ struct RegPassArgs {
   double cb[12];      // coefficient of the flip of bit hb + b
 };
 
+// ---- Hamming-weight sector ---------------------------------------------------
+// A state of the sector of weight w holds the C(n, w) amplitudes of the basis
+// states with w one-bits, at the rank r(z) = sum_k C(p_k, k + 1) over the set
+// bits p_0 < p_1 < ... of z (increasing order of z).  Ranks fit in 32 bits for
+// n <= 34.
+constexpr int kSecThreads = 256;
+constexpr int kSecEPT = 4;          // consecutive ranks per thread and chunk
+constexpr int kSecMaxN = 34;
+constexpr int kSecBinom = 35;       // binomial table C(p, k), p, k <= 34
+constexpr int kSecMaxChunks = 9;    // 4-bit chunks of the rank table
+constexpr int kSecMaxHopTerms = 1024;
+constexpr int kSecGrid = 4096;      // at most this many workgroups per launch
+
+// A weight-preserving flip of two bits and its terms (as DevGroup).
+struct SecHop {
+  uint64_t x;
+  int32_t t0, nt;
+};
+// The diagonal terms sharing one mask of one or two bits (q < 0: one bit p).
+struct SecMask {
+  int32_t p, q;
+  int32_t t0, nt;
+};
+struct SectorDev {
+  int32_t n, w;
+  int32_t zero_bits;   // 1: the diagonal is summed over the 0-bits of z
+  int32_t nch;         // 4-bit chunks of n
+  int32_t nhops, nhterms;
+  int32_t nmasks, nres;
+  int64_t dim;         // C(n, w)
+  const uint32_t* binom;   // [kSecBinom][kSecBinom]
+  const uint32_t* rtab;    // [nch][16][w + 1]: rank part of a chunk given the 1-bits below it
+  const SecHop* hops;
+  const DevTerm* hterms;
+  const SecMask* masks;
+  const DevTerm* mterms;
+  const DevTerm* res;      // diagonal terms with three or more bits
+};
+struct SectorArgs {
+  SectorDev s;
+  const void* src;
+  double f[kMaxSched];
+  double dconst;       // identity terms minus the shift
+  EpiDesc epi;
+};
+
 // ---- launchers (aqc_kernels.hip) -------------------------------------------
 hipError_t launch_regpass(const RegPassArgs& a, int dtype, hipStream_t s);
 // workgroups of a register pass over n qubits
@@ -160,5 +206,38 @@ hipError_t launch_scale(void* y, int dtype, int64_t N, double re, double im, hip
 hipError_t launch_copy(void* dst, const void* src, int dtype, int64_t N, hipStream_t s);
 // zero `bytes` (a multiple of 16) with a fill kernel
 hipError_t launch_zero(void* dst, size_t bytes, hipStream_t s);
+// sector: (H - c) u with the last pass's epilogue (a.epi), per-block
+// reductions into a.epi.red over sector_blocks() blocks
+int64_t sector_blocks(int64_t dim);
+hipError_t launch_sector_matvec(const SectorArgs& a, int dtype, hipStream_t s);
+// sector diagonal: mode 0 per-block min and max -> parts[2][nb]; mode 1
+// mass of psi where the diagonal is <= thr -> parts[nb]
+hipError_t launch_sector_diag(const SectorArgs& a, int mode, double thr, const void* psi, int dtype,
+                              double* parts, hipStream_t s);
+// sector <-> full space: full[z(r)] = sec[r] (full zeroed elsewhere by the caller)
+hipError_t launch_sector_expand(const SectorDev& sd, const void* sec, void* full, int dtype,
+                                hipStream_t s);
+// y[i] = v for i < N
+hipError_t launch_fill(void* y, int dtype, int64_t N, double re, double im, hipStream_t s);
+
+// ---- Lanczos basis operations (lowest eigenvalues) -----------------------------
+// The basis holds vectors V_j = base + j * stride (N <= stride amplitudes each).
+constexpr int kLzMaxBasis = 48;
+constexpr int kLzMaxKeep = 16;
+constexpr int kLzGroup = 8;          // vectors per dot-product pass
+// c_j = <V_j, w>, j < k: partials parts[2j][nb] (re), parts[2j+1][nb] (im)
+int64_t lz_blocks(int64_t N);
+hipError_t launch_multidot(const void* base, int64_t stride, int64_t N, int k, const void* w, int dtype,
+                           double* parts, hipStream_t s);
+// w -= sum_{j<k} c_j V_j (c: device double2[k]) and |w|^2 partials -> parts[nb]
+hipError_t launch_multiaxpy(const void* base, int64_t stride, int64_t N, int k, const double* c, void* w,
+                            int dtype, double* parts, hipStream_t s);
+// dst = src * a (real)
+hipError_t launch_scale_copy(void* dst, const void* src, int dtype, int64_t N, double a, hipStream_t s);
+// V_i <- sum_{j<m} V_j Y[j][i] for i < kk, in place (Y: device double2[m][kk])
+hipError_t launch_basis_transform(void* base, int64_t stride, int64_t N, int m, int kk, const double* Y,
+                                  int dtype, hipStream_t s);
+// a fixed pseudo-random state: components uniform in [-1, 1) from a counter hash
+hipError_t launch_random_fill(void* y, int dtype, int64_t N, uint64_t seed, hipStream_t s);
 
 }  // namespace aqc

@@ -1089,4 +1089,560 @@ hipError_t launch_copy(void* dst, const void* src, int dtype, int64_t N, hipStre
   return hipMemcpyAsync(dst, src, (size_t)N * (dtype == 0 ? 8 : 16), hipMemcpyDeviceToDevice, s);
 }
 
+// ---------------------------------------------------------------------------
+// Hamming-weight sector (Sec. III.A.2-3): H^xy, H^xyz and a diagonal H_f keep
+// the number of 1-bits, so a state of weight w lives on C(n, w) amplitudes
+// stored by rank.  A workgroup walks chunks of kSecThreads * kSecEPT
+// consecutive ranks; each thread unranks its first rank once and steps to the
+// next states of the same weight with Gosper's successor.  A weight-preserving
+// hop of two differing bits reaches the partner at rank r(z ^ x), read from
+// the 4-bit chunk table; the diagonal is summed over the set bits (or the
+// zero bits, whichever are fewer) from per-bit and pairwise coefficients.
+// ---------------------------------------------------------------------------
+struct SecLds {
+  uint32_t binom[kSecBinom * kSecBinom];
+  uint32_t rtab[kSecMaxChunks * 16 * (kSecMaxN + 1)];
+  double hsh[kSecMaxN];      // one-bit coefficients h_p (sigma^z_p)
+  double rsh[kSecMaxN];      // R_p = sum_q J_pq
+  double a[kSecMaxN];        // per-bit part of the diagonal
+  double J[kSecMaxN * kSecMaxN];
+  uint64_t nbr[kSecMaxN];    // bits q < p with J_pq != 0
+  double fsh[kMaxSched];
+  double c0;
+  double red[3 * (kSecThreads / 64)];
+};
+
+// Coefficients at this time: with s_q = 1 - 2 b_q the diagonal
+//   D(z) = dconst + sum_q h_q s_q + sum_{p<q} J_pq s_p s_q + (3+ bit terms)
+// becomes c0 + sum_{p in S} a_p + 4 sum_{q<p in S} J_pq over the set S of the
+// one-bits (a_p = -2 (h_p + R_p), c0 = dconst + sum h + sum_{p<q} J) or of the
+// zero bits (a_p = 2 (h_p - R_p), c0 = dconst - sum h + sum_{p<q} J).
+__device__ void sector_setup(const SectorArgs& a, SecLds& L) {
+  const int tid = threadIdx.x;
+  const SectorDev& s = a.s;
+  const int n = s.n;
+  if (tid < kMaxSched) L.fsh[tid] = a.f[tid];
+  for (int i = tid; i < kSecBinom * kSecBinom; i += kSecThreads) L.binom[i] = s.binom[i];
+  const int nrt = s.nch * 16 * (s.w + 1);
+  for (int i = tid; i < nrt; i += kSecThreads) L.rtab[i] = s.rtab[i];
+  for (int i = tid; i < n * n; i += kSecThreads) L.J[i] = 0.0;
+  if (tid < n) L.hsh[tid] = 0.0;
+  __syncthreads();
+  for (int k = tid; k < s.nmasks; k += kSecThreads) {
+    const SecMask m = s.masks[k];
+    double c = 0.0;
+    for (int t = 0; t < m.nt; ++t) {
+      const DevTerm tt = s.mterms[m.t0 + t];
+      c += tt.w * L.fsh[tt.sid];
+    }
+    if (m.q < 0) {
+      L.hsh[m.p] = c;
+    } else {
+      L.J[m.p * n + m.q] = c;
+      L.J[m.q * n + m.p] = c;
+    }
+  }
+  __syncthreads();
+  if (tid < n) {
+    double r = 0.0;
+    uint64_t nb = 0;
+    for (int q = 0; q < n; ++q) {
+      const double j = L.J[tid * n + q];
+      r += j;
+      if (q < tid && j != 0.0) nb |= 1ull << q;
+    }
+    L.rsh[tid] = r;
+    L.nbr[tid] = nb;
+    L.a[tid] = s.zero_bits ? 2.0 * (L.hsh[tid] - r) : -2.0 * (L.hsh[tid] + r);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double hs = 0.0, js = 0.0;
+    for (int p = 0; p < n; ++p) {
+      hs += L.hsh[p];
+      js += L.rsh[p];
+    }
+    L.c0 = a.dconst + (s.zero_bits ? -hs : hs) + 0.5 * js;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double sector_diag(const SectorArgs& a, const SecLds& L, uint64_t z) {
+  const SectorDev& s = a.s;
+  const uint64_t full = (1ull << s.n) - 1ull;
+  const uint64_t S = s.zero_bits ? (~z & full) : z;
+  double d = L.c0, pj = 0.0;
+  uint64_t m = S;
+  while (m) {
+    const int p = __builtin_ctzll(m);
+    m &= m - 1ull;
+    d += L.a[p];
+    uint64_t nb = L.nbr[p] & S;
+    while (nb) {
+      const int q = __builtin_ctzll(nb);
+      nb &= nb - 1ull;
+      pj += L.J[p * s.n + q];
+    }
+  }
+  d += 4.0 * pj;
+  for (int k = 0; k < s.nres; ++k) {
+    const DevTerm t = s.res[k];
+    const double mm = t.w * L.fsh[t.sid];
+    d += (__popcll(z & t.z) & 1) ? -mm : mm;
+  }
+  return d;
+}
+
+// the basis state of weight w at rank r (largest C(p, k) <= r, bit by bit)
+__device__ __forceinline__ uint64_t sector_unrank(const uint32_t* binom, int n, int w, int64_t r) {
+  uint64_t z = 0;
+  int p = n - 1;
+  uint32_t rr = (uint32_t)r;
+  for (int k = w; k >= 1; --k) {
+    // stops at p >= k - 1, where C(k - 1, k) = 0
+    while (binom[p * kSecBinom + k] > rr) --p;
+    z |= 1ull << p;
+    rr -= binom[p * kSecBinom + k];
+    --p;
+  }
+  return z;
+}
+
+__device__ __forceinline__ uint32_t sector_rank(const uint32_t* rtab, int nch, int w1, uint64_t z) {
+  uint32_t r = 0;
+  int cnt = 0;
+  for (int c = 0; c < nch; ++c) {
+    const uint32_t nib = (uint32_t)(z >> (4 * c)) & 15u;
+    r += rtab[(c * 16 + (int)nib) * w1 + cnt];
+    cnt += __popc(nib);
+  }
+  return r;
+}
+
+// the next larger integer with the same number of 1-bits (Gosper)
+__device__ __forceinline__ uint64_t next_same_weight(uint64_t z) {
+  const uint64_t c = z & (0ull - z);
+  const uint64_t r = z + c;
+  return (((r ^ z) >> 2) >> __builtin_ctzll(c)) | r;
+}
+
+int64_t sector_blocks(int64_t dim) {
+  const int64_t per = (int64_t)kSecThreads * kSecEPT;
+  const int64_t nb = (dim + per - 1) / per;
+  return nb < 1 ? 1 : (nb > kSecGrid ? kSecGrid : nb);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kSecThreads) void k_sector(const SectorArgs a) {
+  using V = typename CT2<R>::V;
+  __shared__ SecLds L;
+  __shared__ R tm[kSecMaxHopTerms];
+  sector_setup(a, L);
+  const SectorDev& s = a.s;
+  for (int k = threadIdx.x; k < s.nhterms; k += kSecThreads) {
+    const DevTerm t = s.hterms[k];
+    tm[k] = (R)(t.w * L.fsh[t.sid]);
+  }
+  __syncthreads();
+  const V* __restrict__ src = reinterpret_cast<const V*>(a.src);
+  const EpiDesc& e = a.epi;
+  const bool has_comp = e.comp != nullptr;
+  uint32_t* __restrict__ compv = reinterpret_cast<uint32_t*>(e.comp);
+  const int w1 = s.w + 1;
+  double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+  const int64_t per = (int64_t)kSecThreads * kSecEPT;
+  for (int64_t base = (int64_t)blockIdx.x * per; base < s.dim; base += (int64_t)gridDim.x * per) {
+    const int64_t rf = base + (int64_t)threadIdx.x * kSecEPT;
+    uint64_t zs[kSecEPT];
+    bool ok[kSecEPT];
+    uint64_t z = rf < s.dim ? sector_unrank(L.binom, s.n, s.w, rf) : 0ull;
+#pragma unroll
+    for (int u = 0; u < kSecEPT; ++u) {
+      ok[u] = rf + u < s.dim;
+      zs[u] = z;
+      if (u + 1 < kSecEPT && rf + u + 1 < s.dim) z = next_same_weight(z);
+    }
+    R hr[kSecEPT], hi[kSecEPT];
+#pragma unroll
+    for (int u = 0; u < kSecEPT; ++u) hr[u] = hi[u] = 0;
+    for (int k = 0; k < s.nhops; ++k) {
+      const SecHop hp = s.hops[k];
+#pragma unroll
+      for (int u = 0; u < kSecEPT; ++u) {
+        if (!ok[u] || __popcll(zs[u] & hp.x) != 1) continue;
+        const uint64_t zp = zs[u] ^ hp.x;
+        // a weight-w state has a rank below dim; the clamp only guards the read
+        const uint32_t rp = sector_rank(L.rtab, s.nch, w1, zp);
+        const V pv = src[min((int64_t)rp, s.dim - 1)];
+        R cr = 0, ci = 0;
+        for (int t = 0; t < hp.nt; ++t) {
+          const DevTerm tt = s.hterms[hp.t0 + t];
+          R m = tm[hp.t0 + t];
+          if (__popcll(zp & tt.z) & 1) m = -m;
+          switch (tt.p & 3) {
+            case 0: cr += m; break;
+            case 1: ci += m; break;
+            case 2: cr -= m; break;
+            default: ci -= m; break;
+          }
+        }
+        hr[u] += cr * pv.x - ci * pv.y;
+        hi[u] += cr * pv.y + ci * pv.x;
+      }
+    }
+    // epilogue: the same update as the last tile pass (see EpiDesc)
+#pragma unroll
+    for (int u = 0; u < kSecEPT; ++u) {
+      if (!ok[u]) continue;
+      const int64_t g = rf + u;
+      const V uq = src[g];
+      const double d = sector_diag(a, L, zs[u]);
+      const R hrr = (R)(d * (double)uq.x + (double)hr[u]);
+      const R hii = (R)(d * (double)uq.y + (double)hi[u]);
+      V xin[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        xin[i] = e.in[i] ? ldnt(reinterpret_cast<const V*>(e.in[i]) + g) : V{0, 0};
+      V lo{0, 0};
+      if (has_comp) {
+        const uint32_t pk = __builtin_nontemporal_load(compv + g);
+        lo = V{(R)bf16_lo(pk), (R)bf16_hi(pk)};
+      }
+#pragma unroll
+      for (int o = 0; o < 3; ++o) {
+        if (!e.out[o]) continue;
+        R ir = (R)e.br[o] * hrr - (R)e.bi[o] * hii;
+        R ii = (R)e.br[o] * hii + (R)e.bi[o] * hrr;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          ir += (R)e.a[o][i] * xin[i + 1].x;
+          ii += (R)e.a[o][i] * xin[i + 1].y;
+        }
+        const R shh = (R)e.scale[o], sll = (R)(e.scale[o] - (double)shh);
+        R vr = shh * ir + sll * ir;
+        R vi = shh * ii + sll * ii;
+        if (e.comp_flags & (1 << o)) {
+          vr += lo.x;
+          vi += lo.y;
+        }
+        const R bre = (R)e.c0[o] * xin[0].x + (R)e.cu[o] * uq.x;
+        const R bim = (R)e.c0[o] * xin[0].y + (R)e.cu[o] * uq.y;
+        const R sr = bre + vr, si = bim + vi;
+        if (o == 0 && (e.comp_flags & 8)) {
+          const R tr = sr - bre, ti = si - bim;
+          const R er = (bre - (sr - tr)) + (vr - tr);
+          const R ei = (bim - (si - ti)) + (vi - ti);
+          __builtin_nontemporal_store(pack_bf16x2((float)er, (float)ei), compv + g);
+        }
+        stnt(reinterpret_cast<V*>(e.out[o]) + g, V{sr, si});
+        if (o == 0) {
+          if (e.red_flags & 1) r0 += (double)sr * (double)sr + (double)si * (double)si;
+          if (e.red_flags & 2) {
+            const double dr = (double)sr - (double)uq.x, di = (double)si - (double)uq.y;
+            r1 += dr * dr + di * di;
+          }
+        }
+      }
+      if (e.red_flags & 4) r2 += (double)uq.x * (double)hrr + (double)uq.y * (double)hii;
+    }
+  }
+  if (e.red_flags) block_reduce3<kSecThreads>(r0, r1, r2, e.red_flags, L.red, e.red, gridDim.x, blockIdx.x);
+}
+
+hipError_t launch_sector_matvec(const SectorArgs& a, int dtype, hipStream_t s) {
+  const dim3 grid((unsigned)sector_blocks(a.s.dim)), block(kSecThreads);
+  if (dtype == 0) hipLaunchKernelGGL(k_sector<float>, grid, block, 0, s, a);
+  else hipLaunchKernelGGL(k_sector<double>, grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename V>
+__global__ __launch_bounds__(kSecThreads) void k_sector_diag(const SectorArgs a, int mode, double thr,
+                                                             const V* psi, double* parts) {
+  __shared__ SecLds L;
+  sector_setup(a, L);
+  const SectorDev& s = a.s;
+  double mn = INFINITY, mx = -INFINITY, ms = 0.0;
+  const int64_t per = (int64_t)kSecThreads * kSecEPT;
+  for (int64_t base = (int64_t)blockIdx.x * per; base < s.dim; base += (int64_t)gridDim.x * per) {
+    const int64_t rf = base + (int64_t)threadIdx.x * kSecEPT;
+    if (rf >= s.dim) continue;
+    uint64_t z = sector_unrank(L.binom, s.n, s.w, rf);
+    for (int u = 0; u < kSecEPT && rf + u < s.dim; ++u) {
+      if (u > 0) z = next_same_weight(z);
+      const double d = sector_diag(a, L, z);
+      if (mode == 0) {
+        mn = fmin(mn, d);
+        mx = fmax(mx, d);
+      } else if (d <= thr) {
+        const V v = psi[rf + u];
+        ms += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+      }
+    }
+  }
+  if (mode == 1) {
+    block_reduce3<kSecThreads>(ms, 0.0, 0.0, 1, L.red, parts, gridDim.x, blockIdx.x);
+    return;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mn = fmin(mn, __shfl_xor(mn, o, 64));
+    mx = fmax(mx, __shfl_xor(mx, o, 64));
+  }
+  constexpr int NW = kSecThreads / 64;
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    L.red[wv] = mn;
+    L.red[NW + wv] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NW; ++k) {
+      mn = fmin(mn, L.red[k]);
+      mx = fmax(mx, L.red[NW + k]);
+    }
+    parts[blockIdx.x] = mn;
+    parts[gridDim.x + blockIdx.x] = mx;
+  }
+}
+
+hipError_t launch_sector_diag(const SectorArgs& a, int mode, double thr, const void* psi, int dtype,
+                              double* parts, hipStream_t s) {
+  const dim3 grid((unsigned)sector_blocks(a.s.dim)), block(kSecThreads);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_sector_diag<float2>, grid, block, 0, s, a, mode, thr, (const float2*)psi,
+                       parts);
+  else
+    hipLaunchKernelGGL(k_sector_diag<double2>, grid, block, 0, s, a, mode, thr, (const double2*)psi,
+                       parts);
+  return hipGetLastError();
+}
+
+template <typename V>
+__global__ __launch_bounds__(kSecThreads) void k_sector_expand(const SectorDev s, const V* sec, V* full) {
+  __shared__ uint32_t binom[kSecBinom * kSecBinom];
+  for (int i = threadIdx.x; i < kSecBinom * kSecBinom; i += kSecThreads) binom[i] = s.binom[i];
+  __syncthreads();
+  for (int64_t r = (int64_t)blockIdx.x * kSecThreads + threadIdx.x; r < s.dim;
+       r += (int64_t)gridDim.x * kSecThreads)
+    full[sector_unrank(binom, s.n, s.w, r)] = sec[r];
+}
+
+hipError_t launch_sector_expand(const SectorDev& sd, const void* sec, void* full, int dtype,
+                                hipStream_t s) {
+  int64_t nb = (sd.dim + kSecThreads - 1) / kSecThreads;
+  if (nb > 65536) nb = 65536;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_sector_expand<float2>, dim3((unsigned)nb), dim3(kSecThreads), 0, s, sd,
+                       (const float2*)sec, (float2*)full);
+  else
+    hipLaunchKernelGGL(k_sector_expand<double2>, dim3((unsigned)nb), dim3(kSecThreads), 0, s, sd,
+                       (const double2*)sec, (double2*)full);
+  return hipGetLastError();
+}
+
+template <typename V>
+__global__ void k_fill(V* y, int64_t N, V v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = v;
+}
+
+hipError_t launch_fill(void* y, int dtype, int64_t N, double re, double im, hipStream_t s) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_fill<float2>, dim3(ew_blocks(N)), dim3(256), 0, s, (float2*)y, N,
+                       float2{(float)re, (float)im});
+  else
+    hipLaunchKernelGGL(k_fill<double2>, dim3(ew_blocks(N)), dim3(256), 0, s, (double2*)y, N,
+                       double2{re, im});
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos basis operations (lowest eigenvalues of H(t), Sec. IV.B).  Every
+// sum is formed in float64; the basis vectors keep the state's type.
+// ---------------------------------------------------------------------------
+int64_t lz_blocks(int64_t N) {
+  int64_t nb = (N + (int64_t)kRedThreads * 8 - 1) / ((int64_t)kRedThreads * 8);
+  return nb < 1 ? 1 : (nb > 4096 ? 4096 : nb);
+}
+
+// blockIdx.y picks a group of kLzGroup basis vectors
+template <typename V>
+__global__ __launch_bounds__(kRedThreads) void k_multidot(const V* base, int64_t stride, int64_t N, int k,
+                                                          const V* w, double* parts) {
+  __shared__ double sb[2 * kLzGroup * (kRedThreads / 64)];
+  const int j0 = blockIdx.y * kLzGroup;
+  const int ng = min(kLzGroup, k - j0);
+  double re[kLzGroup], im[kLzGroup];
+#pragma unroll
+  for (int j = 0; j < kLzGroup; ++j) re[j] = im[j] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    const V b = w[i];
+#pragma unroll
+    for (int j = 0; j < kLzGroup; ++j) {
+      if (j < ng) {
+        const V a = base[(int64_t)(j0 + j) * stride + i];
+        re[j] += (double)a.x * (double)b.x + (double)a.y * (double)b.y;
+        im[j] += (double)a.x * (double)b.y - (double)a.y * (double)b.x;
+      }
+    }
+  }
+  constexpr int NW = kRedThreads / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < kLzGroup; ++j) {
+    const double r = wave_sum(re[j]), q = wave_sum(im[j]);
+    if (lane == 0) {
+      sb[(2 * j) * NW + wv] = r;
+      sb[(2 * j + 1) * NW + wv] = q;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * ng) {
+    double acc = 0.0;
+    for (int v = 0; v < NW; ++v) acc += sb[threadIdx.x * NW + v];
+    parts[(int64_t)(2 * j0 + threadIdx.x) * gridDim.x + blockIdx.x] = acc;
+  }
+}
+
+hipError_t launch_multidot(const void* base, int64_t stride, int64_t N, int k, const void* w, int dtype,
+                           double* parts, hipStream_t s) {
+  const dim3 grid((unsigned)lz_blocks(N), (unsigned)((k + kLzGroup - 1) / kLzGroup));
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_multidot<float2>, grid, dim3(kRedThreads), 0, s, (const float2*)base, stride, N,
+                       k, (const float2*)w, parts);
+  else
+    hipLaunchKernelGGL(k_multidot<double2>, grid, dim3(kRedThreads), 0, s, (const double2*)base, stride,
+                       N, k, (const double2*)w, parts);
+  return hipGetLastError();
+}
+
+template <typename V>
+__global__ __launch_bounds__(kRedThreads) void k_multiaxpy(const V* base, int64_t stride, int64_t N,
+                                                           int k, const double* c, V* w, double* parts) {
+  __shared__ double cs[2 * kLzMaxBasis];
+  __shared__ double sb[3 * (kRedThreads / 64)];
+  if (threadIdx.x < 2 * k) cs[threadIdx.x] = c[threadIdx.x];
+  __syncthreads();
+  double nrm = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    const V b = w[i];
+    double xr = (double)b.x, xi = (double)b.y;
+    for (int j = 0; j < k; ++j) {
+      const V a = base[(int64_t)j * stride + i];
+      const double cr = cs[2 * j], ci = cs[2 * j + 1];
+      xr -= cr * (double)a.x - ci * (double)a.y;
+      xi -= cr * (double)a.y + ci * (double)a.x;
+    }
+    const V o{(decltype(b.x))xr, (decltype(b.x))xi};
+    w[i] = o;
+    nrm += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
+  }
+  block_reduce3<kRedThreads>(nrm, 0.0, 0.0, 1, sb, parts, gridDim.x, blockIdx.x);
+}
+
+hipError_t launch_multiaxpy(const void* base, int64_t stride, int64_t N, int k, const double* c, void* w,
+                            int dtype, double* parts, hipStream_t s) {
+  const dim3 grid((unsigned)lz_blocks(N));
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_multiaxpy<float2>, grid, dim3(kRedThreads), 0, s, (const float2*)base, stride, N,
+                       k, c, (float2*)w, parts);
+  else
+    hipLaunchKernelGGL(k_multiaxpy<double2>, grid, dim3(kRedThreads), 0, s, (const double2*)base, stride,
+                       N, k, c, (double2*)w, parts);
+  return hipGetLastError();
+}
+
+template <typename V, typename R>
+__global__ void k_scale_copy(V* dst, const V* src, int64_t N, double a) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const V v = src[i];
+    dst[i] = V{(R)((double)v.x * a), (R)((double)v.y * a)};
+  }
+}
+
+hipError_t launch_scale_copy(void* dst, const void* src, int dtype, int64_t N, double a, hipStream_t s) {
+  if (dtype == 0)
+    hipLaunchKernelGGL((k_scale_copy<float2, float>), dim3(ew_blocks(N)), dim3(256), 0, s, (float2*)dst,
+                       (const float2*)src, N, a);
+  else
+    hipLaunchKernelGGL((k_scale_copy<double2, double>), dim3(ew_blocks(N)), dim3(256), 0, s,
+                       (double2*)dst, (const double2*)src, N, a);
+  return hipGetLastError();
+}
+
+// One wave per workgroup; a lane stages the m components of its row in LDS,
+// then writes the kk combinations over the first kk vectors (each row is read
+// completely before any of its outputs is written).
+constexpr int kLzTfThreads = 64;
+template <typename V>
+__global__ __launch_bounds__(kLzTfThreads) void k_basis_transform(V* base, int64_t stride, int64_t N, int m,
+                                                                  int kk, const double* Y) {
+  __shared__ V row[kLzMaxBasis * kLzTfThreads];
+  __shared__ double ys[2 * kLzMaxBasis * kLzMaxKeep];
+  for (int i = threadIdx.x; i < 2 * m * kk; i += kLzTfThreads) ys[i] = Y[i];
+  __syncthreads();
+  for (int64_t r = (int64_t)blockIdx.x * kLzTfThreads + threadIdx.x; r < N;
+       r += (int64_t)gridDim.x * kLzTfThreads) {
+    for (int j = 0; j < m; ++j) row[j * kLzTfThreads + threadIdx.x] = base[(int64_t)j * stride + r];
+    for (int i = 0; i < kk; ++i) {
+      double xr = 0.0, xi = 0.0;
+      for (int j = 0; j < m; ++j) {
+        const V a = row[j * kLzTfThreads + threadIdx.x];
+        const double yr = ys[2 * (j * kk + i)], yi = ys[2 * (j * kk + i) + 1];
+        xr += (double)a.x * yr - (double)a.y * yi;
+        xi += (double)a.x * yi + (double)a.y * yr;
+      }
+      base[(int64_t)i * stride + r] = V{(decltype(V{}.x))xr, (decltype(V{}.x))xi};
+    }
+  }
+}
+
+hipError_t launch_basis_transform(void* base, int64_t stride, int64_t N, int m, int kk, const double* Y,
+                                  int dtype, hipStream_t s) {
+  int64_t nb = (N + kLzTfThreads - 1) / kLzTfThreads;
+  if (nb > 8192) nb = 8192;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_basis_transform<float2>, dim3((unsigned)nb), dim3(kLzTfThreads), 0, s,
+                       (float2*)base, stride, N, m, kk, Y);
+  else
+    hipLaunchKernelGGL(k_basis_transform<double2>, dim3((unsigned)nb), dim3(kLzTfThreads), 0, s,
+                       (double2*)base, stride, N, m, kk, Y);
+  return hipGetLastError();
+}
+
+// splitmix64 (Steele, Lea and Flood 2014) of the element index
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+template <typename V, typename R>
+__global__ void k_random_fill(V* y, int64_t N, uint64_t seed) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t a = splitmix64(seed ^ (2ull * (uint64_t)i));
+    const uint64_t b = splitmix64(seed ^ (2ull * (uint64_t)i + 1ull));
+    const double ur = (double)(a >> 11) * (1.0 / 9007199254740992.0);
+    const double ui = (double)(b >> 11) * (1.0 / 9007199254740992.0);
+    y[i] = V{(R)(2.0 * ur - 1.0), (R)(2.0 * ui - 1.0)};
+  }
+}
+
+hipError_t launch_random_fill(void* y, int dtype, int64_t N, uint64_t seed, hipStream_t s) {
+  if (dtype == 0)
+    hipLaunchKernelGGL((k_random_fill<float2, float>), dim3(ew_blocks(N)), dim3(256), 0, s, (float2*)y, N,
+                       seed);
+  else
+    hipLaunchKernelGGL((k_random_fill<double2, double>), dim3(ew_blocks(N)), dim3(256), 0, s,
+                       (double2*)y, N, seed);
+  return hipGetLastError();
+}
+
 }  // namespace aqc

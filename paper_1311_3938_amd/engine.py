@@ -84,6 +84,11 @@ class Hamiltonian:
     def handle(self):
         return self._h
 
+    @property
+    def dim(self):
+        """Amplitudes of a state: 2^n (a sector: C(n, w))."""
+        return int(lib().aqc_ham_dim(self._h))
+
     def info(self):
         i = L.HamInfo()
         check(lib().aqc_ham_info(self._h, C.byref(i)))
@@ -114,13 +119,40 @@ class Hamiltonian:
             pass
 
 
-def _check_state(ctx, ham_n, psi):
+class Sector(Hamiltonian):
+    """A Hamiltonian that keeps the Hamming weight, restricted to the C(n, w)
+    basis states of weight w (Sec. III.A.2-3), stored by increasing z.
+    apply, evolve, energy, ground_mass and spectral_bounds take it like a
+    Hamiltonian, on states of C(n, w) amplitudes."""
+
+    def __init__(self, ctx: Context, ham: Hamiltonian, weight: int):
+        self.ctx = ctx
+        self.n = ham.n
+        self.weight = int(weight)
+        h = C.c_void_p()
+        check(lib().aqc_sector_create(ctx.handle, ham.handle, self.weight, C.byref(h)))
+        self._h = h
+
+    def dicke(self, dtype=torch.complex64):
+        """eq. (initstate): every amplitude of the sector C(n, w)^{-1/2}."""
+        psi = torch.empty(self.dim, dtype=dtype, device=self.ctx.device)
+        check(lib().aqc_sector_dicke(self.ctx.handle, self._h, _ptr(psi), dtype_code(psi)))
+        return psi
+
+    def expand(self, psi):
+        """The 2^n state with the sector's amplitudes and zeros elsewhere."""
+        out = torch.empty(1 << self.n, dtype=psi.dtype, device=psi.device)
+        check(lib().aqc_sector_expand(self.ctx.handle, self._h, _ptr(psi), _ptr(out), dtype_code(psi)))
+        return out
+
+
+def _check_state(ctx, ham, psi):
     if psi.device != ctx.device:
         raise ValueError("state is not on the context's device")
     if not psi.is_contiguous():
         raise ValueError("state must be contiguous")
-    if psi.numel() != (1 << ham_n):
-        raise ValueError(f"state has {psi.numel()} amplitudes, expected 2^{ham_n}")
+    if psi.numel() != ham.dim:
+        raise ValueError(f"state has {psi.numel()} amplitudes, expected {ham.dim}")
     return dtype_code(psi)
 
 
@@ -132,7 +164,7 @@ def workspace(ctx, nbytes):
 
 def apply(ctx: Context, ham: Hamiltonian, t: float, psi: torch.Tensor, out=None, ws=None):
     """out = H(t) psi."""
-    dt = _check_state(ctx, ham.n, psi)
+    dt = _check_state(ctx, ham, psi)
     if out is None:
         out = torch.empty_like(psi)
     need = lib().aqc_apply_workspace_bytes(ham.handle, dt)
@@ -192,7 +224,7 @@ def evolve(ctx: Context, ham: Hamiltonian, psi: torch.Tensor, t0: float, t1: flo
     carry (from new_carry()): continue a chain of fixed-step pc4 calls; psi is
     then left in the shifted frame, psi(t1) = complex(carry.phase_re,
     carry.phase_im) * psi, and the same workspace tensor must be passed again."""
-    dt = _check_state(ctx, ham.n, psi)
+    dt = _check_state(ctx, ham, psi)
     opts, keep, rec = evolve_opts(**kw)
     if carry is not None:
         opts.carry = C.pointer(carry)
@@ -211,15 +243,16 @@ def evolve(ctx: Context, ham: Hamiltonian, psi: torch.Tensor, t0: float, t1: flo
 
 def norm2(ctx, psi):
     out = C.c_double()
-    check(lib().aqc_norm2(ctx.handle, _ptr(psi), dtype_code(psi), int(math.log2(psi.numel())),
-                          C.byref(out)))
+    check(lib().aqc_norm2_len(ctx.handle, _ptr(psi), dtype_code(psi), psi.numel(), C.byref(out)))
     return out.value
 
 
 def overlap(ctx, phi, psi):
     re, im = C.c_double(), C.c_double()
-    check(lib().aqc_overlap(ctx.handle, _ptr(phi), _ptr(psi), dtype_code(psi),
-                            int(math.log2(psi.numel())), C.byref(re), C.byref(im)))
+    if phi.numel() != psi.numel() or phi.dtype != psi.dtype:
+        raise ValueError("overlap of states of different shapes or types")
+    check(lib().aqc_overlap_len(ctx.handle, _ptr(phi), _ptr(psi), dtype_code(psi), psi.numel(),
+                                C.byref(re), C.byref(im)))
     return complex(re.value, im.value)
 
 
@@ -256,6 +289,48 @@ def energy(ctx, ham, t, psi, ws=None):
                            _ptr(ws) if ws is not None else None, ws.numel() if ws is not None else 0,
                            C.byref(out)))
     return out.value
+
+
+def lowest_eigs(ctx, ham, t, k=2, dtype=torch.complex128, max_basis=24, max_matvecs=4000, tol=1e-10,
+                start=None, ws=None, ground=None):
+    """The k smallest eigenvalues of H(t) (aqc_lowest_eigs).  Returns
+    (eigenvalues, residual norms, products used); `ground` (a device state of
+    the Hamiltonian's dimension and `dtype`) receives the lowest Ritz vector."""
+    dt = L.C64 if dtype in (torch.complex64, L.C64) else L.C128
+    need = lib().aqc_lowest_eigs_workspace_bytes(ham.handle, dt, int(max_basis))
+    if need == 0:
+        raise ValueError("bad max_basis for aqc_lowest_eigs")
+    if ws is None or ws.numel() < need:
+        ws = workspace(ctx, need)
+    if start is not None:
+        _check_state(ctx, ham, start)
+        if start.dtype != dtype:
+            raise ValueError("start must have the basis dtype")
+    if ground is not None:
+        _check_state(ctx, ham, ground)
+        if ground.dtype != dtype:
+            raise ValueError("ground must have the basis dtype")
+    ev = (C.c_double * k)()
+    rs = (C.c_double * k)()
+    nmv = C.c_int()
+    check(lib().aqc_lowest_eigs(ctx.handle, ham.handle, float(t), dt, int(k), int(max_basis),
+                                int(max_matvecs), float(tol), _ptr(start) if start is not None else None,
+                                _ptr(ws), ws.numel(), ev, rs, C.byref(nmv),
+                                _ptr(ground) if ground is not None else None))
+    return np.array(ev[:]), np.array(rs[:]), nmv.value
+
+
+def hermitian_eigh(a):
+    """Eigenvalues and eigenvectors of a small Hermitian matrix with the
+    library's host solver (aqc_hermitian_eigh)."""
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+    n = a.shape[0]
+    w = np.zeros(n)
+    z = np.zeros((n, n), dtype=np.complex128)
+    dp = C.POINTER(C.c_double)
+    check(lib().aqc_hermitian_eigh(n, a.view(np.float64).ctypes.data_as(dp), w.ctypes.data_as(dp),
+                                   z.view(np.float64).ctypes.data_as(dp)))
+    return w, z
 
 
 def profile_enable(ctx, on=True):
@@ -299,7 +374,7 @@ class Batch:
     def admit(self, ham, psi, t0, t1, n_steps, shift, ws=None):
         if psi.dtype != self.dtype:
             raise TypeError("state dtype differs from the batch dtype")
-        _check_state(self.ctx, ham.n, psi)
+        _check_state(self.ctx, ham, psi)
         need = self.workspace_bytes(ham)
         if ws is None or ws.numel() < need:
             ws = workspace(self.ctx, need)

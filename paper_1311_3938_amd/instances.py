@@ -173,6 +173,54 @@ def ec3_random_clauses(n, m, rng):
     return out
 
 
+def _clause_ok_mask(n, clause, z):
+    """Assignments (int array z) in which exactly one bit of the clause is 1."""
+    a, b, c = (int(q) - 1 for q in clause)
+    return (((z >> a) & 1) + ((z >> b) & 1) + ((z >> c) & 1)) == 1
+
+
+def usa_hard_instance(n, rng, m_max=None, max_restarts=1000):
+    """A random hard EC3 instance with a unique satisfying assignment, by the
+    recipe of Sec. II.D: from the pool of all clauses, a random first clause
+    starts a graph; clauses that touch the graph and share no pair of bits
+    with it (so n_ij is 0 or 1) are added at random; once every bit is in the
+    graph, a clause that would leave no solution is discarded, and the
+    instance is done when exactly one solution is left.  The search restarts
+    when the pool is empty or m_max clauses are reached.  Returns (clauses,
+    solution).  Solutions are counted over all 2^n assignments (n <= 26);
+    below n = 7 such instances are rare, and the search gives up with an error."""
+    if not 3 <= n <= 26:
+        raise ValueError("usa_hard_instance: 3 <= n <= 26")
+    m_max = n if m_max is None else int(m_max)
+    triples = [tuple(int(q) + 1 for q in t) for t in
+               np.array([(a, b, c) for a in range(n) for b in range(a + 1, n) for c in range(b + 1, n)])]
+    z = np.arange(1 << n, dtype=np.int64)
+    for _ in range(max_restarts):
+        pool = list(triples)
+        first = pool.pop(int(rng.integers(len(pool))))
+        clauses = [first]
+        covered = set(first)
+        edges = {(first[0], first[1]), (first[0], first[2]), (first[1], first[2])}
+        ok = _clause_ok_mask(n, first, z)
+        while pool and len(clauses) < m_max:
+            # drop clauses that share a pair of bits with the graph
+            pool = [c for c in pool if not ({(c[0], c[1]), (c[0], c[2]), (c[1], c[2])} & edges)]
+            touching = [i for i, c in enumerate(pool) if covered & set(c)]
+            if not touching:
+                break
+            c = pool.pop(touching[int(rng.integers(len(touching)))])
+            new_ok = ok & _clause_ok_mask(n, c, z)
+            if len(covered | set(c)) == n and not new_ok.any():
+                continue                       # would leave no solution: discard
+            clauses.append(c)
+            covered |= set(c)
+            edges |= {(c[0], c[1]), (c[0], c[2]), (c[1], c[2])}
+            ok = new_ok
+            if len(covered) == n and int(ok.sum()) == 1:
+                return clauses, int(np.flatnonzero(ok)[0])
+    raise RuntimeError("usa_hard_instance: no instance found")
+
+
 def ec3_terms(n, clauses, omega=1.0):
     """Final Hamiltonian of EC3 in the expanded form of eq. (final_ham).
 
@@ -475,6 +523,27 @@ def workload_ec3_paths(n=13, m=10, T=20.0, kind="cbc", seed=seed_for(5)):
     if kind == "cbc":
         return clause_by_clause(n, clauses, path, meta=meta)
     raise ValueError(kind)
+
+
+def workload_usa(n, i, algorithm="xy", T=1.0, config=6):
+    """Hard instance i of size n (usa_hard_instance) with the straight-line
+    path from the initial Hamiltonian of one algorithm of Sec. III.A: "x"
+    (eq. (Hix), weights n_i/2), "xyz" (eq. (Hixyz)) or "xy" (eq. (Hixy)).
+    meta holds the clauses, the solution and its Hamming weight."""
+    rng = np.random.default_rng(seed_for(config, 1000 * n + i))
+    clauses, sol = usa_hard_instance(n, rng)
+    if algorithm == "x":
+        ni = [sum(q in c for c in clauses) for q in range(1, n + 1)]
+        hi = transverse_terms(n, weights=ni)
+    elif algorithm == "xyz":
+        hi = xyz_initial_terms(n, clauses)
+    elif algorithm == "xy":
+        hi = xy_initial_terms(n, clauses)
+    else:
+        raise ValueError(algorithm)
+    return interpolated(n, hi, ec3_terms(n, clauses), linear_path(T),
+                        meta={"kind": "usa-" + algorithm, "clauses": clauses, "solution": sol,
+                              "weight": bin(sol).count("1"), "n": n, "i": i})
 
 
 def workload_batch_member(i, n_lo=14, n_hi=22, config=3):

@@ -1,0 +1,109 @@
+"""Successful runtime T_s (Sec. III.B): the runtime at which the final energy
+E(T) = <psi(T)|H_f|psi(T)> falls to 1/2 (with E_1 = 0 and every excited level
+at least 1, E(T) <= 1/2 means a ground-state population of at least one
+half).  Every instance of a set is bracketed by doubling T and then bisected
+in log T; the evaluations of one round, one full solve per instance, run
+together in one batch (aqc_batch_*), so a round costs about one solve of
+the largest instance.  Each solve is a fixed-step pc4 run on the library."""
+from __future__ import annotations
+
+import copy
+import math
+from dataclasses import dataclass, field
+
+import torch
+
+from . import engine
+
+
+def with_T(inst, T):
+    """The same instance on the path of duration T."""
+    out = copy.copy(inst)
+    out.path = dict(inst.path)
+    out.path["T"] = float(T)
+    return out
+
+
+def default_plan(ham, T):
+    """(steps, shift) from the spectral enclosure: centred shift, h rho = 0.1."""
+    lo, hi = ham.spectral_bounds(0.0, T)
+    return max(4, int(math.ceil(T * 0.5 * (hi - lo) / 0.1))), 0.5 * (lo + hi)
+
+
+def energies(ctx, insts, Ts, states, dtype=torch.complex64, plan=default_plan, ticks=16):
+    """E(T_i) for instance i evolved from states[i] (host or device arrays of
+    2^n amplitudes) over [0, T_i], all in one batch."""
+    b = engine.Batch(ctx, dtype, capacity=max(1, len(insts)), graph=True)
+    hams, slots = [], {}
+    try:
+        for i, (inst, T, st) in enumerate(zip(insts, Ts, states)):
+            ham = engine.Hamiltonian(ctx, with_T(inst, T))
+            hams.append(ham)
+            K, shift = plan(ham, T)
+            psi = torch.as_tensor(st).to(device=ctx.device, dtype=dtype).contiguous().clone()
+            slots[b.admit(ham, psi, 0.0, T, K, shift)] = i
+        out = [None] * len(insts)
+        while any(v is None for v in out):
+            b.step(ticks)
+            for slot in b.poll():
+                i = slots[slot]
+                psi, _ = b.retire(slot)
+                out[i] = engine.energy(ctx, hams[i], Ts[i], psi)
+        return out
+    finally:
+        b.close()
+        for h in hams:
+            h.free()
+
+
+@dataclass
+class Search:
+    T_lo: float = 0.0           # largest T seen with E(T) > 1/2 (0: none yet)
+    T_hi: float = math.inf      # smallest T seen with E(T) <= 1/2
+    evals: list = field(default_factory=list)   # (T, E)
+
+    @property
+    def T_s(self):
+        if not math.isfinite(self.T_hi):
+            return math.nan
+        return math.sqrt(self.T_lo * self.T_hi) if self.T_lo > 0 else self.T_hi
+
+    def next_T(self, T0, rel):
+        """The next runtime to try, or None when the bracket is narrow enough."""
+        if not math.isfinite(self.T_hi):
+            return T0 if not self.evals else 2.0 * self.T_lo
+        if self.T_lo == 0.0:
+            return self.T_hi / 2.0
+        if self.T_hi / self.T_lo <= 1.0 + rel:
+            return None
+        return math.sqrt(self.T_lo * self.T_hi)
+
+    def record(self, T, E):
+        self.evals.append((T, E))
+        if E > 0.5:
+            self.T_lo = max(self.T_lo, T)
+        else:
+            self.T_hi = min(self.T_hi, T)
+
+
+def find_ts(ctx, insts, states, T0=1.0, rel=0.05, T_max=1e4, dtype=torch.complex64, plan=default_plan,
+            max_rounds=60, log=None):
+    """T_s of every instance (the geometric mean of the final bracket
+    [T_lo, T_hi] with E(T_lo) > 1/2 >= E(T_hi), T_hi / T_lo <= 1 + rel).
+    Returns the Search records."""
+    S = [Search() for _ in insts]
+    for rnd in range(max_rounds):
+        todo = []
+        for i, s in enumerate(S):
+            T = s.next_T(T0, rel)
+            if T is not None and T <= T_max:
+                todo.append((i, T))
+        if not todo:
+            break
+        Es = energies(ctx, [insts[i] for i, _ in todo], [T for _, T in todo],
+                      [states[i] for i, _ in todo], dtype, plan)
+        for (i, T), E in zip(todo, Es):
+            S[i].record(T, E)
+        if log:
+            log(f"round {rnd}: {len(todo)} solves")
+    return S

@@ -1,0 +1,222 @@
+"""GPU: Hamming-weight sectors (Sec. III.A.2-3) through the C ABI against the
+oracle's sector functions: H psi for H^xy, H^xyz and mixed weight-preserving
+pair terms (with Z strings and Y X - X Y parts) over several workgroups and
+ragged ends, both diagonal summation forms (one-bits and zero-bits), the
+one-state sectors; fixed-step and adaptive evolution along the paths of
+Sec. IV.A; Dicke states, expansion, energies and ground masses; rejection of
+Hamiltonians that change the weight."""
+import functools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import integrate, subspace
+from paper_1311_3938_amd import instances as I
+from tests._gpu import TOL, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def eng():
+    from paper_1311_3938_amd import engine
+    ctx = engine.Context(0)
+    yield engine, ctx
+    ctx.close()
+
+
+def _mixed(n, seed):
+    """H^xy + H^xyz-style ZZ + an EC3 H_f on a sector-preserving mix of pair
+    terms: plain XX+YY, XX+YY with a Z string on a third bit, and the
+    current-like X Y - Y X; a three-bit Z string on the diagonal; three
+    schedules."""
+    rng = np.random.default_rng(seed)
+    clauses = I.ec3_random_clauses(n, max(3, (4 * n) // 5), rng)
+    t = I.xy_initial_terms(n, clauses)                      # schedule 0
+    for i, j in [(1, n), (2, n - 1)]:
+        g = rng.normal()
+        t.add({i: "X", j: "X", 3: "Z"}, g, 2)
+        t.add({i: "Y", j: "Y", 3: "Z"}, g, 2)
+        c = rng.normal()
+        t.add({i: "X", j: "Y"}, c, 2)
+        t.add({i: "Y", j: "X"}, -c, 2)
+    t.add({1: "Z", 4: "Z", 6: "Z"}, 0.7, 1)
+    f = I.ec3_terms(n, clauses)
+    f.extend(I.xyz_initial_terms(n, clauses[:2]))
+    tt = I.TermList(n)
+    tt.extend(t)
+    tt.extend(f, sid=1)
+    return tt.instance([I.SCHED_ONE_MINUS_S, I.SCHED_S, I.trig_t(0.6, 1.3, 0.2)], I.linear_path(2.0))
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("n,w", [(14, 0), (14, 1), (14, 5), (14, 7), (14, 9), (14, 14), (16, 8), (17, 3)])
+def test_sector_apply(eng, n, w, dt):
+    engine, ctx = eng
+    import torch
+    inst = _mixed(n, 10 + n)
+    ham = engine.Hamiltonian(ctx, inst)
+    sec = engine.Sector(ctx, ham, w)
+    assert sec.dim == math.comb(n, w)
+    rng = np.random.default_rng(w)
+    v = rng.normal(size=sec.dim) + 1j * rng.normal(size=sec.dim)
+    dv = to_dev(v, dt)
+    out = torch.empty_like(dv)
+    tol = 1e-12 if dt == "c128" else 5e-6
+    for t in (0.0, 0.55, 1.3, 2.0):
+        engine.apply(ctx, sec, t, dv, out)
+        assert rel_err(to_host(out), subspace.apply_h(inst, t, v, w)) < tol, t
+    sec.free()
+    ham.free()
+
+
+def test_sector_dicke_expand_energy_mass(eng):
+    engine, ctx = eng
+    import torch
+    n, w = 13, 5
+    clauses = I.ec3_random_clauses(n, 10, np.random.default_rng(3))
+    h = I.xyz_initial_terms(n, clauses)
+    inst = I.interpolated(n, h, I.ec3_terms(n, clauses), I.linear_path(1.0))
+    ham = engine.Hamiltonian(ctx, inst)
+    sec = engine.Sector(ctx, ham, w)
+    psi = sec.dicke(torch.complex128)
+    assert np.max(np.abs(to_host(psi) - subspace.dicke(n, w))) < 1e-15
+    full = sec.expand(psi)
+    assert np.array_equal(to_host(full), subspace.expand(to_host(psi), n, w))
+    # eq. (initstate) is the zero-energy ground state of H^xyz (s = 0)
+    assert abs(engine.energy(ctx, sec, 0.0, psi)) < 1e-12
+    e_half = engine.energy(ctx, sec, 0.5, psi)
+    assert abs(e_half - subspace.energy(inst, 0.5, to_host(psi), w)) < 1e-11
+    rng = np.random.default_rng(5)
+    v = rng.normal(size=sec.dim) + 1j * rng.normal(size=sec.dim)
+    v /= np.linalg.norm(v)
+    mass, emin = engine.ground_mass(ctx, sec, 1.0, to_dev(v, "c128"))
+    m_ref, e_ref = subspace.ground_mass(inst, 1.0, v, w)
+    assert abs(emin - e_ref) < 1e-12 and abs(mass - m_ref) < 1e-14
+    assert engine.norm2(ctx, psi) == pytest.approx(1.0, abs=1e-14)
+    sec.free()
+    ham.free()
+
+
+@pytest.mark.parametrize("bad", ["transverse", "xx_only", "three_flips"])
+def test_sector_rejects_weight_changing_terms(eng, bad):
+    engine, ctx = eng
+    from paper_1311_3938_amd import _lib as L
+    n = 6
+    t = I.TermList(n)
+    t.add({1: "Z"}, 1.0, 0)
+    if bad == "transverse":
+        t.add({2: "X"}, 0.5, 0)
+    elif bad == "xx_only":
+        t.add({2: "X", 5: "X"}, 0.5, 0)
+    else:
+        t.add({1: "X", 2: "X", 3: "X"}, 0.5, 0)
+    ham = engine.Hamiltonian(ctx, t.instance([I.SCHED_CONST], I.linear_path(1.0)))
+    with pytest.raises(L.AqcError) as ei:
+        engine.Sector(ctx, ham, 3)
+    assert ei.value.status == L.AQC_EINVAL
+    ham.free()
+
+
+def _path_case(kind):
+    n, m, T = 12, 9, 1.0
+    inst = I.workload_ec3_paths(n=n, m=m, T=T, kind=kind, seed=I.seed_for(5, 3))
+    return inst, n, m, T
+
+
+def _steps(inst, T, method):
+    """Step count from a crude bound on |H - identity part|: the sum of
+    |weight| times the largest schedule value (pc4: h * bound <= 0.15)."""
+    if method == "rk4":
+        return 160
+    path = I.linear_path(1.0)
+    from oracle import sqh
+    fmax = [max(abs(sqh.schedule_value(s, x, path)) for x in np.linspace(0, 1, 201)) for s in inst.scheds]
+    b = sum(abs(w) * fmax[sid] for x, z, w, sid in zip(inst.x, inst.z, inst.w, inst.sid) if int(x) or int(z))
+    return int(math.ceil(T * b / 0.15))
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_path(kind, method, K, shift, w):
+    inst, n, m, T = _path_case(kind)
+    return subspace.evolve(inst, subspace.dicke(n, w), w, 0.0, T, K, method, shift)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("kind,method", [("cbc", "pc4"), ("nonlinear", "rk4"), ("linear", "pc4")])
+def test_sector_evolve_paths(eng, kind, method, dt):
+    """Whole paths in the weight-4 sector from its Dicke state; the complex128
+    result also equals the full-space evolution restricted to the sector."""
+    engine, ctx = eng
+    inst, n, m, T = _path_case(kind)
+    w = 4
+    ham = engine.Hamiltonian(ctx, inst)
+    sec = engine.Sector(ctx, ham, w)
+    lo, hi = sec.spectral_bounds(0.0, T)
+    lo_f, hi_f = ham.spectral_bounds(0.0, T)
+    assert lo_f <= lo + 1e-9 and hi <= hi_f + 1e-9      # the sector's enclosure is inside
+    shift = 3.0 * m                                      # identity part of H^xy
+    K = _steps(inst, T, method)
+    import torch
+    psi = sec.dicke(torch.complex128 if dt == "c128" else torch.complex64)
+    engine.evolve(ctx, sec, psi, 0.0, T, method=method, n_steps=K, shift=shift)
+    ref = _oracle_path(kind, method, K, shift, w)
+    assert np.linalg.norm(to_host(psi) - ref) < TOL[dt]
+    if dt == "c128":
+        full = to_dev(subspace.expand(subspace.dicke(n, w), n, w), "c128")
+        engine.evolve(ctx, ham, full, 0.0, T, method=method, n_steps=K, shift=shift)
+        assert np.linalg.norm(subspace.restrict(to_host(full), n, w) - to_host(psi)) < TOL["c128"]
+    mass, emin = engine.ground_mass(ctx, sec, T, psi)
+    m_ref, e_ref = subspace.ground_mass(inst, T, ref, w)
+    assert abs(emin - e_ref) < 1e-9 and abs(mass - m_ref) < TOL[dt]
+    sec.free()
+    ham.free()
+
+
+def test_sector_adaptive_matches_oracle_decisions(eng):
+    engine, ctx = eng
+    inst, n, m, T = _path_case("cbc")
+    w = 5
+    psi0 = subspace.dicke(n, w)
+    kw = dict(atol=1e-9, h0=0.05, window=8)
+    ref_full, segs_ref, cnt = integrate.evolve_adaptive(inst, subspace.expand(psi0, n, w), 0.0, 0.5,
+                                                        shift=18.0, **kw)
+    ham = engine.Hamiltonian(ctx, inst)
+    sec = engine.Sector(ctx, ham, w)
+    psi = to_dev(psi0, "c128")
+    st, segs = engine.evolve(ctx, sec, psi, 0.0, 0.5, method="pc4", n_steps=0, record_cap=512,
+                             shift=18.0, **kw)
+    assert st["n_segments"] == len(segs_ref)
+    assert [s[2] for s in segs] == [s[2] for s in segs_ref]
+    assert st["steps"] == cnt.steps and st["rejected"] == cnt.rejected
+    assert np.linalg.norm(to_host(psi) - subspace.restrict(ref_full, n, w)) < TOL["c128"]
+    sec.free()
+    ham.free()
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_sector_carry_chain_equals_one_call(eng, dt):
+    engine, ctx = eng
+    import torch
+    inst, n, m, T = _path_case("cbc")
+    ham = engine.Hamiltonian(ctx, inst)
+    sec = engine.Sector(ctx, ham, 6)
+    h = 0.01
+    outs = []
+    for pieces in ([2, 38], [2, 1, 7, 30]):
+        psi = sec.dicke(torch.complex128 if dt == "c128" else torch.complex64)
+        carry = engine.new_carry()
+        ws = None
+        t = 0.0
+        for k in pieces:
+            opts = dict(method="pc4", n_steps=k, shift=18.0)
+            o, _, _ = engine.evolve_opts(**opts)
+            if ws is None:
+                ws = engine.workspace(ctx, engine.evolve_workspace_bytes(sec, engine.dtype_code(psi), o))
+            engine.evolve(ctx, sec, psi, t, t + k * h, ws=ws, carry=carry, **opts)
+            t += k * h
+        outs.append(to_host(psi))
+    assert np.array_equal(outs[0], outs[1])
+    sec.free()
+    ham.free()

@@ -1,0 +1,81 @@
+"""GPU: the successful runtime T_s of Sec. III.B over batches, against the
+same bracket-and-bisect search run on the oracle: every runtime the search
+tries and every final energy E(T) agree.  X algorithm from |+> and XY
+algorithm from the ground state of H^xy in the solution's weight sector (the
+library's Lanczos vector, checked against the oracle's dense eigenvector)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import integrate, observables, spectrum, sqh, subspace
+from paper_1311_3938_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def eng():
+    from paper_1311_3938_amd import engine
+    ctx = engine.Context(0)
+    yield engine, ctx
+    ctx.close()
+
+
+def _bound(inst):
+    path = I.linear_path(1.0)
+    fmax = [max(abs(sqh.schedule_value(s, x, path)) for x in np.linspace(0, 1, 101)) for s in inst.scheds]
+    return sum(abs(w) * fmax[sid] for x, z, w, sid in zip(inst.x, inst.z, inst.w, inst.sid) if int(x) or int(z))
+
+
+def _plan_for(inst):
+    """Steps and shift from the instance description alone (no device)."""
+    b = _bound(inst)
+    ident = sum(w for x, z, w in zip(inst.x, inst.z, inst.w) if not int(x) and not int(z))
+    shift = round(0.5 * ident, 3)
+    return lambda ham, T: (max(4, int(math.ceil(T * (b + abs(0.5 * ident)) / 0.15))), shift)
+
+
+def _oracle_search(inst, psi0, plan, T0, rel):
+    from paper_1311_3938_amd.tsearch import Search, with_T
+    s = Search()
+    while True:
+        T = s.next_T(T0, rel)
+        if T is None:
+            return s
+        K, shift = plan(None, T)
+        it = with_T(inst, T)
+        y = integrate.evolve(it, psi0, 0.0, T, K, "pc4", shift)
+        s.record(T, observables.energy(it, T, y))
+
+
+@pytest.mark.parametrize("algorithm,n", [("x", 7), ("xy", 8)])
+def test_ts_search_matches_oracle(eng, algorithm, n):
+    engine, ctx = eng
+    import torch
+    from paper_1311_3938_amd import tsearch
+    inst = I.workload_usa(n, 0, algorithm)
+    plan = _plan_for(inst)
+    if algorithm == "x":
+        psi_gpu = psi_ref = I.plus_state(n)
+    else:
+        # the ground state of H^xy in the sector of the solution's weight
+        w = inst.meta["weight"]
+        ham = engine.Hamiltonian(ctx, inst)
+        sec = engine.Sector(ctx, ham, w)
+        g = torch.empty(sec.dim, dtype=torch.complex128, device="cuda")
+        engine.lowest_eigs(ctx, sec, 0.0, k=1, max_basis=12, tol=1e-12, ground=g)
+        psi_gpu = sec.expand(g).cpu().numpy()
+        sec.free()
+        ham.free()
+        b = subspace.basis(n, w)
+        H0 = np.array([subspace.apply_h(inst, 0.0, e, w) for e in np.eye(len(b), dtype=complex)]).T
+        vals, vecs = np.linalg.eigh(0.5 * (H0 + H0.conj().T))
+        assert vals[1] - vals[0] > 1e-6                      # a unique ground state
+        psi_ref = subspace.expand(vecs[:, 0], n, w)
+        assert abs(abs(np.vdot(psi_ref, psi_gpu)) - 1.0) < 1e-10
+    S = tsearch.find_ts(ctx, [inst], [psi_gpu], T0=2.0, rel=0.1, dtype=torch.complex128, plan=plan)[0]
+    R = _oracle_search(inst, psi_ref, plan, 2.0, 0.1)
+    assert [T for T, _ in S.evals] == [T for T, _ in R.evals]
+    assert np.allclose([E for _, E in S.evals], [E for _, E in R.evals], atol=1e-9, rtol=0)
+    assert math.isfinite(S.T_s) and S.T_s == R.T_s

@@ -68,4 +68,28 @@ def test_argument_errors_without_a_device(lib):
     assert lib.aqc_evolve_workspace_bytes(None, 0, None) == 0
     d = C.c_double()
     assert lib.aqc_norm2(None, None, 0, 3, C.byref(d)) == _lib.AQC_EINVAL
+    assert lib.aqc_norm2_len(None, None, 0, 10, C.byref(d)) == _lib.AQC_EINVAL
+    assert lib.aqc_sector_create(None, None, 2, C.byref(out)) == _lib.AQC_EINVAL
+    assert lib.aqc_ham_dim(None) == 0 and lib.aqc_ham_sector_weight(None) == -1
+    assert lib.aqc_sector_dicke(None, None, None, 0) == _lib.AQC_EINVAL
     assert lib.aqc_version().startswith(b"aqc")
+
+
+def test_host_hermitian_solver_matches_numpy(lib):
+    """The host solver of the projected Lanczos problem (no device needed):
+    random Hermitian matrices, a diagonal one with repeated entries and a
+    2 x 2 with a complex coupling."""
+    import numpy as np
+    from paper_1311_3938_amd import engine
+    rng = np.random.default_rng(0)
+    for n in (1, 2, 5, 17, 48):
+        a = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+        a = a + a.conj().T
+        w, z = engine.hermitian_eigh(a)
+        assert np.allclose(w, np.linalg.eigvalsh(a), atol=1e-11 * max(1, np.abs(w).max()))
+        assert np.allclose(z.conj().T @ z, np.eye(n), atol=1e-12)
+        assert np.allclose(a @ z, z * w, atol=1e-10 * max(1, np.abs(w).max()))
+    d = np.diag([3.0, 1.0, 1.0, -2.0]).astype(complex)
+    assert np.allclose(engine.hermitian_eigh(d)[0], [-2, 1, 1, 3])
+    w, _ = engine.hermitian_eigh(np.array([[1.0, 2j], [-2j, 1.0]]))
+    assert np.allclose(w, [-1.0, 3.0])
