@@ -519,6 +519,75 @@ def run_tsearch_mode(args):
     print(json.dumps(res), flush=True)
 
 
+def run_scaling_mode(args):
+    """Step time against n for the SK workload family (sin^2 path, transverse
+    field, pc4, c64 with float64 reductions): the library (median of 5
+    windows of 50 chained steps) beside the oracle (NumPy complex128, one
+    thread), with the versions of the software stack."""
+    import numpy as np
+    import torch
+    from oracle import integrate, sqh
+    from paper_1311_3938_amd import engine
+    from paper_1311_3938_amd import instances as I
+    ctx = engine.Context(0)
+    rows = []
+    for n in [int(v) for v in args.scaling_sizes.split(",")]:
+        inst = I.workload_sk_sin2(n=n, T=30.0, seed=I.seed_for(2))
+        ham = engine.Hamiltonian(ctx, inst)
+        lo, hi = ham.spectral_bounds(0.0, 30.0)
+        K = int(math.ceil(30.0 * 0.5 * (hi - lo) / 0.1))
+        h = 30.0 / K
+        N = 1 << n
+        psi = torch.full((N,), N ** -0.5, dtype=torch.complex64, device="cuda")
+        opts = dict(method="pc4", n_steps=50, shift=0.5 * (lo + hi))
+        o, _, _ = engine.evolve_opts(**opts)
+        ws = engine.workspace(ctx, engine.evolve_workspace_bytes(ham, engine.dtype_code(psi), o))
+        carry = engine.new_carry()
+        t = 0.0
+        engine.evolve(ctx, ham, psi, t, t + 50 * h, ws=ws, carry=carry, **opts)
+        t += 50 * h
+        times = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            engine.evolve(ctx, ham, psi, t, t + 50 * h, ws=ws, carry=carry, **opts)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) / 50)
+            t += 50 * h
+        gpu = float(np.median(times))
+        row = {"n": n, "gpu_ms_per_step": 1e3 * gpu, "gpu_amp_updates_per_s": N / gpu}
+        del ws, psi
+        ham.free()
+        torch.cuda.empty_cache()
+        if n <= args.scaling_oracle_max:
+            psi0 = I.plus_state(n)
+            steps = 4 if n <= 16 else 1
+            seg = integrate.Segment(inst, psi0, 0.0, h, "pc4", 0.5 * (lo + hi))
+            seg.advance(3)                     # the RK4 bootstrap
+            t0 = time.perf_counter()
+            seg.advance(steps)
+            o_dt = (time.perf_counter() - t0) / steps
+            row.update({"oracle_ms_per_step": 1e3 * o_dt, "oracle_amp_updates_per_s": N / o_dt,
+                        "ratio": o_dt / gpu})
+        rows.append(row)
+        log(f"n={n}: {row}")
+    fit = [r for r in rows if "oracle_ms_per_step" in r]
+    per_amp = fit[-1]["oracle_ms_per_step"] / (1 << fit[-1]["n"]) if fit else None
+    versions = {"torch": torch.__version__, "hip": getattr(torch.version, "hip", None),
+                "device": torch.cuda.get_device_properties(0).name,
+                "arch": torch.cuda.get_device_properties(0).gcnArchName}
+    res = {
+        "metric": "amp-updates/s", "value": rows[-1]["gpu_amp_updates_per_s"], "unit": "amp-updates/s",
+        "n_gpus": 1, "steps": 5, "warmup": 1, "ms_per_step": rows[-1]["gpu_ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "SK + transverse field, sin^2 path, T=30, pc4, chained windows of 50 steps"},
+        "rows": rows, "versions": versions,
+        "oracle_n30_extrapolated_s_per_step": per_amp * (1 << 30) * 1e-3 if per_amp else None,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -536,8 +605,10 @@ def main():
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB copy (for scaling hardware byte counters)")
     ap.add_argument("--mode", choices=["single", "batch", "serve", "adaptive", "paths", "sector", "gap",
-                                       "tsearch"], default="single")
+                                       "tsearch", "scaling"], default="single")
     ap.add_argument("--ts-sizes", default="10,12,14")
+    ap.add_argument("--scaling-sizes", default="12,16,20,24,28,30")
+    ap.add_argument("--scaling-oracle-max", type=int, default=20)
     ap.add_argument("--ts-instances", type=int, default=8)
     ap.add_argument("--ts-algorithms", default="x,xy")
     ap.add_argument("--ts-rel", type=float, default=0.05)
@@ -576,6 +647,8 @@ def main():
         return run_gap_mode(args)
     if args.mode == "tsearch":
         return run_tsearch_mode(args)
+    if args.mode == "scaling":
+        return run_scaling_mode(args)
 
     import torch
     from paper_1311_3938_amd import engine

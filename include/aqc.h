@@ -311,7 +311,8 @@ aqc_status aqc_overlap_len(aqc_ctx* ctx, const void* phi, const void* psi, int d
  * flips exactly two bits, and for each such pair and schedule the summed
  * coefficient vanishes on the states whose two bits are equal (checked
  * exactly over the terms' Z bits, at most 16 besides the pair, else
- * AQC_ENOTSUP).  n <= 34 and at most 1024 pair terms (AQC_ENOTSUP).
+ * AQC_ENOTSUP).  n <= 34, at most 600 flip pairs and 1024 pair terms
+ * (AQC_ENOTSUP).
  * Device tables: a few tens of KB, allocated here.                          */
 aqc_status aqc_sector_create(aqc_ctx* ctx, const aqc_ham* ham, int weight, aqc_ham** out);
 /* amplitudes of a state of `ham`: 2^n, or C(n, w) for a sector            */

@@ -1389,12 +1389,23 @@ extern "C" aqc_status aqc_sector_create(aqc_ctx* ctx, const aqc_ham* src, int we
   std::vector<SecHop> hops;
   std::vector<DevTerm> hterms;
   for (const GroupH& g : src->groups) {
-    SecHop hp{g.x, (int32_t)hterms.size(), (int32_t)g.terms.size()};
-    for (const HTerm& t : g.terms) hterms.push_back(DevTerm{t.z, t.w, t.sid, popc(t.x & t.z) & 3});
+    SecHop hp{};
+    hp.x = g.x;
+    hp.t0 = (int32_t)hterms.size();
+    hp.nt = (int32_t)g.terms.size();
+    hp.bi = __builtin_ctzll(g.x);
+    hp.bj = 63 - __builtin_clzll(g.x);
+    hp.fast = 1;
+    for (const HTerm& t : g.terms) {
+      hterms.push_back(DevTerm{t.z, t.w, t.sid, popc(t.x & t.z) & 3});
+      if (t.z & ~g.x) hp.fast = 0;
+    }
     hops.push_back(hp);
   }
   if (hterms.size() > (size_t)kSecMaxHopTerms)
     return fail(AQC_ENOTSUP, "aqc_sector_create: more than 1024 pair terms");
+  if (hops.size() > (size_t)kSecMaxHops)
+    return fail(AQC_ENOTSUP, "aqc_sector_create: more than 600 flip pairs");
   std::map<uint64_t, std::vector<HTerm>> bymask;
   std::vector<DevTerm> res;
   for (const HTerm& t : src->diag) {

@@ -134,7 +134,12 @@ constexpr int kSecGrid = 4096;      // at most this many workgroups per launch
 struct SecHop {
   uint64_t x;
   int32_t t0, nt;
+  int32_t bi, bj;  // the two flipped bits, bi < bj
+  int32_t fast;    // 1: every Z string lies inside x, so the coefficient of
+                   // a state with differing bits depends only on bit bi
+  int32_t pad;
 };
+constexpr int kSecMaxHops = 600;
 // The diagonal terms sharing one mask of one or two bits (q < 0: one bit p).
 struct SecMask {
   int32_t p, q;

@@ -1232,17 +1232,48 @@ int64_t sector_blocks(int64_t dim) {
   return nb < 1 ? 1 : (nb > kSecGrid ? kSecGrid : nb);
 }
 
+// Coefficients of the pair hops at this time: for a "fast" hop (every Z
+// string inside its two bits) the coefficient of a state whose two bits
+// differ depends only on the partner's bit bi: hc[4k..4k+1] for partner bit 0,
+// hc[4k+2..4k+3] for 1 (re, im).  Other hops keep per-term values in tm.
+template <typename R>
+__device__ __forceinline__ void sector_hop_setup(const SectorDev& s, const SecLds& L, R* tm, R* hc) {
+  for (int k = threadIdx.x; k < s.nhterms; k += kSecThreads) {
+    const DevTerm t = s.hterms[k];
+    tm[k] = (R)(t.w * L.fsh[t.sid]);
+  }
+  for (int k = threadIdx.x; k < s.nhops; k += kSecThreads) {
+    const SecHop hp = s.hops[k];
+    if (!hp.fast) continue;
+    double c[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < hp.nt; ++t) {
+      const DevTerm tt = s.hterms[hp.t0 + t];
+      const double m = tt.w * L.fsh[tt.sid];
+      const int zi = (int)((tt.z >> hp.bi) & 1ull), zj = (int)((tt.z >> hp.bj) & 1ull);
+      for (int b = 0; b < 2; ++b) {
+        // the partner's bits are (bi, bj) = (b, 1 - b)
+        const double v = (((zi & b) ^ (zj & (1 - b))) & 1) ? -m : m;
+        switch (tt.p & 3) {
+          case 0: c[2 * b] += v; break;
+          case 1: c[2 * b + 1] += v; break;
+          case 2: c[2 * b] -= v; break;
+          default: c[2 * b + 1] -= v; break;
+        }
+      }
+    }
+    for (int q = 0; q < 4; ++q) hc[4 * k + q] = (R)c[q];
+  }
+}
+
 template <typename R>
 __global__ __launch_bounds__(kSecThreads) void k_sector(const SectorArgs a) {
   using V = typename CT2<R>::V;
   __shared__ SecLds L;
   __shared__ R tm[kSecMaxHopTerms];
+  __shared__ R hc[4 * kSecMaxHops];
   sector_setup(a, L);
   const SectorDev& s = a.s;
-  for (int k = threadIdx.x; k < s.nhterms; k += kSecThreads) {
-    const DevTerm t = s.hterms[k];
-    tm[k] = (R)(t.w * L.fsh[t.sid]);
-  }
+  sector_hop_setup<R>(s, L, tm, hc);
   __syncthreads();
   const V* __restrict__ src = reinterpret_cast<const V*>(a.src);
   const EpiDesc& e = a.epi;
@@ -1255,35 +1286,70 @@ __global__ __launch_bounds__(kSecThreads) void k_sector(const SectorArgs a) {
     const int64_t rf = base + (int64_t)threadIdx.x * kSecEPT;
     uint64_t zs[kSecEPT];
     bool ok[kSecEPT];
-    uint64_t z = rf < s.dim ? sector_unrank(L.binom, s.n, s.w, rf) : 0ull;
+    // the rank table part of each chunk of each state
+    uint32_t contrib[kSecEPT][kSecMaxChunks];
+    {
+      uint64_t z = rf < s.dim ? sector_unrank(L.binom, s.n, s.w, rf) : 0ull;
 #pragma unroll
-    for (int u = 0; u < kSecEPT; ++u) {
-      ok[u] = rf + u < s.dim;
-      zs[u] = z;
-      if (u + 1 < kSecEPT && rf + u + 1 < s.dim) z = next_same_weight(z);
+      for (int u = 0; u < kSecEPT; ++u) {
+        ok[u] = rf + u < s.dim;
+        zs[u] = z;
+        if (u + 1 < kSecEPT && rf + u + 1 < s.dim) z = next_same_weight(z);
+        int cnt = 0;
+#pragma unroll
+        for (int c = 0; c < kSecMaxChunks; ++c) {
+          contrib[u][c] = 0u;
+          if (c < s.nch && ok[u]) {
+            const uint32_t nib = (uint32_t)(zs[u] >> (4 * c)) & 15u;
+            contrib[u][c] = L.rtab[(c * 16 + (int)nib) * w1 + cnt];
+            cnt += __popc(nib);
+          }
+        }
+      }
     }
     R hr[kSecEPT], hi[kSecEPT];
 #pragma unroll
     for (int u = 0; u < kSecEPT; ++u) hr[u] = hi[u] = 0;
     for (int k = 0; k < s.nhops; ++k) {
       const SecHop hp = s.hops[k];
+      const int ca = hp.bi >> 2, cb = hp.bj >> 2;
 #pragma unroll
       for (int u = 0; u < kSecEPT; ++u) {
-        if (!ok[u] || __popcll(zs[u] & hp.x) != 1) continue;
-        const uint64_t zp = zs[u] ^ hp.x;
+        const uint64_t z = zs[u];
+        const uint32_t zi = (uint32_t)(z >> hp.bi) & 1u, zj = (uint32_t)(z >> hp.bj) & 1u;
+        if (!ok[u] || zi == zj) continue;
+        const uint64_t zp = z ^ hp.x;
+        // rank of the partner: only the chunks from bi's to bj's change; between
+        // them the number of 1-bits below moves by zp_bi - z_bi
+        const int delta = zi ? -1 : 1;
+        uint32_t rp = (uint32_t)(rf + u);
+#pragma unroll
+        for (int c = 0; c < kSecMaxChunks; ++c) {
+          if (c < ca || c > cb) continue;
+          const uint32_t nib = (uint32_t)(zp >> (4 * c)) & 15u;
+          const int cn = __popcll(z & ((1ull << (4 * c)) - 1ull)) + (c > ca ? delta : 0);
+          rp += L.rtab[(c * 16 + (int)nib) * w1 + cn] - contrib[u][c];
+        }
         // a weight-w state has a rank below dim; the clamp only guards the read
-        const uint32_t rp = sector_rank(L.rtab, s.nch, w1, zp);
         const V pv = src[min((int64_t)rp, s.dim - 1)];
-        R cr = 0, ci = 0;
-        for (int t = 0; t < hp.nt; ++t) {
-          const DevTerm tt = s.hterms[hp.t0 + t];
-          R m = tm[hp.t0 + t];
-          if (__popcll(zp & tt.z) & 1) m = -m;
-          switch (tt.p & 3) {
-            case 0: cr += m; break;
-            case 1: ci += m; break;
-            case 2: cr -= m; break;
-            default: ci -= m; break;
+        R cr, ci;
+        if (hp.fast) {
+          const int q = 4 * k + 2 * (int)(1u - zi);
+          cr = hc[q];
+          ci = hc[q + 1];
+        } else {
+          cr = 0;
+          ci = 0;
+          for (int t = 0; t < hp.nt; ++t) {
+            const DevTerm tt = s.hterms[hp.t0 + t];
+            R m = tm[hp.t0 + t];
+            if (__popcll(zp & tt.z) & 1) m = -m;
+            switch (tt.p & 3) {
+              case 0: cr += m; break;
+              case 1: ci += m; break;
+              case 2: cr -= m; break;
+              default: ci -= m; break;
+            }
           }
         }
         hr[u] += cr * pv.x - ci * pv.y;
