@@ -269,7 +269,7 @@ def run_paths_mode(args):
     dicke = torch.from_numpy(I.dicke_state(n, weight, dtype=np.complex64)).to("cuda")
     ctx = engine.Context(0)
     out = {}
-    for kind in ("linear", "nonlinear", "cbc"):
+    for kind in args.paths_kinds.split(","):
         inst = I.workload_ec3_paths(n=n, m=m, T=T, kind=kind, seed=I.seed_for(5))
         ham = engine.Hamiltonian(ctx, inst)
         lo, hi = ham.spectral_bounds(0.0, T)
@@ -320,7 +320,7 @@ def run_paths_mode(args):
         del ws, psi
         ham.free()
         torch.cuda.empty_cache()
-    lin = out["linear"]
+    lin = out[next(iter(out))]
     res = {
         "metric": "amp-updates/s", "value": lin["amp_updates_per_s"], "unit": "amp-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -620,6 +620,7 @@ def main():
                     help="weight of the sector (default n/2, gap mode n/3; -2: full space)")
     ap.add_argument("--sector-paths", default="linear,cbc")
     ap.add_argument("--n-paths", type=int, default=26, help="qubits of the paths mode")
+    ap.add_argument("--paths-kinds", default="linear,nonlinear,cbc")
     ap.add_argument("--atol", type=float, default=1e-9)
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--baseline-subset", type=int, default=16)

@@ -439,10 +439,12 @@ static uint64_t pext_host(uint64_t v, uint64_t mask) {
   return r;
 }
 
-static aqc_status build_pass_tables(Pass& ps, const aqc_ham* h, hipStream_t s) {
+static aqc_status build_pass_tables(Pass& ps, const aqc_ham* h, int dtype, hipStream_t s) {
   std::vector<DevGroup> dg;
   std::vector<DevTerm> dt;
   const uint64_t tmask = ((1ull << ps.lbits) - 1ull) | ps.hmask;
+  const int slots = dtype == AQC_C64 ? kFastSlotsC64 : kFastSlotsC128;
+  int nfast = 0;
   for (int gi : ps.groups) {
     const GroupH& g = h->groups[gi];
     DevGroup d{};
@@ -451,8 +453,17 @@ static aqc_status build_pass_tables(Pass& ps, const aqc_ham* h, hipStream_t s) {
     d.t0 = (int)dt.size();
     d.nt = (int)g.terms.size();
     d.plain = g.plain ? 1 : 0;
-    for (const HTerm& t : g.terms)
+    d.fslot = -1;
+    bool inside = popc(g.x) <= 2;
+    for (const HTerm& t : g.terms) {
       dt.push_back(DevTerm{t.z, t.w, t.sid, popc(t.x & t.z) & 3});
+      inside = inside && !(t.z & ~g.x);
+    }
+    if (!g.plain && inside && nfast < slots) {
+      d.fslot = nfast++;
+      const int bi = __builtin_ctzll(g.x), bj = 63 - __builtin_clzll(g.x);
+      d.bij = bi | (bj << 8);
+    }
     dg.push_back(d);
   }
   ps.ng = (int)dg.size();
@@ -725,7 +736,7 @@ static aqc_status build_plan(aqc_ham* h, int dtype, hipStream_t s) {
   p.has_stream = false;
   for (const Pass& ps : p.passes) p.has_stream = p.has_stream || ps.stream;
   for (Pass& ps : p.passes)
-    if (ps.kind == 0) STCHK(build_pass_tables(ps, h, s));
+    if (ps.kind == 0) STCHK(build_pass_tables(ps, h, dtype, s));
   STCHK(build_diag_tables(p, h, s));
   p.built = true;
   return AQC_OK;

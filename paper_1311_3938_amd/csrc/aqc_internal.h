@@ -33,7 +33,15 @@ struct DevGroup {
   int32_t t0;      // first term (index into the pass's term array)
   int32_t nt;      // number of terms
   int32_t plain;   // 1: all z_t = 0 and p_t = 0, so c_x is one real number
+  int32_t fslot;   // >= 0: x flips one or two bits bi <= bj and every z_t lies
+                   // inside x, so c_x depends only on the source's bits bi,
+                   // bj: a 4-entry table, slot fslot of the pass (else -1)
+  int32_t bij;     // bi | bj << 8 (fast groups)
 };
+// fast-group tables per pass: 4 complex values each, in the LDS bytes of the
+// per-term float64 coefficients (free once the set-up has used them)
+constexpr int kFastSlotsC64 = 128;
+constexpr int kFastSlotsC128 = 64;
 
 // Diagonal part split for a tile of `tb` low bits ("lo") and the remaining
 // high bits ("hi"): E_s(g) = CT_s[hi] + sum_{i<tb} LT_s[hi][i] (-1)^{lo_i}

@@ -315,6 +315,10 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
     tm[tid] = (R)v;
   }
   __syncthreads();
+  // fast groups: c_x as a function of the source's bits (bi, bj), entry
+  // sb_i + 2 sb_j, from the per-term values (written over them below)
+  double fv[8];
+  const bool isfast = hasg && gr.fslot >= 0;
   if (hasg) {
     double c = 0.0;
     if (gr.plain)
@@ -324,7 +328,34 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
     // g, bit 30 one whose partner lies outside the tile (read from memory)
     gxl[tid] = gr.xl | (gr.plain ? 0u : 0x80000000u) | ((gr.x & ~tmask) ? 0x40000000u : 0u);
   }
+  if (isfast) {
+    const int bi = gr.bij & 255, bj = gr.bij >> 8;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) fv[q] = 0.0;
+    for (int t = 0; t < gr.nt; ++t) {
+      const DevTerm ft = a.terms[gr.t0 + t];
+      const double m = tmd[gr.t0 + t];
+      const int hi_ = (int)((ft.z >> bi) & 1ull), hj = bj != bi ? (int)((ft.z >> bj) & 1ull) : 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int par = ((q & 1) & hi_) ^ ((q >> 1) & hj);
+        const double v = par ? -m : m;
+        switch (ft.p & 3) {
+          case 0: fv[2 * q] += v; break;
+          case 1: fv[2 * q + 1] += v; break;
+          case 2: fv[2 * q] -= v; break;
+          default: fv[2 * q + 1] -= v; break;
+        }
+      }
+    }
+  }
   if (FINAL) diag_setup_b(a, lin, LA, LB);
+  __syncthreads();
+  R* ftab = reinterpret_cast<R*>(tmd);   // per-term float64 values are dead now
+  if (isfast) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ftab[8 * gr.fslot + q] = (R)fv[q];
+  }
   __syncthreads();
 
   // ---- 3. products and epilogue --------------------------------------------
@@ -414,6 +445,18 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
             hr[u] += c * pv[u].x;
             hi[u] += c * pv[u].y;
           }
+        } else if (gr.fslot >= 0) {
+          const int bi = gr.bij & 255, bj = gr.bij >> 8;
+          const R* fc = ftab + 8 * gr.fslot;
+#pragma unroll
+          for (int u = 0; u < EB; ++u) {
+            if (!ok[u]) continue;
+            const uint64_t src_idx = gidx_of(u) ^ gr.x;
+            const int q = 2 * ((int)((src_idx >> bi) & 1ull) | ((int)((src_idx >> bj) & 1ull) << 1));
+            const R cr = fc[q], ci = fc[q + 1];
+            hr[u] += cr * pv[u].x - ci * pv[u].y;
+            hi[u] += cr * pv[u].y + ci * pv[u].x;
+          }
         } else {
 #pragma unroll
           for (int u = 0; u < EB; ++u) {
@@ -449,6 +492,22 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
         }
       } else {
         const DevGroup gr = a.groups[k];
+        if (gr.fslot >= 0) {
+          const int bi = gr.bij & 255, bj = gr.bij >> 8;
+          const R* fc = ftab + 8 * gr.fslot;
+#pragma unroll
+          for (int u = 0; u < EB; ++u) {
+            if (!ok[u]) continue;
+            const uint32_t l = tid + kThreads * (jb + u);
+            const uint64_t src_idx = gidx_of(u) ^ gr.x;
+            const int q = 2 * ((int)((src_idx >> bi) & 1ull) | ((int)((src_idx >> bj) & 1ull) << 1));
+            const R cr = fc[q], ci = fc[q + 1];
+            const V v = tile[l ^ gr.xl];
+            hr[u] += cr * v.x - ci * v.y;
+            hi[u] += cr * v.y + ci * v.x;
+          }
+          continue;
+        }
 #pragma unroll
         for (int u = 0; u < EB; ++u) {
           if (!ok[u]) continue;

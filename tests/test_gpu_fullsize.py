@@ -99,3 +99,56 @@ def test_sk_diagonal_full_size_exact_phases(eng):
     del psi
     ham.free()
     torch.cuda.empty_cache()
+
+
+def _colex_rank(z):
+    """Rank of a weight-w basis state among those of its weight in increasing
+    order: sum over its set bits p_0 < p_1 < ... of C(p_k, k + 1)."""
+    r, k, p = 0, 0, 0
+    while z:
+        if z & 1:
+            r += math.comb(p, k + 1)
+            k += 1
+        z >>= 1
+        p += 1
+    return r
+
+
+def test_sector_apply_sampled_rows_full_size(eng):
+    """The Hamming-weight sector of the sector benchmark (n = 30, w = 15,
+    C(30, 15) = 155 117 520 states, complex64) on the clause-by-clause XY
+    path: sampled rows of H psi against the oracle's row-wise product of the
+    expanded state (amplitudes outside the sector are zero)."""
+    engine, ctx, torch = eng
+    n, w = N_FULL, 15
+    inst = I.workload_ec3_paths(n=n, m=24, T=20.0, kind="cbc", seed=I.seed_for(5))
+    ham = engine.Hamiltonian(ctx, inst)
+    sec = engine.Sector(ctx, ham, w)
+    assert sec.dim == math.comb(n, w)
+    g = torch.Generator(device="cuda").manual_seed(7)
+    psi = torch.randn(sec.dim, dtype=torch.complex64, device="cuda", generator=g)
+    out = engine.apply(ctx, sec, 9.5, psi)
+    rng = np.random.default_rng(8)
+    rows = []
+    while len(rows) < 300:                     # random weight-15 states
+        rows.append(int(sum(1 << int(q) for q in rng.choice(n, w, replace=False))))
+    rows += [(1 << w) - 1, ((1 << w) - 1) << (n - w)]   # the first and the last state
+    rows = np.unique(np.array(rows, dtype=np.int64))
+
+    def values_at(idx):
+        idx = np.asarray(idx, dtype=np.int64)
+        keep = np.array([bin(int(z)).count("1") == w for z in idx])
+        vals = np.zeros(idx.shape, dtype=np.complex128)
+        if keep.any():
+            ranks = torch.tensor([_colex_rank(int(z)) for z in idx[keep]], dtype=torch.int64, device="cuda")
+            vals[keep] = psi.index_select(0, ranks).cpu().to(torch.complex128).numpy()
+        return vals
+
+    want = sqh.apply_h_rows(inst, 9.5, values_at, rows)
+    ranks = torch.tensor([_colex_rank(int(z)) for z in rows], dtype=torch.int64, device="cuda")
+    got = out.index_select(0, ranks).cpu().to(torch.complex128).numpy()
+    assert np.max(np.abs(got - want)) / np.abs(want).max() < 5e-6
+    del out, psi
+    sec.free()
+    ham.free()
+    torch.cuda.empty_cache()
