@@ -147,20 +147,27 @@ __device__ __forceinline__ void diag_setup_a(const PassArgs& a, uint64_t hi, con
   const int tid = threadIdx.x;
   const int tb = a.tb;
   const int64_t nhi = (int64_t)1 << (a.n - tb);
+  // the first four schedules unrolled (their loads issued together); more
+  // schedules (a clause-by-clause path has one per clause) in a loop
+  constexpr int kUnrolled = 4;
   if (tid < tb) {
     double v = 0.0;
 #pragma unroll
-    for (int s = 0; s < kMaxDiagSched; ++s) {
+    for (int s = 0; s < kUnrolled; ++s) {
       if (s < a.dg.nsd) v += fsh[a.dg.sd_sid[s]] * a.dg.LT[((int64_t)s * nhi + (int64_t)hi) * tb + tid];
     }
+    for (int s = kUnrolled; s < a.dg.nsd; ++s)
+      v += fsh[a.dg.sd_sid[s]] * a.dg.LT[((int64_t)s * nhi + (int64_t)hi) * tb + tid];
     lin[tid] = v;
   }
   if (tid == 64) {
     double c = a.dconst;
 #pragma unroll
-    for (int s = 0; s < kMaxDiagSched; ++s) {
+    for (int s = 0; s < kUnrolled; ++s) {
       if (s < a.dg.nsd) c += fsh[a.dg.sd_sid[s]] * a.dg.CT[(int64_t)s * nhi + (int64_t)hi];
     }
+    for (int s = kUnrolled; s < a.dg.nsd; ++s)
+      c += fsh[a.dg.sd_sid[s]] * a.dg.CT[(int64_t)s * nhi + (int64_t)hi];
     *cp = c;
   }
 }
