@@ -155,7 +155,7 @@ def ec3_random_clauses(n, m, rng):
     """m different clauses, each over 3 different bits drawn uniformly (eq. (1clause)).
 
     Clauses are sorted triples of 1-based qubit labels; a duplicate clause is
-    redrawn, so all m are different (Sec. II.C asks for a set of different clauses).
+    redrawn, so all m are different (Sec. II.C requires distinct clauses).
     """
     if n < 3:
         raise ValueError("EC3 needs n >= 3")
