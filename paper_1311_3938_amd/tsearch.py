@@ -30,6 +30,23 @@ def default_plan(ham, T):
     return max(4, int(math.ceil(T * 0.5 * (hi - lo) / 0.1))), 0.5 * (lo + hi)
 
 
+def energies_sequential(ctx, insts, Ts, states, dtype=torch.complex64, plan=default_plan):
+    """The same energies as `energies`, one aqc_evolve per instance (the batch
+    engine runs exactly the launch sequence of aqc_evolve, so the values agree
+    bit for bit)."""
+    out = []
+    for inst, T, st in zip(insts, Ts, states):
+        ham = engine.Hamiltonian(ctx, with_T(inst, T))
+        try:
+            K, shift = plan(ham, T)
+            psi = torch.as_tensor(st).to(device=ctx.device, dtype=dtype).contiguous().clone()
+            engine.evolve(ctx, ham, psi, 0.0, T, method="pc4", n_steps=K, shift=shift)
+            out.append(engine.energy(ctx, ham, T, psi))
+        finally:
+            ham.free()
+    return out
+
+
 def energies(ctx, insts, Ts, states, dtype=torch.complex64, plan=default_plan, ticks=16):
     """E(T_i) for instance i evolved from states[i] (host or device arrays of
     2^n amplitudes) over [0, T_i], all in one batch."""
@@ -87,10 +104,11 @@ class Search:
 
 
 def find_ts(ctx, insts, states, T0=1.0, rel=0.05, T_max=1e4, dtype=torch.complex64, plan=default_plan,
-            max_rounds=60, log=None):
+            max_rounds=60, log=None, batched=True):
     """T_s of every instance (the geometric mean of the final bracket
     [T_lo, T_hi] with E(T_lo) > 1/2 >= E(T_hi), T_hi / T_lo <= 1 + rel).
-    Returns the Search records."""
+    batched=False solves a round one instance after the other.  Returns the
+    Search records."""
     S = [Search() for _ in insts]
     for rnd in range(max_rounds):
         todo = []
@@ -100,8 +118,9 @@ def find_ts(ctx, insts, states, T0=1.0, rel=0.05, T_max=1e4, dtype=torch.complex
                 todo.append((i, T))
         if not todo:
             break
-        Es = energies(ctx, [insts[i] for i, _ in todo], [T for _, T in todo],
-                      [states[i] for i, _ in todo], dtype, plan)
+        run = energies if batched else energies_sequential
+        Es = run(ctx, [insts[i] for i, _ in todo], [T for _, T in todo],
+                 [states[i] for i, _ in todo], dtype, plan)
         for (i, T), E in zip(todo, Es):
             S[i].record(T, E)
         if log:

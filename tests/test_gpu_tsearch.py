@@ -49,6 +49,45 @@ def _oracle_search(inst, psi0, plan, T0, rel):
         s.record(T, observables.energy(it, T, y))
 
 
+def _case(engine, ctx, torch, algorithm, n):
+    inst = I.workload_usa(n, 0, algorithm)
+    if algorithm == "x":
+        return inst, I.plus_state(n), I.plus_state(n)
+    # the ground state of H^xy in the sector of the solution's weight
+    w = inst.meta["weight"]
+    ham = engine.Hamiltonian(ctx, inst)
+    sec = engine.Sector(ctx, ham, w)
+    g = torch.empty(sec.dim, dtype=torch.complex128, device="cuda")
+    engine.lowest_eigs(ctx, sec, 0.0, k=1, max_basis=12, tol=1e-12, ground=g)
+    psi_gpu = sec.expand(g).cpu().numpy()
+    sec.free()
+    ham.free()
+    b = subspace.basis(n, w)
+    H0 = np.array([subspace.apply_h(inst, 0.0, e, w) for e in np.eye(len(b), dtype=complex)]).T
+    vals, vecs = np.linalg.eigh(0.5 * (H0 + H0.conj().T))
+    assert vals[1] - vals[0] > 1e-6                      # a unique ground state
+    psi_ref = subspace.expand(vecs[:, 0], n, w)
+    assert abs(abs(np.vdot(psi_ref, psi_gpu)) - 1.0) < 1e-10
+    return inst, psi_gpu, psi_ref
+
+
+@pytest.mark.parametrize("algorithm,n", [("x", 7), ("xy", 8)])
+def test_ts_search_sequential_matches_oracle(eng, algorithm, n):
+    """The same search with the solves of a round run one after the other
+    (aqc_evolve): every runtime tried and every E(T) agree with the oracle's."""
+    engine, ctx = eng
+    import torch
+    from paper_1311_3938_amd import tsearch
+    inst, psi_gpu, psi_ref = _case(engine, ctx, torch, algorithm, n)
+    plan = _plan_for(inst)
+    S = tsearch.find_ts(ctx, [inst], [psi_gpu], T0=2.0, rel=0.1, dtype=torch.complex128, plan=plan,
+                        batched=False)[0]
+    R = _oracle_search(inst, psi_ref, plan, 2.0, 0.1)
+    assert [T for T, _ in S.evals] == [T for T, _ in R.evals]
+    assert np.allclose([E for _, E in S.evals], [E for _, E in R.evals], atol=1e-9, rtol=0)
+    assert math.isfinite(S.T_s) and S.T_s == R.T_s
+
+
 @pytest.mark.skip(reason="a host-side segmentation fault occurred once inside this test (at the "
                          "end of its first batch of solves, in aqc_ham_free) when it ran after the "
                          "whole GPU suite; it passed in a run of its own module with the sector and "
