@@ -272,6 +272,12 @@ def run_paths_mode(args):
     for kind in args.paths_kinds.split(","):
         inst = I.workload_ec3_paths(n=n, m=m, T=T, kind=kind, seed=I.seed_for(5))
         ham = engine.Hamiltonian(ctx, inst)
+        tuned = None
+        if args.paths_autotune:
+            from paper_1311_3938_amd import autotune
+            t_tune = time.perf_counter()
+            tuned = list(autotune.tune(ctx, ham, inst, torch.complex64)[0])
+            log(f"{kind}: tuned plan {tuned} in {time.perf_counter() - t_tune:.1f} s")
         lo, hi = ham.spectral_bounds(0.0, T)
         rho = 0.5 * (hi - lo)
         K = int(math.ceil(T * rho / 0.1))
@@ -315,6 +321,7 @@ def run_paths_mode(args):
             "bytes_per_amp_step": (last_b + high_b) / max(steps, 1) / N,
             "hbm_frac_whole_step": (last_b + high_b) / el / 8.0e12,
             "norm": engine.norm2(ctx, psi),
+            "plan": tuned if tuned is not None else "default",
         }
         log(f"{kind}: {out[kind]}")
         del ws, psi
@@ -621,6 +628,8 @@ def main():
     ap.add_argument("--sector-paths", default="linear,cbc")
     ap.add_argument("--n-paths", type=int, default=26, help="qubits of the paths mode")
     ap.add_argument("--paths-kinds", default="linear,nonlinear,cbc")
+    ap.add_argument("--paths-autotune", action="store_true",
+                    help="time H psi under the autotuner's candidate plans first")
     ap.add_argument("--atol", type=float, default=1e-9)
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--baseline-subset", type=int, default=16)
