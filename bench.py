@@ -96,7 +96,7 @@ def error_summary(dFs, reqs, res):
 def run_batch_mode(args):
     """Mixed batch of independent solves (EC3 and SK, n uniform in 14..22, XX
     catalysts, T uniform in 10..100) admitted together into one batch;
-    complex64 state, float64 reductions, graph-captured ticks."""
+    complex64 state, float64 reductions, ticks launched as graphs."""
     import numpy as np
     import torch
     from paper_1311_3938_amd import engine, serve
@@ -130,7 +130,7 @@ def run_batch_mode(args):
         "steps": 1, "warmup": 0, "ms_per_step": wall * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
         "config": {"workload": f"{len(res)} mixed EC3/SK solves, n 14..22, XX catalysts, "
-                               "T 10..100, pc4, graph-captured batch ticks",
+                               "T 10..100, pc4, batch ticks launched as graphs",
                    "solves": len(res)},
         "amp_updates_per_s": amp_steps / wall,
         "autotune_s_before_timing": tune_s,
