@@ -506,8 +506,16 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
           for (int u = 0; u < EB; ++u) {
             if (!ok[u]) continue;
             const uint32_t l = tid + kThreads * (jb + u);
-            const uint64_t src_idx = gidx_of(u) ^ gr.x;
-            const int q = 2 * ((int)((src_idx >> bi) & 1ull) | ((int)((src_idx >> bj) & 1ull) << 1));
+            int q;
+            if constexpr (FINAL) {
+              // the last pass's tile is the low tb bits: the source's bits
+              // bi, bj are those of its tile index
+              const uint32_t sl = l ^ gr.xl;
+              q = 2 * (int)(((sl >> bi) & 1u) | (((sl >> bj) & 1u) << 1));
+            } else {
+              const uint64_t src_idx = gidx_of(u) ^ gr.x;
+              q = 2 * ((int)((src_idx >> bi) & 1ull) | ((int)((src_idx >> bj) & 1ull) << 1));
+            }
             const R cr = fc[q], ci = fc[q + 1];
             const V v = tile[l ^ gr.xl];
             hr[u] += cr * v.x - ci * v.y;
