@@ -80,14 +80,15 @@ def test_paths_apply_n16(eng, kind, dt):
     ham.free()
 
 
+# pc4 restarted per clause window only matters where the schedules have kinks
+CASES = [(k, m, False) for k in KINDS for m in ("rk4", "pc4")] + [("cbc", "pc4", True)]
+
+
 @pytest.mark.parametrize("dt", ["c128", "c64"])
-@pytest.mark.parametrize("method,windows", [("rk4", False), ("pc4", False), ("pc4", True)])
-@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("kind,method,windows", CASES)
 def test_paths_evolve(eng, kind, method, windows, dt):
     """The whole path [0, T] from the Dicke state: RK4, pc4 across the clause
     kinks, and pc4 restarted at every kink (one call per window of T/m)."""
-    if windows and kind != "cbc":
-        pytest.skip("windows only matter where the schedules have kinks")
     engine, ctx = eng
     inst, K, shift = _case(kind)
     ham = engine.Hamiltonian(ctx, inst)
