@@ -502,7 +502,7 @@ def run_tsearch_mode(args):
                 ham.free()
             t0 = time.perf_counter()
             S = tsearch.find_ts(ctx, insts, states, T0=4.0, rel=args.ts_rel, dtype=torch.complex64,
-                                log=log)
+                                log=log, batched=args.ts_batched)
             el = time.perf_counter() - t0
             ts = [s.T_s for s in S]
             ns = sum(len(s.evals) for s in S)
@@ -520,7 +520,8 @@ def run_tsearch_mode(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
         "config": {"workload": f"T_s search, hard EC3 instances with a unique solution, n in {sizes}, "
                                f"{args.ts_instances} per size, algorithms {args.ts_algorithms}, "
-                               f"bracket ratio {1 + args.ts_rel:g}"},
+                               f"bracket ratio {1 + args.ts_rel:g}, "
+                               + ("batched rounds" if args.ts_batched else "sequential solves")},
         "runs": out,
     }
     print(json.dumps(res), flush=True)
@@ -619,6 +620,8 @@ def main():
     ap.add_argument("--ts-instances", type=int, default=8)
     ap.add_argument("--ts-algorithms", default="x,xy")
     ap.add_argument("--ts-rel", type=float, default=0.05)
+    ap.add_argument("--ts-batched", action="store_true",
+                    help="solve each round of the T_s search as one batch")
     ap.add_argument("--n-gap", type=int, default=20)
     ap.add_argument("--gap-path", default="cbc")
     ap.add_argument("--gap-points", type=int, default=21)

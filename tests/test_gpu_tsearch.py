@@ -117,7 +117,8 @@ def test_ts_search_matches_oracle(eng, algorithm, n):
         assert vals[1] - vals[0] > 1e-6                      # a unique ground state
         psi_ref = subspace.expand(vecs[:, 0], n, w)
         assert abs(abs(np.vdot(psi_ref, psi_gpu)) - 1.0) < 1e-10
-    S = tsearch.find_ts(ctx, [inst], [psi_gpu], T0=2.0, rel=0.1, dtype=torch.complex128, plan=plan)[0]
+    S = tsearch.find_ts(ctx, [inst], [psi_gpu], T0=2.0, rel=0.1, dtype=torch.complex128, plan=plan,
+                        batched=True)[0]
     R = _oracle_search(inst, psi_ref, plan, 2.0, 0.1)
     assert [T for T, _ in S.evals] == [T for T, _ in R.evals]
     assert np.allclose([E for _, E in S.evals], [E for _, E in R.evals], atol=1e-9, rtol=0)
