@@ -1,0 +1,136 @@
+"""Drive the host code of the library, built against the CPU stand-in of the
+HIP runtime (fake_hip.cpp) with AddressSanitizer, through the Python front
+end: Hamiltonian compilation for every workload family, tilings, H|psi>,
+fixed, chained and adaptive evolution, reductions, sectors, Lanczos, the host
+eigensolver and the batch engine with retire / re-admit and graphs, then the
+batched energies of the T_s search.  Prints "host paths done" and exits 0
+when every path ran and no handle is left alive.
+
+Usage: python drive.py <path of the instrumented libaqc.so>"""
+import ctypes as C
+import os
+import sys
+import types
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "..", ".."))
+import numpy as np
+import torch
+
+from paper_1311_3938_amd import _lib as L
+
+L.LIB_PATH = sys.argv[1]
+from paper_1311_3938_amd import engine, instances as I, tsearch  # noqa: E402
+from paper_1311_3938_amd._lib import check, lib  # noqa: E402
+
+
+class CpuCtx(engine.Context):
+    """A context whose "device" tensors are host tensors (the stand-in
+    runtime's device memory is host memory)."""
+
+    def __init__(self):
+        self.device = torch.device("cpu")
+        self.stream = types.SimpleNamespace(cuda_stream=0)
+        h = C.c_void_p()
+        check(lib().aqc_create(0, C.c_void_p(0), C.byref(h)))
+        self._h = h
+
+
+def expect(f, *errors):
+    """Run f; library errors with one of the given statuses are expected
+    outcomes of kernels that compute nothing (no convergence and the like)."""
+    try:
+        return f()
+    except L.AqcError as e:
+        if e.status not in errors:
+            raise
+
+
+def main():
+    lib().fake_hip_live.restype = C.c_long
+    base = lib().fake_hip_live()
+    ctx = CpuCtx()
+    insts = [I.workload_sk_sin2(n=12), I.workload_ec3_catalyst(n=14, m=12, n_pairs=10),
+             I.workload_ec3_paths(n=13, kind="cbc"), I.workload_ec3_paths(n=13, kind="nonlinear"),
+             I.workload_usa(10, 0, "xy"), I.workload_usa(10, 1, "xyz")]
+    for inst in insts:
+        for dt in (torch.complex64, torch.complex128):
+            ham = engine.Hamiltonian(ctx, inst)
+            N = 1 << inst.n
+            psi = torch.zeros(N, dtype=dt)
+            psi[0] = 1
+            engine.apply(ctx, ham, 0.3, psi, torch.empty_like(psi))
+            ham.spectral_bounds(0.0, inst.path["T"])
+            engine.evolve(ctx, ham, psi, 0.0, 1.0, method="pc4", n_steps=10, shift="center")
+            engine.evolve(ctx, ham, psi, 0.0, 1.0, method="rk4", n_steps=5)
+            expect(lambda: engine.evolve(ctx, ham, psi, 0.0, 1.0, method="pc4", n_steps=0, atol=1e-6,
+                                         h0=0.01, window=4, hmin=1e-3, record_cap=16), L.AQC_EUNSTABLE)
+            carry, ws = engine.new_carry(), engine.workspace(ctx, 1 << 25)
+            for k in range(3):
+                engine.evolve(ctx, ham, psi, 0.1 * k, 0.1 * (k + 1), ws=ws, carry=carry, method="pc4",
+                              n_steps=5, shift=0.5)
+            engine.energy(ctx, ham, 1.0, psi)
+            engine.ground_mass(ctx, ham, 1.0, psi)
+            engine.norm2(ctx, psi)
+            engine.overlap(ctx, psi, psi)
+            engine.fidelity_basis(ctx, psi, [0, 1, 3])
+            for til in ((12, 12, 4, 3), (11, 12, 3, 2), (13, 13, 4, 4), (10, 11, 3, 0), (12, 13, 5, 7)):
+                ham.set_tiling(dt, *til)
+                engine.apply(ctx, ham, 0.3, psi, torch.empty_like(psi))
+            expect(lambda: engine.lowest_eigs(ctx, ham, 0.5, k=2, dtype=dt, max_basis=12, max_matvecs=60),
+                   L.AQC_EUNSTABLE)
+            keeps = all(bin(int(x)).count("1") in (0, 2) for x in inst.x)
+            for w in ((1, inst.n // 2, inst.n - 1) if keeps else ()):
+                sec = engine.Sector(ctx, ham, w)
+                sec.dicke(dt)
+                sp = torch.zeros(sec.dim, dtype=dt)
+                sp[0] = 1
+                sec.expand(sp)
+                engine.apply(ctx, sec, 0.4, sp, torch.empty_like(sp))
+                engine.evolve(ctx, sec, sp, 0.0, 1.0, method="pc4", n_steps=8, shift="center")
+                engine.energy(ctx, sec, 1.0, sp)
+                engine.ground_mass(ctx, sec, 1.0, sp)
+                expect(lambda: engine.lowest_eigs(ctx, sec, 0.5, k=2, dtype=dt, max_basis=10, max_matvecs=40),
+                       L.AQC_EUNSTABLE)
+                sec.free()
+            ham.free()
+    rng = np.random.default_rng(1)
+    for n in (1, 2, 5, 17, 48):
+        a = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+        a = a + a.conj().T
+        w, _ = engine.hermitian_eigh(a)
+        assert np.max(np.abs(np.sort(w) - np.linalg.eigvalsh(a))) < 1e-10 * max(1.0, np.abs(w).max())
+    # a batch smaller than its queue: solves retire and new ones are admitted
+    for graph in (True, False):
+        b = engine.Batch(ctx, torch.complex64, capacity=6, graph=graph)
+        hams = [engine.Hamiltonian(ctx, I.workload_batch_member(k, 10, 14)) for k in range(10)]
+        nxt = 0
+
+        def admit():
+            nonlocal nxt
+            psi = torch.zeros(1 << hams[nxt].n, dtype=torch.complex64)
+            psi[0] = 1
+            b.admit(hams[nxt], psi, 0.0, 1.0, 5 + 3 * nxt, 0.3)
+            nxt += 1
+
+        while nxt < 6:
+            admit()
+        while b.info()["active"] or nxt < 10:
+            b.step(5)
+            for s in b.poll():
+                b.retire(s)
+                if nxt < 10:
+                    admit()
+        b.close()
+        for h in hams:
+            h.free()
+    for alg, n in (("x", 7), ("xy", 8), ("xy", 10)):
+        insts = [I.workload_usa(n, k, alg) for k in range(3)]
+        tsearch.energies(ctx, insts, [1.0, 2.0, 3.0], [I.plus_state(n)] * 3)
+    ctx.close()
+    live = lib().fake_hip_live() - base
+    assert live == 0, f"{live} runtime handles left alive"
+    print("host paths done", flush=True)
+
+
+if __name__ == "__main__":
+    main()
