@@ -363,7 +363,7 @@ class Batch:
         self._h = h
         self.capacity = capacity
         self.set_graph(graph)
-        self._keep = {}   # slot -> (psi, workspace) kept alive until retired
+        self._keep = {}   # slot -> (psi, workspace, Hamiltonian) kept alive until retired
 
     def set_graph(self, on):
         check(lib().aqc_batch_set_graph(self._h, 1 if on else 0))
