@@ -1395,7 +1395,7 @@ extern "C" aqc_status aqc_sector_create(aqc_ctx* ctx, const aqc_ham* src, int we
           v += binom64(4 * c + b, cnt + j + 1);
           ++j;
         }
-        if (valid && v <= 0xFFFFFFFFull) rtab[((size_t)c * 16 + nib) * w1 + cnt] = (uint32_t)v;
+        if (valid && v <= 0xFFFFFFFFull) rtab[((size_t)c * w1 + cnt) * 16 + nib] = (uint32_t)v;
       }
   std::vector<SecHop> hops;
   std::vector<DevTerm> hterms;

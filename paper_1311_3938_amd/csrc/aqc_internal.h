@@ -161,7 +161,7 @@ struct SectorDev {
   int32_t nmasks, nres;
   int64_t dim;         // C(n, w)
   const uint32_t* binom;   // [kSecBinom][kSecBinom]
-  const uint32_t* rtab;    // [nch][16][w + 1]: rank part of a chunk given the 1-bits below it
+  const uint32_t* rtab;    // [nch][w + 1][16]: rank part of a chunk given the 1-bits below it
   const SecHop* hops;
   const DevTerm* hterms;
   const SecMask* masks;

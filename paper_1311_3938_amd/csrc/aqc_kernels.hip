@@ -1282,17 +1282,6 @@ __device__ __forceinline__ uint64_t sector_unrank(const uint32_t* binom, int n, 
   return z;
 }
 
-__device__ __forceinline__ uint32_t sector_rank(const uint32_t* rtab, int nch, int w1, uint64_t z) {
-  uint32_t r = 0;
-  int cnt = 0;
-  for (int c = 0; c < nch; ++c) {
-    const uint32_t nib = (uint32_t)(z >> (4 * c)) & 15u;
-    r += rtab[(c * 16 + (int)nib) * w1 + cnt];
-    cnt += __popc(nib);
-  }
-  return r;
-}
-
 // the next larger integer with the same number of 1-bits (Gosper)
 __device__ __forceinline__ uint64_t next_same_weight(uint64_t z) {
   const uint64_t c = z & (0ull - z);
@@ -1343,10 +1332,14 @@ template <typename R>
 __global__ __launch_bounds__(kSecThreads) void k_sector(const SectorArgs a) {
   using V = typename CT2<R>::V;
   __shared__ SecLds L;
-  __shared__ R tm[kSecMaxHopTerms];
-  __shared__ R hc[4 * kSecMaxHops];
-  sector_setup(a, L);
+  // hop coefficients (4 per hop) and per-term values of the other hops, sized
+  // to this sector at launch (sector_dyn_lds_bytes) so that more workgroups
+  // share a compute unit
+  extern __shared__ __align__(16) unsigned char smem[];
   const SectorDev& s = a.s;
+  R* hc = reinterpret_cast<R*>(smem);
+  R* tm = hc + 4 * s.nhops;
+  sector_setup(a, L);
   sector_hop_setup<R>(s, L, tm, hc);
   __syncthreads();
   const V* __restrict__ src = reinterpret_cast<const V*>(a.src);
@@ -1360,8 +1353,6 @@ __global__ __launch_bounds__(kSecThreads) void k_sector(const SectorArgs a) {
     const int64_t rf = base + (int64_t)threadIdx.x * kSecEPT;
     uint64_t zs[kSecEPT];
     bool ok[kSecEPT];
-    // the rank table part of each chunk of each state
-    uint32_t contrib[kSecEPT][kSecMaxChunks];
     {
       uint64_t z = rf < s.dim ? sector_unrank(L.binom, s.n, s.w, rf) : 0ull;
 #pragma unroll
@@ -1369,16 +1360,6 @@ __global__ __launch_bounds__(kSecThreads) void k_sector(const SectorArgs a) {
         ok[u] = rf + u < s.dim;
         zs[u] = z;
         if (u + 1 < kSecEPT && rf + u + 1 < s.dim) z = next_same_weight(z);
-        int cnt = 0;
-#pragma unroll
-        for (int c = 0; c < kSecMaxChunks; ++c) {
-          contrib[u][c] = 0u;
-          if (c < s.nch && ok[u]) {
-            const uint32_t nib = (uint32_t)(zs[u] >> (4 * c)) & 15u;
-            contrib[u][c] = L.rtab[(c * 16 + (int)nib) * w1 + cnt];
-            cnt += __popc(nib);
-          }
-        }
       }
     }
     R hr[kSecEPT], hi[kSecEPT];
@@ -1386,23 +1367,26 @@ __global__ __launch_bounds__(kSecThreads) void k_sector(const SectorArgs a) {
     for (int u = 0; u < kSecEPT; ++u) hr[u] = hi[u] = 0;
     for (int k = 0; k < s.nhops; ++k) {
       const SecHop hp = s.hops[k];
+      // the chunks of the two bits and the bits below the first (uniform)
       const int ca = hp.bi >> 2, cb = hp.bj >> 2;
+      const uint64_t below = (1ull << (4 * ca)) - 1ull;
 #pragma unroll
       for (int u = 0; u < kSecEPT; ++u) {
         const uint64_t z = zs[u];
         const uint32_t zi = (uint32_t)(z >> hp.bi) & 1u, zj = (uint32_t)(z >> hp.bj) & 1u;
         if (!ok[u] || zi == zj) continue;
         const uint64_t zp = z ^ hp.x;
-        // rank of the partner: only the chunks from bi's to bj's change; between
-        // them the number of 1-bits below moves by zp_bi - z_bi
+        // rank of the partner: only the chunks from bi's to bj's change, and
+        // above bi's chunk the number of 1-bits below moves by zp_bi - z_bi;
+        // the chunk loop is the same for every lane
         const int delta = zi ? -1 : 1;
+        int cn = __popcll(z & below);
         uint32_t rp = (uint32_t)(rf + u);
-#pragma unroll
-        for (int c = 0; c < kSecMaxChunks; ++c) {
-          if (c < ca || c > cb) continue;
-          const uint32_t nib = (uint32_t)(zp >> (4 * c)) & 15u;
-          const int cn = __popcll(z & ((1ull << (4 * c)) - 1ull)) + (c > ca ? delta : 0);
-          rp += L.rtab[(c * 16 + (int)nib) * w1 + cn] - contrib[u][c];
+        for (int c = ca; c <= cb; ++c) {
+          const uint32_t nz = (uint32_t)(z >> (4 * c)) & 15u, np = (uint32_t)(zp >> (4 * c)) & 15u;
+          const uint32_t* row = L.rtab + c * w1 * 16;
+          rp += row[(cn + (c > ca ? delta : 0)) * 16 + (int)np] - row[cn * 16 + (int)nz];
+          cn += __popc(nz);
         }
         // a weight-w state has a rank below dim; the clamp only guards the read
         const V pv = src[min((int64_t)rp, s.dim - 1)];
@@ -1489,10 +1473,18 @@ __global__ __launch_bounds__(kSecThreads) void k_sector(const SectorArgs a) {
   if (e.red_flags) block_reduce3<kSecThreads>(r0, r1, r2, e.red_flags, L.red, e.red, gridDim.x, blockIdx.x);
 }
 
+// dynamic LDS of k_sector: 4 coefficients per hop and one value per hop term
+static size_t sector_dyn_lds_bytes(const SectorDev& sd, int dtype) {
+  return (size_t)(4 * sd.nhops + sd.nhterms) * (dtype == 0 ? sizeof(float) : sizeof(double));
+}
+
 hipError_t launch_sector_matvec(const SectorArgs& a, int dtype, hipStream_t s) {
+  if (a.s.nhops < 0 || a.s.nhops > kSecMaxHops || a.s.nhterms < 0 || a.s.nhterms > kSecMaxHopTerms)
+    return hipErrorInvalidValue;
   const dim3 grid((unsigned)sector_blocks(a.s.dim)), block(kSecThreads);
-  if (dtype == 0) hipLaunchKernelGGL(k_sector<float>, grid, block, 0, s, a);
-  else hipLaunchKernelGGL(k_sector<double>, grid, block, 0, s, a);
+  const size_t dyn = sector_dyn_lds_bytes(a.s, dtype);
+  if (dtype == 0) hipLaunchKernelGGL(k_sector<float>, grid, block, dyn, s, a);
+  else hipLaunchKernelGGL(k_sector<double>, grid, block, dyn, s, a);
   return hipGetLastError();
 }
 
