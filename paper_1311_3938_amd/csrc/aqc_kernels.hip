@@ -1175,7 +1175,6 @@ hipError_t launch_copy(void* dst, const void* src, int dtype, int64_t N, hipStre
 // ---------------------------------------------------------------------------
 struct SecLds {
   uint32_t binom[kSecBinom * kSecBinom];
-  uint32_t rtab[kSecMaxChunks * 16 * (kSecMaxN + 1)];
   double hsh[kSecMaxN];      // one-bit coefficients h_p (sigma^z_p)
   double rsh[kSecMaxN];      // R_p = sum_q J_pq
   double a[kSecMaxN];        // per-bit part of the diagonal
@@ -1197,8 +1196,6 @@ __device__ void sector_setup(const SectorArgs& a, SecLds& L) {
   const int n = s.n;
   if (tid < kMaxSched) L.fsh[tid] = a.f[tid];
   for (int i = tid; i < kSecBinom * kSecBinom; i += kSecThreads) L.binom[i] = s.binom[i];
-  const int nrt = s.nch * 16 * (s.w + 1);
-  for (int i = tid; i < nrt; i += kSecThreads) L.rtab[i] = s.rtab[i];
   for (int i = tid; i < n * n; i += kSecThreads) L.J[i] = 0.0;
   if (tid < n) L.hsh[tid] = 0.0;
   __syncthreads();
@@ -1328,17 +1325,25 @@ __device__ __forceinline__ void sector_hop_setup(const SectorDev& s, const SecLd
   }
 }
 
+// the rank table's share of k_sector's dynamic LDS, padded to 16 bytes
+__host__ __device__ __forceinline__ size_t sector_rtab_lds_bytes(const SectorDev& sd) {
+  return ((size_t)sd.nch * 16 * (sd.w + 1) * sizeof(uint32_t) + 15) & ~(size_t)15;
+}
+
 template <typename R>
-__global__ __launch_bounds__(kSecThreads) void k_sector(const SectorArgs a) {
+__global__ __launch_bounds__(kSecThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_sector(const SectorArgs a) {
   using V = typename CT2<R>::V;
   __shared__ SecLds L;
-  // hop coefficients (4 per hop) and per-term values of the other hops, sized
-  // to this sector at launch (sector_dyn_lds_bytes) so that more workgroups
-  // share a compute unit
+  // the rank table, the hop coefficients (4 per hop) and per-term values of
+  // the other hops, sized to this sector at launch (sector_dyn_lds_bytes) so
+  // that more workgroups share a compute unit
   extern __shared__ __align__(16) unsigned char smem[];
   const SectorDev& s = a.s;
-  R* hc = reinterpret_cast<R*>(smem);
+  const int nrt = s.nch * 16 * (s.w + 1);
+  uint32_t* rtab = reinterpret_cast<uint32_t*>(smem);
+  R* hc = reinterpret_cast<R*>(smem + sector_rtab_lds_bytes(s));
   R* tm = hc + 4 * s.nhops;
+  for (int i = threadIdx.x; i < nrt; i += kSecThreads) rtab[i] = s.rtab[i];
   sector_setup(a, L);
   sector_hop_setup<R>(s, L, tm, hc);
   __syncthreads();
@@ -1384,7 +1389,7 @@ __global__ __launch_bounds__(kSecThreads) void k_sector(const SectorArgs a) {
         uint32_t rp = (uint32_t)(rf + u);
         for (int c = ca; c <= cb; ++c) {
           const uint32_t nz = (uint32_t)(z >> (4 * c)) & 15u, np = (uint32_t)(zp >> (4 * c)) & 15u;
-          const uint32_t* row = L.rtab + c * w1 * 16;
+          const uint32_t* row = rtab + c * w1 * 16;
           rp += row[(cn + (c > ca ? delta : 0)) * 16 + (int)np] - row[cn * 16 + (int)nz];
           cn += __popc(nz);
         }
@@ -1473,13 +1478,16 @@ __global__ __launch_bounds__(kSecThreads) void k_sector(const SectorArgs a) {
   if (e.red_flags) block_reduce3<kSecThreads>(r0, r1, r2, e.red_flags, L.red, e.red, gridDim.x, blockIdx.x);
 }
 
-// dynamic LDS of k_sector: 4 coefficients per hop and one value per hop term
+// dynamic LDS of k_sector: the rank table, then 4 coefficients per hop and
+// one value per hop term
 static size_t sector_dyn_lds_bytes(const SectorDev& sd, int dtype) {
-  return (size_t)(4 * sd.nhops + sd.nhterms) * (dtype == 0 ? sizeof(float) : sizeof(double));
+  return sector_rtab_lds_bytes(sd) +
+         (size_t)(4 * sd.nhops + sd.nhterms) * (dtype == 0 ? sizeof(float) : sizeof(double));
 }
 
 hipError_t launch_sector_matvec(const SectorArgs& a, int dtype, hipStream_t s) {
-  if (a.s.nhops < 0 || a.s.nhops > kSecMaxHops || a.s.nhterms < 0 || a.s.nhterms > kSecMaxHopTerms)
+  if (a.s.nhops < 0 || a.s.nhops > kSecMaxHops || a.s.nhterms < 0 || a.s.nhterms > kSecMaxHopTerms ||
+      a.s.nch < 1 || a.s.nch > kSecMaxChunks || a.s.w < 0 || a.s.w > kSecMaxN)
     return hipErrorInvalidValue;
   const dim3 grid((unsigned)sector_blocks(a.s.dim)), block(kSecThreads);
   const size_t dyn = sector_dyn_lds_bytes(a.s, dtype);
