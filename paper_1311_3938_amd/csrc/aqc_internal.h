@@ -136,7 +136,8 @@ constexpr int kSecMaxN = 34;
 constexpr int kSecBinom = 35;       // binomial table C(p, k), p, k <= 34
 constexpr int kSecMaxChunks = 9;    // 4-bit chunks of the rank table
 constexpr int kSecMaxHopTerms = 1024;
-constexpr int kSecGrid = 4096;      // at most this many workgroups per launch
+constexpr int kSecGrid = 3840;      // at most this many workgroups per launch: three rounds of
+                                     // 256 compute units x 5 resident workgroups of k_sector
 
 // A weight-preserving flip of two bits and its terms (as DevGroup).
 struct SecHop {
