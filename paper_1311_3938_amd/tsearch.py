@@ -2,8 +2,9 @@
 E(T) = <psi(T)|H_f|psi(T)> falls to 1/2 (with E_1 = 0 and every excited level
 at least 1, E(T) <= 1/2 means a ground-state population of at least one
 half).  Every instance of a set is bracketed by doubling T and then bisected
-in log T; the evaluations of one round, one full solve per instance, run
-together in one batch (aqc_batch_*), so a round costs about one solve of
+in log T; a round evaluates every unfinished instance once, by one full
+solve each: one aqc_evolve after the other, or on request all of them
+together in one batch (aqc_batch_*), where a round costs about one solve of
 the largest instance.  Each solve is a fixed-step pc4 run on the library."""
 from __future__ import annotations
 
