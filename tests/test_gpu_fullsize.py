@@ -194,3 +194,28 @@ def test_sector_apply_sampled_rows_max_qubits(eng, w):
     sec.free()
     ham.free()
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n", [32, 33])
+def test_apply_sampled_rows_past_32bit_indices(eng, n):
+    """H psi of the SK workload with amplitude indices past 2^31 (n = 32) and
+    past 2^32 (n = 33, 64 GiB per complex64 vector): sampled rows, the first
+    and the last amplitude among them, against the oracle's row-wise product."""
+    engine, ctx, torch = eng
+    inst = I.workload_sk_sin2(n=n, T=30.0, seed=I.seed_for(2))
+    ham = engine.Hamiltonian(ctx, inst)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    psi = torch.randn(1 << n, dtype=torch.complex64, device="cuda", generator=g)
+    out = engine.apply(ctx, ham, 17.0, psi)
+    rows = _rows(np.random.default_rng(6), n)
+
+    def values_at(idx):
+        t = torch.from_numpy(np.ascontiguousarray(idx)).to("cuda")
+        return psi.index_select(0, t).cpu().to(torch.complex128).numpy()
+
+    want = sqh.apply_h_rows(inst, 17.0, values_at, rows)
+    got = out.index_select(0, torch.from_numpy(rows).to("cuda")).cpu().to(torch.complex128).numpy()
+    assert np.max(np.abs(got - want)) / np.abs(want).max() < 5e-6
+    del out, psi
+    ham.free()
+    torch.cuda.empty_cache()
