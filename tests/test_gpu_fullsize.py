@@ -1,6 +1,7 @@
 """Checks at the benchmark's full size (n = 30, 2^30 amplitudes, complex64, the
-three-pass plan the benchmark times): sampled outputs against the oracle's
-row-wise product, and closed forms that hold at any size."""
+three-pass plan the benchmark times) and above it (n = 32, 33; sectors at
+n = 34): sampled outputs against the oracle's row-wise product, and closed
+forms that hold at any size."""
 import math
 
 import numpy as np
