@@ -3,7 +3,7 @@ HIP runtime (fake_hip.cpp) with AddressSanitizer, through the Python front
 end: Hamiltonian compilation for every workload family, tilings, H|psi>,
 fixed, chained and adaptive evolution, reductions, sectors, Lanczos, the host
 eigensolver and the batch engine with retire / re-admit and graphs, then the
-batched energies of the T_s search.  Prints "host paths done" and exits 0
+batched energies and whole batched rounds of the T_s search.  Prints "host paths done" and exits 0
 when every path ran and no handle is left alive.
 
 Usage: python drive.py <path of the instrumented libaqc.so>"""
@@ -126,6 +126,12 @@ def main():
     for alg, n in (("x", 7), ("xy", 8), ("xy", 10)):
         insts = [I.workload_usa(n, k, alg) for k in range(3)]
         tsearch.energies(ctx, insts, [1.0, 2.0, 3.0], [I.plus_state(n)] * 3)
+    # whole batched searches: every round creates and closes a batch and its
+    # Hamiltonians (the stand-in's energies are 1, so T doubles up to T_max)
+    insts = [I.workload_usa(8, k, "xy") for k in range(4)]
+    S = tsearch.find_ts(ctx, insts, [I.plus_state(8)] * 4, T_max=64.0, batched=True,
+                        plan=lambda ham, T: (int(8 + T), 0.5))
+    assert all(len(s.evals) == 7 for s in S)
     ctx.close()
     live = lib().fake_hip_live() - base
     assert live == 0, f"{live} runtime handles left alive"
