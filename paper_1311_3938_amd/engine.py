@@ -6,7 +6,6 @@ into libaqc.so (include/aqc.h)."""
 from __future__ import annotations
 
 import ctypes as C
-import math
 
 import numpy as np
 import torch
@@ -141,6 +140,7 @@ class Sector(Hamiltonian):
 
     def expand(self, psi):
         """The 2^n state with the sector's amplitudes and zeros elsewhere."""
+        _check_state(self.ctx, self, psi)
         out = torch.empty(1 << self.n, dtype=psi.dtype, device=psi.device)
         check(lib().aqc_sector_expand(self.ctx.handle, self._h, _ptr(psi), _ptr(out), dtype_code(psi)))
         return out
@@ -256,9 +256,22 @@ def overlap(ctx, phi, psi):
     return complex(re.value, im.value)
 
 
+def _full_space_n(psi):
+    """n of a 2^n-amplitude state (the C calls below take n, not a length)."""
+    N = psi.numel()
+    if N < 1 or N & (N - 1):
+        raise ValueError(f"a full-space state has 2^n amplitudes, got {N}")
+    if not psi.is_contiguous():
+        raise ValueError("state must be contiguous")
+    return N.bit_length() - 1
+
+
 def fidelity_state(ctx, psi, phi):
+    _full_space_n(psi)
+    if phi.numel() != psi.numel() or phi.dtype != psi.dtype or phi.device != psi.device or not phi.is_contiguous():
+        raise ValueError("target state must match the state's size, type and device")
     out = C.c_double()
-    check(lib().aqc_fidelity(ctx.handle, _ptr(psi), dtype_code(psi), int(math.log2(psi.numel())),
+    check(lib().aqc_fidelity(ctx.handle, _ptr(psi), dtype_code(psi), _full_space_n(psi),
                              L.TARGET_STATE, _ptr(phi), 0, C.byref(out)))
     return out.value
 
@@ -266,13 +279,14 @@ def fidelity_state(ctx, psi, phi):
 def fidelity_basis(ctx, psi, indices):
     idx = np.ascontiguousarray(np.asarray(indices, dtype=np.int64))
     out = C.c_double()
-    check(lib().aqc_fidelity(ctx.handle, _ptr(psi), dtype_code(psi), int(math.log2(psi.numel())),
+    check(lib().aqc_fidelity(ctx.handle, _ptr(psi), dtype_code(psi), _full_space_n(psi),
                              L.TARGET_BASIS_LIST, idx.ctypes.data_as(C.c_void_p), len(idx),
                              C.byref(out)))
     return out.value
 
 
 def ground_mass(ctx, ham, t, psi, rel_tol=1e-9):
+    _check_state(ctx, ham, psi)
     mass, emin = C.c_double(), C.c_double()
     check(lib().aqc_ground_mass(ctx.handle, ham.handle, float(t), _ptr(psi), dtype_code(psi),
                                 float(rel_tol), C.byref(mass), C.byref(emin)))
@@ -280,7 +294,7 @@ def ground_mass(ctx, ham, t, psi, rel_tol=1e-9):
 
 
 def energy(ctx, ham, t, psi, ws=None):
-    dt = dtype_code(psi)
+    dt = _check_state(ctx, ham, psi)
     need = lib().aqc_apply_workspace_bytes(ham.handle, dt)
     if need and ws is None:
         ws = workspace(ctx, need)

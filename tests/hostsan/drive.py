@@ -73,6 +73,15 @@ def main():
             engine.norm2(ctx, psi)
             engine.overlap(ctx, psi, psi)
             engine.fidelity_basis(ctx, psi, [0, 1, 3])
+            engine.fidelity_state(ctx, psi, psi.clone())
+            for bad in (lambda: engine.fidelity_state(ctx, psi, psi[:-1].clone()),
+                        lambda: engine.fidelity_basis(ctx, psi[:-1].clone(), [0])):
+                try:
+                    bad()
+                except ValueError:
+                    pass
+                else:
+                    raise AssertionError("a state of the wrong size was accepted")
             for til in ((12, 12, 4, 3), (11, 12, 3, 2), (13, 13, 4, 4), (10, 11, 3, 0), (12, 13, 5, 7)):
                 ham.set_tiling(dt, *til)
                 engine.apply(ctx, ham, 0.3, psi, torch.empty_like(psi))
@@ -85,6 +94,16 @@ def main():
                 sp = torch.zeros(sec.dim, dtype=dt)
                 sp[0] = 1
                 sec.expand(sp)
+                # the wrappers check sizes the C calls do not take
+                for bad in (lambda: sec.expand(torch.zeros(sec.dim + 1, dtype=dt)),
+                            lambda: engine.energy(ctx, sec, 1.0, torch.zeros(sec.dim - 1, dtype=dt)),
+                            lambda: engine.ground_mass(ctx, ham, 1.0, sp)):
+                    try:
+                        bad()
+                    except ValueError:
+                        pass
+                    else:
+                        raise AssertionError("a state of the wrong size was accepted")
                 engine.apply(ctx, sec, 0.4, sp, torch.empty_like(sp))
                 engine.evolve(ctx, sec, sp, 0.0, 1.0, method="pc4", n_steps=8, shift="center")
                 engine.energy(ctx, sec, 1.0, sp)
