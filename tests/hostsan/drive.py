@@ -112,6 +112,28 @@ def main():
                        L.AQC_EUNSTABLE)
                 sec.free()
             ham.free()
+    # sector limits and refusals, decided on the host
+    full_xy = I.TermList(34)
+    for i in range(1, 35):
+        for j in range(i + 1, 35):
+            full_xy.add({i: "X", j: "X"}, -0.5, 0)
+            full_xy.add({i: "Y", j: "Y"}, -0.5, 0)
+    big = engine.Hamiltonian(ctx, full_xy.instance([I.SCHED_S], I.linear_path(1.0)))
+    sk = engine.Hamiltonian(ctx, I.workload_sk_sin2(n=8))
+    small = engine.Hamiltonian(ctx, I.workload_usa(8, 0, "xy"))
+    one = engine.Sector(ctx, small, 3)
+    for ham_, w, status in ((big, 17, L.AQC_ENOTSUP),      # 1122 pair terms > 1024
+                            (big, 35, L.AQC_EINVAL), (small, -1, L.AQC_EINVAL),
+                            (sk, 4, L.AQC_EINVAL),         # transverse field changes the weight
+                            (one, 1, L.AQC_EINVAL)):       # already a sector
+        try:
+            engine.Sector(ctx, ham_, w)
+        except L.AqcError as e:
+            assert e.status == status, (w, e)
+        else:
+            raise AssertionError(f"sector of weight {w} was not refused")
+    for h in (one, small, sk, big):
+        h.free()
     rng = np.random.default_rng(1)
     for n in (1, 2, 5, 17, 48):
         a = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
