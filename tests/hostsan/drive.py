@@ -45,6 +45,69 @@ def expect(f, *errors):
             raise
 
 
+def status_of(f):
+    try:
+        f()
+    except L.AqcError as e:
+        return e.status
+    return L.AQC_OK
+
+
+def host_error_paths(ctx):
+    """Error returns the header documents that need a context: sizes,
+    alignment, aliasing, workspace, batch slots."""
+    lib_ = lib()
+    ham = engine.Hamiltonian(ctx, I.workload_sk_sin2(n=10))
+    N = 1 << 10
+    a = torch.zeros(N + 2, dtype=torch.complex128)
+    b = torch.zeros(N, dtype=torch.complex128)
+    ws = torch.zeros(1 << 22, dtype=torch.uint8)
+    P = C.c_void_p
+    ap, bp, wp = P(a.data_ptr()), P(b.data_ptr()), P(ws.data_ptr())
+    mis = P(a.data_ptr() + 8)                      # 8-byte offset: not 16-byte aligned
+    need = lib_.aqc_apply_workspace_bytes(ham.handle, L.C128)
+    assert status_of(lambda: check(lib_.aqc_apply(ctx.handle, ham.handle, 0.1, ap, ap, L.C128, wp, need))) \
+        == L.AQC_EINVAL                            # in == out
+    assert status_of(lambda: check(lib_.aqc_apply(ctx.handle, ham.handle, 0.1, mis, bp, L.C128, wp, need))) \
+        == L.AQC_EINVAL                            # alignment
+    assert status_of(lambda: check(lib_.aqc_apply(ctx.handle, ham.handle, 0.1, ap, bp, 7, wp, need))) \
+        == L.AQC_ENOTSUP                           # dtype
+    if need:
+        assert status_of(lambda: check(lib_.aqc_apply(ctx.handle, ham.handle, 0.1, ap, bp, L.C128, wp,
+                                                      need - 16))) == L.AQC_ENOMEM
+    opts, _, _ = engine.evolve_opts(method="pc4", n_steps=10, shift=0.5)
+    st = L.EvolveStats()
+    wneed = lib_.aqc_evolve_workspace_bytes(ham.handle, L.C128, C.byref(opts))
+    assert status_of(lambda: check(lib_.aqc_evolve(ctx.handle, ham.handle, ap, L.C128, 0.0, 1.0, C.byref(opts),
+                                                   wp, wneed - 16, C.byref(st)))) == L.AQC_ENOMEM
+    assert status_of(lambda: check(lib_.aqc_evolve(ctx.handle, ham.handle, ap, L.C128, 1.0, 0.0, C.byref(opts),
+                                                   wp, wneed, C.byref(st)))) == L.AQC_EINVAL   # t1 < t0
+    bad = engine.evolve_opts(method="pc4", n_steps=0, atol=0.0)[0]
+    assert status_of(lambda: check(lib_.aqc_evolve(ctx.handle, ham.handle, ap, L.C128, 0.0, 1.0, C.byref(bad),
+                                                   wp, ws.numel(), C.byref(st)))) == L.AQC_EINVAL
+    assert status_of(lambda: ham.set_tiling(torch.complex128, 40, 12, 3, 1)) != L.AQC_OK
+    # a batch of one slot: a second admission is refused, an unfinished solve
+    # cannot retire, a short workspace is refused
+    bt = engine.Batch(ctx, torch.complex64, capacity=1, graph=True)
+    p1 = torch.zeros(N, dtype=torch.complex64)
+    p2 = torch.zeros(N, dtype=torch.complex64)
+    short = torch.zeros(16, dtype=torch.uint8)
+    sl = C.c_int()
+    assert status_of(lambda: check(lib_.aqc_batch_admit(bt._h, ham.handle, P(p1.data_ptr()), P(short.data_ptr()),
+                                                        short.numel(), 0.0, 1.0, 20, 0.0, C.byref(sl)))) \
+        == L.AQC_ENOMEM
+    slot = bt.admit(ham, p1, 0.0, 1.0, 20, 0.0)
+    assert status_of(lambda: bt.admit(ham, p2, 0.0, 1.0, 20, 0.0)) == L.AQC_EBUSY
+    assert status_of(lambda: check(lib_.aqc_batch_retire(bt._h, slot, None))) == L.AQC_EBUSY
+    assert status_of(lambda: check(lib_.aqc_batch_retire(bt._h, 5, None))) == L.AQC_EINVAL
+    while bt.step(8):
+        pass
+    assert bt.poll() == [slot]
+    bt.retire(slot)
+    bt.close()
+    ham.free()
+
+
 def main():
     lib().fake_hip_live.restype = C.c_long
     base = lib().fake_hip_live()
@@ -134,6 +197,7 @@ def main():
             raise AssertionError(f"sector of weight {w} was not refused")
     for h in (one, small, sk, big):
         h.free()
+    host_error_paths(ctx)
     rng = np.random.default_rng(1)
     for n in (1, 2, 5, 17, 48):
         a = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
