@@ -644,7 +644,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the engine runs on one GPU; multi-GPU sharding is not implemented, so --gpus must be 1",
+              file=sys.stderr)
         sys.exit(2)
     if args.mode == "batch":
         return run_batch_mode(args)
