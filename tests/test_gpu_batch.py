@@ -105,3 +105,31 @@ def test_batch_matches_oracle(eng):
         assert np.linalg.norm(got[s] - ref) < TOL["c128"]
         hm.free()
     b.close()
+
+
+def test_batch_short_solves_and_empty_steps(eng):
+    """Solves of 1 to 5 steps (the first three are RK4 bootstrap steps only)
+    share ticks with a longer one and finish inside a group of ticks; a step
+    of an empty batch does nothing.  Every result against the oracle."""
+    engine, ctx = eng
+    import torch
+    b = engine.Batch(ctx, torch.complex128, capacity=8)
+    assert b.step(4) == 0 and b.poll() == []
+    rng = np.random.default_rng(9)
+    slots = {}
+    for j, K in enumerate([1, 2, 3, 4, 5, 40]):
+        inst = I.workload_batch_member(j, n_lo=8, n_hi=10)
+        psi0 = I.random_state(inst.n, rng)
+        hm = engine.Hamiltonian(ctx, inst)
+        t1 = K * 0.003
+        slots[b.admit(hm, to_dev(psi0, "c128"), 0.0, t1, K, 1.5)] = (inst, psi0, K, t1, hm)
+    got = {}
+    while b.step(16) > 0 or len(got) < len(slots):
+        for s in b.poll():
+            got[s] = to_host(b.retire(s)[0])
+    for s, (inst, psi0, K, t1, hm) in slots.items():
+        ref = integrate.evolve(inst, psi0, 0.0, t1, K, "pc4", 1.5)
+        assert np.linalg.norm(got[s] - ref) < TOL["c128"], K
+        hm.free()
+    assert b.step(4) == 0 and b.info()["active"] == 0
+    b.close()
