@@ -127,3 +127,19 @@ def test_not_converged_is_reported(eng):
     with pytest.raises(ValueError):
         engine.lowest_eigs(ctx, ham, 0.5, k=2, max_basis=60)
     ham.free()
+
+
+@pytest.mark.parametrize("n,m,seed", [(3, 8, 40), (4, 16, 42), (4, 12, 42)])
+def test_krylov_space_as_large_as_the_state(eng, n, m, seed):
+    """A basis as large as the state (n = 3 with 8 vectors, n = 4 with 16) or
+    nearly so (n = 4, 12 of 16): the Krylov space can exhaust the whole space;
+    the two lowest levels of a random Hamiltonian (seeds whose levels are all
+    at least 0.05 apart: a Krylov space holds one vector of a degenerate
+    level) still match the oracle's dense spectrum."""
+    engine, ctx = eng
+    inst = I.random_terms(n, 10, np.random.default_rng(seed)).instance([I.SCHED_CONST], I.linear_path(1.0))
+    ham = engine.Hamiltonian(ctx, inst)
+    ev, res, nmv = engine.lowest_eigs(ctx, ham, 0.0, k=2, max_basis=m, tol=1e-10)
+    ref = spectrum.lowest_dense(inst, 0.0, 2)
+    assert np.all(np.abs(ev - ref) <= 1e-9 * np.maximum(1.0, np.abs(ref))), (ev, ref)
+    ham.free()
