@@ -86,6 +86,13 @@ def host_error_paths(ctx):
     assert status_of(lambda: check(lib_.aqc_evolve(ctx.handle, ham.handle, ap, L.C128, 0.0, 1.0, C.byref(bad),
                                                    wp, ws.numel(), C.byref(st)))) == L.AQC_EINVAL
     assert status_of(lambda: ham.set_tiling(torch.complex128, 40, 12, 3, 1)) != L.AQC_OK
+    # Lanczos: a basis larger than the space, too many levels, a basis too small for them
+    tiny = engine.Hamiltonian(ctx, I.random_terms(2, 6, np.random.default_rng(2)).instance(
+        [I.SCHED_CONST], I.linear_path(1.0)))
+    assert status_of(lambda: engine.lowest_eigs(ctx, tiny, 0.0, k=2, max_basis=8)) == L.AQC_EINVAL
+    assert status_of(lambda: engine.lowest_eigs(ctx, ham, 0.0, k=9, max_basis=24)) == L.AQC_EINVAL
+    assert status_of(lambda: engine.lowest_eigs(ctx, ham, 0.0, k=3, max_basis=4)) == L.AQC_EINVAL
+    tiny.free()
     # a batch of one slot: a second admission is refused, an unfinished solve
     # cannot retire, a short workspace is refused
     bt = engine.Batch(ctx, torch.complex64, capacity=1, graph=True)
