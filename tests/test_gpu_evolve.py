@@ -238,3 +238,24 @@ def test_carry_chain_equals_one_call(eng, dt, key, monkeypatch):
     with pytest.raises(_lib.AqcError):
         engine.evolve(ctx, ham, chain, ta + h, ta + 2 * h, ws=ws2, carry=c2, n_steps=1, **kw)
     ham.free()
+
+
+@pytest.mark.parametrize("t1", [0.01, 0.35])
+def test_adaptive_interval_shorter_than_first_steps(eng, t1):
+    """Adaptive runs over an interval shorter than the first step (t1 = 0.01,
+    h0 = 0.2) or than the RK4 bootstrap (t1 = 0.35): the last step is cut to
+    end at t1; the accepted grid and the state equal the oracle's."""
+    engine, ctx = eng
+    inst, psi0 = _adaptive_problem()
+    kw = dict(atol=1e-9, h0=0.2, window=8)
+    ref, segs_ref, cnt = integrate.evolve_adaptive(inst, psi0, 0.0, t1, **kw)
+    ham = engine.Hamiltonian(ctx, inst)
+    psi = to_dev(psi0, "c128")
+    st, segs = engine.evolve(ctx, ham, psi, 0.0, t1, method="pc4", n_steps=0, record_cap=64, **kw)
+    assert st["n_segments"] == len(segs_ref)
+    assert [s[2] for s in segs] == [s[2] for s in segs_ref]
+    np.testing.assert_allclose(np.array(segs)[:, :2], np.array(segs_ref)[:, :2], rtol=0, atol=0)
+    assert st["steps"] == cnt.steps and st["rejected"] == cnt.rejected
+    assert st["t_reached"] == t1
+    assert np.linalg.norm(to_host(psi) - ref) < TOL["c128"]
+    ham.free()
