@@ -621,7 +621,7 @@ def main():
     ap.add_argument("--ts-algorithms", default="x,xy")
     ap.add_argument("--ts-rel", type=float, default=0.05)
     ap.add_argument("--ts-batched", action="store_true",
-                    help="solve each round of the T_s search as one batch")
+                    help="solve each round of the T_s search as one batch (refused: see find_ts)")
     ap.add_argument("--n-gap", type=int, default=20)
     ap.add_argument("--gap-path", default="cbc")
     ap.add_argument("--gap-points", type=int, default=21)

@@ -14,5 +14,6 @@ Modules
   * ``observables``  norm, overlap, energy, ground-state fidelity (Sec. III.B)
   * ``subspace``     states and evolution within one Hamming weight (Sec. III.A)
   * ``spectrum``     lowest eigenvalues and the gap of H(t) (Sec. IV.B)
+  * ``tsearch``      the successful runtime T_s, E(T_s) = 1/2 (Sec. III.B)
 """
-from . import sqh, integrate, observables, subspace, spectrum  # noqa: F401
+from . import sqh, integrate, observables, subspace, spectrum, tsearch  # noqa: F401

@@ -46,17 +46,18 @@ AM4 = (9.0, 19.0, -5.0, 1.0)
 MILNE = 19.0 / 270.0
 
 
-def rhs(ham, t, y, shift=0.0):
-    """f(t, y) = -i (H(t) - shift) y."""
-    return -1j * apply_h(ham, t, y, shift)
+def rhs(ham, t, y, shift=0.0, apply=apply_h):
+    """f(t, y) = -i (H(t) - shift) y.  ``apply`` computes (H(t) - shift) y:
+    sqh.apply_h, or sqh.apply_h_parallel (identical values) for large states."""
+    return -1j * apply(ham, t, y, shift)
 
 
-def rk4_step(ham, t, y, h, shift=0.0, k1=None):
+def rk4_step(ham, t, y, h, shift=0.0, k1=None, apply=apply_h):
     if k1 is None:
-        k1 = rhs(ham, t, y, shift)
-    k2 = rhs(ham, t + 0.5 * h, y + (0.5 * h) * k1, shift)
-    k3 = rhs(ham, t + 0.5 * h, y + (0.5 * h) * k2, shift)
-    k4 = rhs(ham, t + h, y + h * k3, shift)
+        k1 = rhs(ham, t, y, shift, apply)
+    k2 = rhs(ham, t + 0.5 * h, y + (0.5 * h) * k1, shift, apply)
+    k3 = rhs(ham, t + 0.5 * h, y + (0.5 * h) * k2, shift, apply)
+    k4 = rhs(ham, t + h, y + h * k3, shift, apply)
     return y + (h / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
 
 
@@ -73,10 +74,11 @@ class Segment:
     f_k = f(t_k, y_k) (RK4's first stage), evaluates f_3 once, and then takes
     predictor-corrector steps."""
 
-    def __init__(self, ham, y, t_s, h, method="pc4", shift=0.0, counter=None):
+    def __init__(self, ham, y, t_s, h, method="pc4", shift=0.0, counter=None, apply=apply_h):
         if method not in ("pc4", "rk4"):
             raise ValueError(method)
         self.ham, self.t_s, self.h, self.method, self.shift = ham, t_s, h, method, shift
+        self.apply = apply
         self.cnt = counter if counter is not None else Counter()
         self.k = 0
         self.y = np.array(y, dtype=np.complex128, copy=True)
@@ -94,26 +96,26 @@ class Segment:
     def advance(self, nsteps, errs=None):
         """Take nsteps steps; append each predictor-corrector step's Milne
         estimate to ``errs`` when given."""
-        ham, h, sh, cnt = self.ham, self.h, self.shift, self.cnt
+        ham, h, sh, cnt, ap = self.ham, self.h, self.shift, self.cnt, self.apply
         for _ in range(nsteps):
             k = self.k
             tk = self.t(k)
             y = self.y
             if self.method == "rk4":
-                y = rk4_step(ham, tk, y, h, sh)
+                y = rk4_step(ham, tk, y, h, sh, apply=ap)
                 cnt.matvecs += 4
             elif k < 3:
-                fk = rhs(ham, tk, y, sh)
+                fk = rhs(ham, tk, y, sh, ap)
                 self.f.append(fk)
-                y = rk4_step(ham, tk, y, h, sh, k1=fk)   # RK4's first stage is f_k
+                y = rk4_step(ham, tk, y, h, sh, k1=fk, apply=ap)   # RK4's first stage is f_k
                 cnt.matvecs += 4
             else:
                 if k == 3:
-                    self.f.append(rhs(ham, tk, y, sh))   # f_3 closes the bootstrap
+                    self.f.append(rhs(ham, tk, y, sh, ap))   # f_3 closes the bootstrap
                     cnt.matvecs += 1
                 fk, fk1, fk2, fk3 = self.f[-1], self.f[-2], self.f[-3], self.f[-4]
                 yp = y + (h / 24.0) * (AB4[0] * fk + AB4[1] * fk1 + AB4[2] * fk2 + AB4[3] * fk3)
-                fp = rhs(ham, self.t(k + 1), yp, sh)     # the single evaluation
+                fp = rhs(ham, self.t(k + 1), yp, sh, ap)     # the single evaluation
                 yc = y + (h / 24.0) * (AM4[0] * fp + AM4[1] * fk + AM4[2] * fk1 + AM4[3] * fk2)
                 if errs is not None:
                     errs.append(MILNE * float(np.linalg.norm(yc - yp)))
@@ -126,15 +128,15 @@ class Segment:
         return self.y
 
 
-def run_segment(ham, y0, t_s, h, K, method="pc4", shift=0.0, counter=None, errs=None):
+def run_segment(ham, y0, t_s, h, K, method="pc4", shift=0.0, counter=None, errs=None, apply=apply_h):
     """K steps of size h from (t_s, y0)."""
-    return Segment(ham, y0, t_s, h, method, shift, counter).advance(K, errs)
+    return Segment(ham, y0, t_s, h, method, shift, counter, apply).advance(K, errs)
 
 
-def evolve(ham, psi0, t0, t1, n_steps, method="pc4", shift=0.0, counter=None):
+def evolve(ham, psi0, t0, t1, n_steps, method="pc4", shift=0.0, counter=None, apply=apply_h):
     """Fixed-step solution psi(t1) from psi(t0) = psi0 with h = (t1 - t0)/n_steps."""
     h = (t1 - t0) / n_steps
-    y = run_segment(ham, psi0, t0, h, n_steps, method, shift, counter)
+    y = run_segment(ham, psi0, t0, h, n_steps, method, shift, counter, apply=apply)
     return np.exp(-1j * shift * (t1 - t0)) * y
 
 

@@ -3,9 +3,9 @@ E(T) = <psi(T)|H_f|psi(T)> falls to 1/2 (with E_1 = 0 and every excited level
 at least 1, E(T) <= 1/2 means a ground-state population of at least one
 half).  Every instance of a set is bracketed by doubling T and then bisected
 in log T; a round evaluates every unfinished instance once, by one full
-solve each: one aqc_evolve after the other, or on request all of them
-together in one batch (aqc_batch_*), where a round costs about one solve of
-the largest instance.  Each solve is a fixed-step pc4 run on the library."""
+solve each, one aqc_evolve after the other.  Each solve is a fixed-step pc4
+run on the library.  `energies` solves a round as one batch (aqc_batch_*);
+find_ts does not use it (see find_ts)."""
 from __future__ import annotations
 
 import copy
@@ -104,13 +104,11 @@ class Search:
             self.T_hi = min(self.T_hi, T)
 
 
-def find_ts(ctx, insts, states, T0=1.0, rel=0.05, T_max=1e4, dtype=torch.complex64, plan=default_plan,
-            max_rounds=60, log=None, batched=False):
-    """T_s of every instance (the geometric mean of the final bracket
-    [T_lo, T_hi] with E(T_lo) > 1/2 >= E(T_hi), T_hi / T_lo <= 1 + rel).
-    A round's solves run one after the other, or with batched=True as one
-    batch (a host-side crash was once seen at the end of such a batch and is
-    not explained, so it is not the default).  Returns the Search records."""
+def search_rounds(ctx, insts, states, run, T0=1.0, rel=0.05, T_max=1e4, dtype=torch.complex64,
+                  plan=default_plan, max_rounds=60, log=None):
+    """The rounds of the search: each round evaluates E(T) of every unfinished
+    instance with run(ctx, insts, Ts, states, dtype, plan) (energies_sequential
+    or energies).  Returns the Search records."""
     S = [Search() for _ in insts]
     for rnd in range(max_rounds):
         todo = []
@@ -120,7 +118,6 @@ def find_ts(ctx, insts, states, T0=1.0, rel=0.05, T_max=1e4, dtype=torch.complex
                 todo.append((i, T))
         if not todo:
             break
-        run = energies if batched else energies_sequential
         Es = run(ctx, [insts[i] for i, _ in todo], [T for _, T in todo],
                  [states[i] for i, _ in todo], dtype, plan)
         for (i, T), E in zip(todo, Es):
@@ -128,3 +125,21 @@ def find_ts(ctx, insts, states, T0=1.0, rel=0.05, T_max=1e4, dtype=torch.complex
         if log:
             log(f"round {rnd}: {len(todo)} solves")
     return S
+
+
+def find_ts(ctx, insts, states, T0=1.0, rel=0.05, T_max=1e4, dtype=torch.complex64, plan=default_plan,
+            max_rounds=60, log=None, batched=False):
+    """T_s of every instance (the geometric mean of the final bracket
+    [T_lo, T_hi] with E(T_lo) > 1/2 >= E(T_hi), T_hi / T_lo <= 1 + rel); the
+    solves of a round run one after the other (aqc_evolve).  Returns the
+    Search records.
+
+    batched=True (a round as one batch) is refused: one run of the GPU test
+    suite ended with a host-side crash at the end of such a batch, and its
+    cause has not been shown, so that form stays off the GPU."""
+    if batched:
+        raise NotImplementedError(
+            "batched T_s rounds are disabled: a host-side crash once ended a run at the end of such "
+            "a batch and its cause has not been found; use the sequential rounds (batched=False)")
+    return search_rounds(ctx, insts, states, energies_sequential, T0, rel, T_max, dtype, plan,
+                         max_rounds, log)

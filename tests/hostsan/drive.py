@@ -241,8 +241,8 @@ def main():
     # whole batched searches: every round creates and closes a batch and its
     # Hamiltonians (the stand-in's energies are 1, so T doubles up to T_max)
     insts = [I.workload_usa(8, k, "xy") for k in range(4)]
-    S = tsearch.find_ts(ctx, insts, [I.plus_state(8)] * 4, T_max=64.0, batched=True,
-                        plan=lambda ham, T: (int(8 + T), 0.5))
+    S = tsearch.search_rounds(ctx, insts, [I.plus_state(8)] * 4, tsearch.energies, T_max=64.0,
+                              plan=lambda ham, T: (int(8 + T), 0.5))
     assert all(len(s.evals) == 7 for s in S)
     ctx.close()
     live = lib().fake_hip_live() - base

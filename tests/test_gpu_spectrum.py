@@ -39,6 +39,8 @@ def test_lowest_two_full_space_small(eng, kind, dt):
         g = torch.empty(1 << 10, dtype=_dt(dt), device="cuda")
         ev, res, nmv = engine.lowest_eigs(ctx, ham, s, k=2, dtype=_dt(dt), tol=LZ_TOL[dt], ground=g)
         ref = spectrum.lowest(inst, s, 2)
+        print(f"lanczos {kind} {dt} s={s}: rel err {np.max(np.abs(ev - ref) / np.maximum(1.0, np.abs(ref))):.2e}",
+              flush=True)
         assert np.all(np.abs(ev - ref) <= TOL_E[dt] * np.maximum(1.0, np.abs(ref))), (s, ev, ref)
         assert nmv > 0
         # the returned vector is a normalised eigenvector of the oracle's H(s)
@@ -92,6 +94,8 @@ def test_lowest_two_in_a_sector(eng, dt):
         ev, res, nmv = engine.lowest_eigs(ctx, sec, s, k=2, dtype=_dt(dt), tol=LZ_TOL[dt])
         ref = spectrum.lowest(inst, s, 2, weight=w)
         assert ref[1] - ref[0] > 1e-3
+        print(f"lanczos sector {dt} s={s}: rel err {np.max(np.abs(ev - ref) / np.maximum(1.0, np.abs(ref))):.2e}",
+              flush=True)
         assert np.all(np.abs(ev - ref) <= TOL_E[dt] * np.maximum(1.0, np.abs(ref))), (s, ev, ref)
     # the Dicke state as the start vector gives the same levels
     ev2, _, _ = engine.lowest_eigs(ctx, sec, 0.7, k=2, dtype=_dt(dt), tol=LZ_TOL[dt],

@@ -8,7 +8,8 @@ import math
 import numpy as np
 import pytest
 
-from oracle import integrate, observables, spectrum, sqh, subspace
+from oracle import sqh, subspace
+from oracle import tsearch as oracle_tsearch
 from paper_1311_3938_amd import instances as I
 
 pytestmark = pytest.mark.gpu
@@ -37,16 +38,17 @@ def _plan_for(inst):
 
 
 def _oracle_search(inst, psi0, plan, T0, rel):
-    from paper_1311_3938_amd.tsearch import Search, with_T
-    s = Search()
-    while True:
-        T = s.next_T(T0, rel)
-        if T is None:
-            return s
-        K, shift = plan(None, T)
-        it = with_T(inst, T)
-        y = integrate.evolve(it, psi0, 0.0, T, K, "pc4", shift)
-        s.record(T, observables.energy(it, T, y))
+    """The oracle's own bracket-and-bisect search (oracle.tsearch): every
+    E(T) from an oracle evolution; nothing from the library."""
+    return oracle_tsearch.search_instance(inst, psi0, lambda T: plan(None, T), T0, rel)
+
+
+def _compare(S, R):
+    tried, lo, hi, ts = R
+    assert [T for T, _ in S.evals] == [T for T, _ in tried]
+    assert np.allclose([E for _, E in S.evals], [E for _, E in tried], atol=1e-9, rtol=0)
+    assert (S.T_lo, S.T_hi) == (lo, hi)
+    assert math.isfinite(S.T_s) and S.T_s == ts
 
 
 def _case(engine, ctx, torch, algorithm, n):
@@ -82,10 +84,7 @@ def test_ts_search_sequential_matches_oracle(eng, algorithm, n):
     plan = _plan_for(inst)
     S = tsearch.find_ts(ctx, [inst], [psi_gpu], T0=2.0, rel=0.1, dtype=torch.complex128, plan=plan,
                         batched=False)[0]
-    R = _oracle_search(inst, psi_ref, plan, 2.0, 0.1)
-    assert [T for T, _ in S.evals] == [T for T, _ in R.evals]
-    assert np.allclose([E for _, E in S.evals], [E for _, E in R.evals], atol=1e-9, rtol=0)
-    assert math.isfinite(S.T_s) and S.T_s == R.T_s
+    _compare(S, _oracle_search(inst, psi_ref, plan, 2.0, 0.1))
 
 
 @pytest.mark.skip(reason="a host-side segmentation fault occurred once inside this test (at the "
@@ -119,7 +118,4 @@ def test_ts_search_matches_oracle(eng, algorithm, n):
         assert abs(abs(np.vdot(psi_ref, psi_gpu)) - 1.0) < 1e-10
     S = tsearch.find_ts(ctx, [inst], [psi_gpu], T0=2.0, rel=0.1, dtype=torch.complex128, plan=plan,
                         batched=True)[0]
-    R = _oracle_search(inst, psi_ref, plan, 2.0, 0.1)
-    assert [T for T, _ in S.evals] == [T for T, _ in R.evals]
-    assert np.allclose([E for _, E in S.evals], [E for _, E in R.evals], atol=1e-9, rtol=0)
-    assert math.isfinite(S.T_s) and S.T_s == R.T_s
+    _compare(S, _oracle_search(inst, psi_ref, plan, 2.0, 0.1))

@@ -113,3 +113,21 @@ def test_row_wise_product_matches_full_product():
     np.testing.assert_allclose(got, full[rows], atol=1e-13)
     np.testing.assert_allclose(sqh.diagonal_rows(inst, 0.8, rows), sqh.diagonal(inst, 0.8)[rows],
                                atol=1e-13)
+
+
+@pytest.mark.parametrize("n,seed", [(9, 1), (12, 2)])
+def test_parallel_product_is_the_plain_product(n, seed):
+    """apply_h_parallel (row blocks of apply_h_rows on threads) gives exactly
+    apply_h's values, and so does an evolution that uses it."""
+    from oracle import integrate
+    rng = np.random.default_rng(seed)
+    inst = I.random_terms(n, 3 * n, rng, n_sched=2).instance(
+        [I.SCHED_ONE_MINUS_S, I.SCHED_S], I.linear_path(3.0))
+    psi = I.random_state(n, rng)
+    a = sqh.apply_h(inst, 1.3, psi, shift=0.7)
+    b = sqh.apply_h_parallel(inst, 1.3, psi, shift=0.7, threads=4, block=1 << (n - 3))
+    assert np.array_equal(a, b)
+    y0 = integrate.evolve(inst, psi, 0.2, 0.5, 9, "pc4", 0.4)
+    y1 = integrate.evolve(inst, psi, 0.2, 0.5, 9, "pc4", 0.4,
+                          apply=lambda *a_: sqh.apply_h_parallel(*a_, threads=3, block=1 << (n - 2)))
+    assert np.array_equal(y0, y1)
