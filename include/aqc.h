@@ -113,7 +113,9 @@ const char* aqc_version(void);
  * non-finite weights, a sched_id outside [0, n_sched), n_sched > 32, bad
  * schedule or path data; ENOTSUP for n_qubits > 34.  The compiled tables live
  * in library-owned device memory (small: O(terms + 2^(n-13) n) entries) until
- * aqc_ham_free.  The context's stream is used for uploads.                  */
+ * aqc_ham_free.  Up to 26 qubits the tables of both dtypes are built here;
+ * larger Hamiltonians build them at their first use.  The context's stream
+ * is used for uploads.                                                      */
 aqc_status aqc_build_hamiltonian(aqc_ctx* ctx, int n_qubits, int64_t n_terms,
                                  const uint64_t* x_mask, const uint64_t* z_mask,
                                  const double* weight, const int32_t* sched_id,
@@ -133,7 +135,8 @@ typedef struct {
 aqc_status aqc_ham_info(const aqc_ham* ham, aqc_ham_info_t* out);
 
 /* Tiling of the tile passes for this Hamiltonian and dtype (replaces the
- * default and rebuilds the plan at the next use; synchronises the device).
+ * default and rebuilds the plan: here up to 26 qubits, else at the next use;
+ * synchronises the device).
  * tbf: bits of the last pass's contiguous tile (1..14 complex64, 1..13
  * complex128); tbh: bits of a high-pass tile; lh: its contiguous low bits
  * (1 <= lh < tbh).  options, bits 0-1: how single-qubit flips above the last

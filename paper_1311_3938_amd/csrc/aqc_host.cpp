@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -286,7 +287,14 @@ struct aqc_ham {
   int sector_w = -1;             // weight of a sector (aqc_sector_create), else -1
   SectorDev sd{};                // a sector's device tables
   std::vector<void*> sec_bufs;   // and their allocations
+  // plans and the diagonal range are built on first use when not built
+  // eagerly; this lock makes that safe from several host threads
+  std::recursive_mutex mu;
 };
+
+// plans of both dtypes are built with the Hamiltonian up to this size (the
+// tables are small there); larger ones are built on first use
+constexpr int kEagerPlanMaxN = 26;
 
 static void free_plan(Plan& p) {
   for (auto& ps : p.passes) {
@@ -314,6 +322,7 @@ extern "C" aqc_status aqc_ham_free(aqc_ham* h) {
 }
 
 static int popc(uint64_t v) { return __builtin_popcountll(v); }
+static aqc_status build_plan(aqc_ham* h, int dtype, hipStream_t s);
 
 extern "C" aqc_status aqc_build_hamiltonian(aqc_ctx* ctx, int n, int64_t n_terms,
                                             const uint64_t* xm, const uint64_t* zm,
@@ -390,6 +399,17 @@ extern "C" aqc_status aqc_build_hamiltonian(aqc_ctx* ctx, int n, int64_t n_terms
       GroupH& g = h->groups[it->second];
       g.terms.push_back(t);
       if (t.z != 0) g.plain = false;
+    }
+  }
+  if (n <= kEagerPlanMaxN) {
+    HIPCHK(hipSetDevice(ctx->device));
+    for (int d = 0; d < 2; ++d) {
+      // a Hamiltonian the default tiling cannot hold is still returned: the
+      // error then comes from the first use (or aqc_ham_set_tiling fixes it)
+      if (build_plan(h.get(), d, ctx->stream) != AQC_OK) {
+        free_plan(h->plans[d]);
+        g_last_error.clear();
+      }
     }
   }
   *out = h.release();
@@ -716,6 +736,7 @@ static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& 
 }
 
 static aqc_status build_plan(aqc_ham* h, int dtype, hipStream_t s) {
+  std::lock_guard<std::recursive_mutex> lk(h->mu);
   Plan& p = h->plans[dtype];
   if (p.built) return AQC_OK;
   if (h->sector_w >= 0) {
@@ -926,6 +947,7 @@ extern "C" aqc_status aqc_ham_set_tiling(aqc_ham* h, int dtype, int tbf, int tbh
     return fail(AQC_EINVAL, "aqc_ham_set_tiling: tile bits out of range");
   if (options < 0 || options > 7)
     return fail(AQC_EINVAL, "aqc_ham_set_tiling: options is 0..7");
+  std::lock_guard<std::recursive_mutex> lk(h->mu);
   // check the layout before replacing the plan
   const bool old_set = h->tiling_set[dtype];
   int old[4];
@@ -948,6 +970,12 @@ extern "C" aqc_status aqc_ham_set_tiling(aqc_ham* h, int dtype, int tbf, int tbh
     HIPCHK(hipSetDevice(h->device));
     HIPCHK(hipDeviceSynchronize());
     free_plan(h->plans[dtype]);
+  }
+  if (h->n <= kEagerPlanMaxN) {
+    // rebuilt now, as aqc_build_hamiltonian does, so that later calls need
+    // no allocation (uploads on the null stream: the device is idle here)
+    HIPCHK(hipSetDevice(h->device));
+    STCHK(build_plan(h, dtype, nullptr));
   }
   return AQC_OK;
 }
@@ -1216,6 +1244,7 @@ extern "C" aqc_status aqc_ground_mass(aqc_ctx* ctx, const aqc_ham* h, double t, 
 }
 
 static aqc_status ensure_minmax(aqc_ctx* ctx, aqc_ham* h) {
+  std::lock_guard<std::recursive_mutex> lk(h->mu);
   if (h->have_minmax) return AQC_OK;
   STCHK(build_plan(h, 1, ctx->stream));
   const Plan& p = h->plans[1];
@@ -1444,6 +1473,9 @@ extern "C" aqc_status aqc_sector_create(aqc_ctx* ctx, const aqc_ham* src, int we
   STCHK(sector_upload(h.get(), masks, &sd.masks));
   STCHK(sector_upload(h.get(), mterms, &sd.mterms));
   STCHK(sector_upload(h.get(), res, &sd.res));
+  // a sector's plan is one kernel per product and needs no tables
+  STCHK(build_plan(h.get(), 0, ctx->stream));
+  STCHK(build_plan(h.get(), 1, ctx->stream));
   *out = h.release();
   return AQC_OK;
 }
