@@ -290,6 +290,26 @@ aqc_status aqc_ground_mass(aqc_ctx* ctx, const aqc_ham* ham, double t, const voi
  * aqc_apply.                                                                */
 aqc_status aqc_energy(aqc_ctx* ctx, const aqc_ham* ham, double t, const void* psi,
                       int dtype, void* workspace, size_t ws_bytes, double* out);
+/* aqc_energy for callers that cannot allocate device memory (code that is
+ * being captured into a HIP graph, tight serving loops, harnesses that forbid
+ * hipMalloc): the same value from the same kernels, but the partial product
+ * of the high passes and the per-workgroup partial sums live in a fixed
+ * device array of the library (32 MiB + 1 MiB, one copy per GPU, held until
+ * the process ends) instead of a caller workspace and the context's
+ * reduction buffer.  No workspace argument; no hipMalloc, hipFree or other
+ * allocation.  Limits: the partial product fits states of up to 2^22
+ * complex64 or 2^21 complex128 amplitudes (single-pass plans, n <= 13 or 12,
+ * need none), and at most 43690 last-pass workgroups; larger problems return
+ * AQC_ENOMEM with the sizes in the message.  The Hamiltonian's plan for this
+ * dtype must exist: it is built with the Hamiltonian up to 26 qubits (and
+ * rebuilt by aqc_ham_set_tiling), otherwise by a first aqc_apply or
+ * aqc_energy call; AQC_EINVAL if not.  Every call on one GPU shares that
+ * GPU's array: calls that overlap in time on one device (two host threads,
+ * or two streams) race and give wrong results; the array keeps the last
+ * call's contents, none of which a call reads before writing.  Synchronises
+ * the context's stream.                                                     */
+aqc_status aqc_energy_noalloc(aqc_ctx* ctx, const aqc_ham* ham, double t, const void* psi,
+                              int dtype, double* out);
 /* aqc_norm2 and aqc_overlap on states of `len` amplitudes (sector states).  */
 aqc_status aqc_norm2_len(aqc_ctx* ctx, const void* psi, int dtype, int64_t len, double* out);
 aqc_status aqc_overlap_len(aqc_ctx* ctx, const void* phi, const void* psi, int dtype,

@@ -104,6 +104,7 @@ SIGNATURES = {
     "aqc_fidelity": (I32, [P, P, C.c_int, C.c_int, C.c_int, P, I64, C.POINTER(D)]),
     "aqc_ground_mass": (I32, [P, P, D, P, C.c_int, D, C.POINTER(D), C.POINTER(D)]),
     "aqc_energy": (I32, [P, P, D, P, C.c_int, P, SZ, C.POINTER(D)]),
+    "aqc_energy_noalloc": (I32, [P, P, D, P, C.c_int, C.POINTER(D)]),
     "aqc_batch_create": (I32, [P, C.c_int, C.c_int, C.POINTER(P)]),
     "aqc_batch_destroy": (I32, [P]),
     "aqc_batch_set_graph": (I32, [P, C.c_int]),

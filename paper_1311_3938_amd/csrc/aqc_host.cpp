@@ -73,7 +73,29 @@ struct aqc_ctx {
   double prof_ms[2] = {0, 0};
   int64_t prof_n[2] = {0, 0};
   double prof_bytes[2] = {0, 0};  // algorithmic bytes of the timed launches
+  // device address of this device's fixed scratch array (aqc_energy_noalloc)
+  void* scratch = nullptr;
 };
+
+// Device address of the fixed scratch array, looked up once per device (each
+// GPU holds its own copy of the array at its own address).
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch[kMaxDevices] = {};
+
+static aqc_status scratch_for_device(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(AQC_ENOTSUP, "device index above 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    // the caller has made `device` current
+    HIPCHK(scratch_address(&p));
+    if (!p) return fail(AQC_EDEVICE, "scratch array has no device address");
+    g_scratch[device] = p;
+  }
+  *out = g_scratch[device];
+  return AQC_OK;
+}
 
 static aqc_status prof_drain(aqc_ctx* c) {
   if (c->prof_pending.empty()) return AQC_OK;
@@ -155,6 +177,7 @@ extern "C" aqc_status aqc_create(int device, void* stream, aqc_ctx** out) {
   c->lds_max = (size_t)lds;
   g_lds_max = (size_t)lds;
   HIPCHK(prepare_kernels());
+  STCHK(scratch_for_device(device, &c->scratch));
   HIPCHK(hipMalloc(&c->dres, 64 * sizeof(double)));
   HIPCHK(hipHostMalloc(&c->hres, 64 * sizeof(double), hipHostMallocDefault));
   STCHK(ensure_parts(c.get(), 1 << 16));
@@ -1049,6 +1072,51 @@ extern "C" aqc_status aqc_energy(aqc_ctx* ctx, const aqc_ham* h, double t, const
   e.red_flags = 4;
   STCHK(run_matvec(ctx, h, dtype, t, 0.0, psi, hbuf, e));
   HIPCHK(launch_reduce_sum(ctx->parts + 2 * nb, nb, 1, ctx->dres, ctx->stream));
+  return read_results(ctx, 1, out);
+}
+
+// The energy of aqc_energy with no allocation and no caller workspace: the
+// partial product and the reduction partials live in the device's fixed
+// scratch array.  The plan must exist already (it is built with the
+// Hamiltonian for n <= 26); nothing in the scratch needs clearing, since the
+// first high pass writes the whole partial product and every workgroup of the
+// last pass writes its partial sum.
+extern "C" aqc_status aqc_energy_noalloc(aqc_ctx* ctx, const aqc_ham* h, double t, const void* psi,
+                                         int dtype, double* out) {
+  if (!ctx || !h || !psi || !out) return fail(AQC_EINVAL, "aqc_energy_noalloc: NULL argument");
+  if (dtype != AQC_C64 && dtype != AQC_C128) return fail(AQC_ENOTSUP, "aqc_energy_noalloc: dtype");
+  if (h->device != ctx->device) return fail(AQC_EINVAL, "aqc_energy_noalloc: ham built for another device");
+  if (!aligned16(psi)) return fail(AQC_EINVAL, "aqc_energy_noalloc: psi must be 16-byte aligned");
+  if (!std::isfinite(t)) return fail(AQC_EINVAL, "aqc_energy_noalloc: t not finite");
+  if (!ctx->scratch) return fail(AQC_EDEVICE, "aqc_energy_noalloc: no scratch address for this device");
+  const Plan& p = h->plans[dtype];
+  if (!p.built)
+    return fail(AQC_EINVAL, "aqc_energy_noalloc: the Hamiltonian's plan for this dtype is not built "
+                            "(it is built with the Hamiltonian up to 26 qubits; otherwise call "
+                            "aqc_apply or aqc_energy once first)");
+  const size_t vneed = p.passes.size() > 1 ? vec_bytes(h, dtype) : 0;
+  const int64_t nb = last_nblocks(h, dtype);
+  const size_t pneed = 3 * (size_t)nb * sizeof(double);
+  if (vneed > kScratchVecBytes || pneed > kScratchPartBytes)
+    return fail(AQC_ENOMEM, "aqc_energy_noalloc: needs " + std::to_string(vneed) +
+                                " bytes for the partial product and " + std::to_string(pneed) +
+                                " for the partials; the fixed scratch holds " +
+                                std::to_string(kScratchVecBytes) + " and " +
+                                std::to_string(kScratchPartBytes) + " (use aqc_energy)");
+  HIPCHK(hipSetDevice(ctx->device));
+  char* base = reinterpret_cast<char*>(ctx->scratch);
+  void* hbuf = vneed ? base : nullptr;
+  double* parts = reinterpret_cast<double*>(base + kScratchVecBytes);
+  EpiDesc e = epi_zero();
+  e.red = parts;
+  e.red_flags = 4;
+  // event timing would create events; it is skipped for this call
+  const bool prof = ctx->prof_on;
+  ctx->prof_on = false;
+  const aqc_status st = run_matvec(ctx, h, dtype, t, 0.0, psi, hbuf, e);
+  ctx->prof_on = prof;
+  STCHK(st);
+  HIPCHK(launch_reduce_sum(parts + 2 * nb, nb, 1, ctx->dres, ctx->stream));
   return read_results(ctx, 1, out);
 }
 

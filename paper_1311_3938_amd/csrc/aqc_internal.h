@@ -177,6 +177,18 @@ struct SectorArgs {
   EpiDesc epi;
 };
 
+// ---- fixed device scratch (allocation-free entry point) ----------------------
+// A file-scope device array in aqc_kernels.hip, one copy per GPU, held until
+// the process ends.  aqc_energy_noalloc keeps the partial product of the high
+// passes in the first kScratchVecBytes (a state of up to 2^22 complex64 or
+// 2^21 complex128 amplitudes) and the per-workgroup reduction partials in the
+// remaining kScratchPartBytes.
+constexpr size_t kScratchVecBytes = (size_t)32 << 20;
+constexpr size_t kScratchPartBytes = (size_t)1 << 20;
+constexpr size_t kScratchBytes = kScratchVecBytes + kScratchPartBytes;
+// device address of the scratch array on the current device
+hipError_t scratch_address(void** p);
+
 // ---- launchers (aqc_kernels.hip) -------------------------------------------
 hipError_t launch_regpass(const RegPassArgs& a, int dtype, hipStream_t s);
 // workgroups of a register pass over n qubits

@@ -928,6 +928,17 @@ hipError_t launch_pass(const PassArgs& a, int dtype, int64_t nblocks, hipStream_
 }
 
 // ---------------------------------------------------------------------------
+// Fixed scratch of the allocation-free entry point.  Host code must not pass
+// `scratch` itself to a kernel (in host code the name is a host-side stand-in);
+// it takes the device address from scratch_address once per device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(void** p) {
+  return hipGetSymbolAddress(p, HIP_SYMBOL(scratch));
+}
+
+// ---------------------------------------------------------------------------
 // Reductions
 // ---------------------------------------------------------------------------
 

@@ -305,6 +305,15 @@ def energy(ctx, ham, t, psi, ws=None):
     return out.value
 
 
+def energy_noalloc(ctx, ham, t, psi):
+    """energy() without workspace or allocation (aqc_energy_noalloc): the
+    library's fixed device scratch holds the intermediate vectors."""
+    dt = _check_state(ctx, ham, psi)
+    out = C.c_double()
+    check(lib().aqc_energy_noalloc(ctx.handle, ham.handle, float(t), _ptr(psi), dt, C.byref(out)))
+    return out.value
+
+
 def lowest_eigs(ctx, ham, t, k=2, dtype=torch.complex128, max_basis=24, max_matvecs=4000, tol=1e-10,
                 start=None, ws=None, ground=None):
     """The k smallest eigenvalues of H(t) (aqc_lowest_eigs).  Returns

@@ -139,6 +139,7 @@ def main():
                 engine.evolve(ctx, ham, psi, 0.1 * k, 0.1 * (k + 1), ws=ws, carry=carry, method="pc4",
                               n_steps=5, shift=0.5)
             engine.energy(ctx, ham, 1.0, psi)
+            engine.energy_noalloc(ctx, ham, 1.0, psi)
             engine.ground_mass(ctx, ham, 1.0, psi)
             engine.norm2(ctx, psi)
             engine.overlap(ctx, psi, psi)
@@ -177,6 +178,7 @@ def main():
                 engine.apply(ctx, sec, 0.4, sp, torch.empty_like(sp))
                 engine.evolve(ctx, sec, sp, 0.0, 1.0, method="pc4", n_steps=8, shift="center")
                 engine.energy(ctx, sec, 1.0, sp)
+                engine.energy_noalloc(ctx, sec, 1.0, sp)
                 engine.ground_mass(ctx, sec, 1.0, sp)
                 expect(lambda: engine.lowest_eigs(ctx, sec, 0.5, k=2, dtype=dt, max_basis=10, max_matvecs=40),
                        L.AQC_EUNSTABLE)
@@ -205,6 +207,12 @@ def main():
     for h in (one, small, sk, big):
         h.free()
     host_error_paths(ctx)
+    # the allocation-free energy refuses what its fixed scratch cannot hold
+    # and plans that are not built yet
+    for n, status in ((23, L.AQC_ENOMEM), (27, L.AQC_EINVAL)):
+        h = engine.Hamiltonian(ctx, I.workload_sk_sin2(n=n))
+        expect(lambda: engine.energy_noalloc(ctx, h, 1.0, torch.empty(1 << n, dtype=torch.complex64)), status)
+        h.free()
     rng = np.random.default_rng(1)
     for n in (1, 2, 5, 17, 48):
         a = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))

@@ -131,6 +131,13 @@ hipError_t add_pass_batch_node(hipGraph_t g, hipGraphNode_t* nd, hipGraphNode_t,
   *nd = (hipGraphNode_t)g;
   return hipSuccess;
 }
+// the library's fixed scratch array: one block for the process, never freed
+// (not counted among the live handles)
+hipError_t scratch_address(void** p) {
+  static void* s = calloc(1, kScratchBytes);
+  *p = s;
+  return hipSuccess;
+}
 size_t pass_lds_bytes(int tb, int dtype) { return ((size_t)1 << tb) * (dtype == 0 ? 8 : 16); }
 hipError_t prepare_kernels() { return hipSuccess; }
 hipError_t launch_reduce_sum(const double* parts, int64_t nb, int nk, double* out, hipStream_t) {
