@@ -676,7 +676,11 @@ template <int WB> struct RegShape {
   static constexpr int threads = WB == 0 ? 256 : (64 << WB);
 };
 
-template <typename R, int RB, int WB>
+// ACC: the pass adds the partial product of earlier passes (acc_in).  It is a
+// template parameter so that the pass without it has no loads inside its
+// store loop: loads and stores share one in-order counter on this GPU, so a
+// wait for a load issued after a store also waits for that store.
+template <typename R, int RB, int WB, bool ACC>
 __device__ __forceinline__ void regpass_body(const RegPassArgs& a, const uint64_t blk,
                                              typename CT2<R>::V* ex) {
   using V = typename CT2<R>::V;
@@ -701,20 +705,31 @@ __device__ __forceinline__ void regpass_body(const RegPassArgs& a, const uint64_
   const V* src = reinterpret_cast<const V*>(a.src);
   const V* accin = reinterpret_cast<const V*>(a.acc_in);
   V* accout = reinterpret_cast<V*>(a.acc_out);
+  auto at = [&](int v) -> uint64_t { return (ubase + ((uint64_t)v << hb)) + lane; };
   V x[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) x[v] = ldnt(src + (ubase + ((uint64_t)v << hb)) + lane);
+  for (int v = 0; v < NV; ++v) x[v] = ldnt(src + at(v));
   R c[RB];
 #pragma unroll
   for (int b = 0; b < RB; ++b) c[b] = (R)a.cb[b];
   if constexpr (WB == 0) {
+    // blocks of VB vertices; with ACC the partial product of block k + 1 is
+    // requested before block k is stored
     constexpr int VB = 8;
+    V ain[2][VB];
+    if constexpr (ACC) {
+#pragma unroll
+      for (int u = 0; u < VB; ++u) ain[0][u] = ldnt(accin + at(u));
+    }
 #pragma unroll
     for (int v0 = 0; v0 < NV; v0 += VB) {
-      V ain[VB];
+      const int cb_ = (v0 / VB) & 1;
+      if constexpr (ACC) {
+        if (v0 + VB < NV) {
 #pragma unroll
-      for (int u = 0; u < VB; ++u)
-        ain[u] = accin ? ldnt(accin + (ubase + ((uint64_t)(v0 + u) << hb)) + lane) : V{0, 0};
+          for (int u = 0; u < VB; ++u) ain[cb_ ^ 1][u] = ldnt(accin + at(v0 + VB + u));
+        }
+      }
 #pragma unroll
       for (int u = 0; u < VB; ++u) {
         const int v = v0 + u;
@@ -724,7 +739,11 @@ __device__ __forceinline__ void regpass_body(const RegPassArgs& a, const uint64_
           hr += c[b] * x[v ^ (1 << b)].x;
           hi += c[b] * x[v ^ (1 << b)].y;
         }
-        stnt(accout + (ubase + ((uint64_t)v << hb)) + lane, V{hr + ain[u].x, hi + ain[u].y});
+        if constexpr (ACC) {
+          hr += ain[cb_][u].x;
+          hi += ain[cb_][u].y;
+        }
+        stnt(accout + at(v), V{hr, hi});
       }
     }
   } else {
@@ -733,15 +752,24 @@ __device__ __forceinline__ void regpass_body(const RegPassArgs& a, const uint64_
 #pragma unroll
     for (int j = 0; j < WB; ++j) cw[j] = (R)a.cb[RB + j];
     const int tid = threadIdx.x;
+    V ain[2][CV];
+    if constexpr (ACC) {
+#pragma unroll
+      for (int u = 0; u < CV; ++u) ain[0][u] = ldnt(accin + at(u));
+    }
 #pragma unroll
     for (int v0 = 0; v0 < NV; v0 += CV) {
-      V* buf = ex + ((v0 / CV) & 1) * (CV * NT);
+      const int cb_ = (v0 / CV) & 1;
+      V* buf = ex + cb_ * (CV * NT);
 #pragma unroll
       for (int u = 0; u < CV; ++u) buf[u * NT + tid] = x[v0 + u];
-      V ain[CV];
+      // the next chunk's partial product is requested one chunk ahead
+      if constexpr (ACC) {
+        if (v0 + CV < NV) {
 #pragma unroll
-      for (int u = 0; u < CV; ++u)
-        ain[u] = accin ? ldnt(accin + (ubase + ((uint64_t)(v0 + u) << hb)) + lane) : V{0, 0};
+          for (int u = 0; u < CV; ++u) ain[cb_ ^ 1][u] = ldnt(accin + at(v0 + CV + u));
+        }
+      }
       __syncthreads();
 #pragma unroll
       for (int u = 0; u < CV; ++u) {
@@ -758,7 +786,11 @@ __device__ __forceinline__ void regpass_body(const RegPassArgs& a, const uint64_
           hr += cw[j] * p.x;
           hi += cw[j] * p.y;
         }
-        stnt(accout + (ubase + ((uint64_t)v << hb)) + lane, V{hr + ain[u].x, hi + ain[u].y});
+        if constexpr (ACC) {
+          hr += ain[cb_][u].x;
+          hi += ain[cb_][u].y;
+        }
+        stnt(accout + at(v), V{hr, hi});
       }
     }
   }
@@ -770,10 +802,10 @@ template <typename R, int WB> struct RegLds {
   static constexpr int count = WB == 0 ? 1 : 2 * CV * RegShape<WB>::threads;
 };
 
-template <typename R, int RB, int WB>
+template <typename R, int RB, int WB, bool ACC>
 __global__ __launch_bounds__(RegShape<WB>::threads) void k_regpass(const RegPassArgs a) {
   __shared__ typename CT2<R>::V ex[RegLds<R, WB>::count];
-  regpass_body<R, RB, WB>(a, blockIdx.x, ex);
+  regpass_body<R, RB, WB, ACC>(a, blockIdx.x, ex);
 }
 
 template <typename R, int RB, int WB>
@@ -782,7 +814,9 @@ __global__ __launch_bounds__(RegShape<WB>::threads) void k_regpass_batch(
   __shared__ typename CT2<R>::V ex[RegLds<R, WB>::count];
   const int2 m = bmap[blockIdx.x];
   if (m.x < 0) return;   // uniform over the workgroup
-  regpass_body<R, RB, WB>(args[m.x], (uint64_t)m.y, ex);
+  const RegPassArgs& a = args[m.x];
+  if (a.acc_in) regpass_body<R, RB, WB, true>(a, (uint64_t)m.y, ex);
+  else regpass_body<R, RB, WB, false>(a, (uint64_t)m.y, ex);
 }
 
 int64_t regpass_blocks(int n, int wb, int dtype) {
@@ -872,22 +906,22 @@ hipError_t add_pass_batch_node(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_
                          pass_lds_bytes(max_tb, dtype), prm);
 }
 
+template <typename R, int RB, int WB>
+static void launch_regpass_t(const RegPassArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)regpass_blocks(a.n, WB, sizeof(R) == 4 ? 0 : 1));
+  const dim3 block(RegShape<WB>::threads);
+  if (a.acc_in) hipLaunchKernelGGL((k_regpass<R, RB, WB, true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((k_regpass<R, RB, WB, false>), grid, block, 0, s, a);
+}
+
 hipError_t launch_regpass(const RegPassArgs& a, int dtype, hipStream_t s) {
-  const dim3 grid((unsigned)regpass_blocks(a.n, a.wb, dtype));
   if (a.wb != 0 && a.wb != kWaveBits) return hipErrorInvalidValue;
   if (dtype == 0) {
-    if (a.wb == 0)
-      hipLaunchKernelGGL((k_regpass<float, kRegBitsC64, 0>), grid, dim3(RegShape<0>::threads), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_regpass<float, kRegBitsC64, kWaveBits>), grid,
-                         dim3(RegShape<kWaveBits>::threads), 0, s, a);
+    if (a.wb == 0) launch_regpass_t<float, kRegBitsC64, 0>(a, s);
+    else launch_regpass_t<float, kRegBitsC64, kWaveBits>(a, s);
   } else {
-    if (a.wb == 0)
-      hipLaunchKernelGGL((k_regpass<double, kRegBitsC128, 0>), grid, dim3(RegShape<0>::threads), 0, s,
-                         a);
-    else
-      hipLaunchKernelGGL((k_regpass<double, kRegBitsC128, kWaveBits>), grid,
-                         dim3(RegShape<kWaveBits>::threads), 0, s, a);
+    if (a.wb == 0) launch_regpass_t<double, kRegBitsC128, 0>(a, s);
+    else launch_regpass_t<double, kRegBitsC128, kWaveBits>(a, s);
   }
   return hipGetLastError();
 }
