@@ -398,6 +398,21 @@ typedef struct aqc_batch aqc_batch;
 aqc_status aqc_batch_create(aqc_ctx* ctx, int dtype, int capacity, aqc_batch** out);
 aqc_status aqc_batch_destroy(aqc_batch* batch);
 aqc_status aqc_batch_set_graph(aqc_batch* batch, int on);
+/* Resident solves.  With max_n > 0 (at most 20), a solve admitted later with
+ * n <= max_n is not stepped by the ticks: the next aqc_batch_step launches
+ * all such solves admitted since the previous step in one persistent launch,
+ * one workgroup per solve, which runs each solve's whole fixed-step pc4
+ * segment (RK4 bootstrap, predictor-corrector steps, the shift's phase) with
+ * workgroup barriers only, on a stream of the batch, ordered after the
+ * context stream's earlier work.  It uses the Hamiltonian's plan of tile
+ * passes only (built on first use), so its results equal aqc_evolve's to
+ * rounding, not bit for bit.  Such a solve counts as running until its launch
+ * has finished; aqc_batch_poll reports it then, and aqc_batch_step, when it
+ * has no ticks to run, waits for the oldest resident launch instead of
+ * returning at once.  Plans that do not fit (more than four passes, a tile
+ * larger than the LDS) fall back to the ticks.  0 (the default) turns it off.
+ * EINVAL for max_n outside 0..20.                                           */
+aqc_status aqc_batch_set_resident(aqc_batch* batch, int max_n);
 /* workspace one solve needs (pc4, compensated for AQC_C64)                   */
 size_t aqc_batch_workspace_bytes(const aqc_ham* ham, int dtype);
 /* Admit the solve psi(t0) -> psi(t1) in n_steps equal steps with the constant

@@ -108,6 +108,7 @@ SIGNATURES = {
     "aqc_batch_create": (I32, [P, C.c_int, C.c_int, C.POINTER(P)]),
     "aqc_batch_destroy": (I32, [P]),
     "aqc_batch_set_graph": (I32, [P, C.c_int]),
+    "aqc_batch_set_resident": (I32, [P, C.c_int]),
     "aqc_batch_workspace_bytes": (SZ, [P, C.c_int]),
     "aqc_batch_admit": (I32, [P, P, P, P, SZ, D, D, I64, D, C.POINTER(C.c_int)]),
     "aqc_batch_step": (I32, [P, C.c_int, C.POINTER(C.c_int)]),

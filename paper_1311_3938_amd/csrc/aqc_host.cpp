@@ -208,43 +208,6 @@ extern "C" aqc_status aqc_set_stream(aqc_ctx* c, void* stream) {
 // ---------------------------------------------------------------------------
 // schedules (time dependence of the coefficients, end of Sec. II.A)
 // ---------------------------------------------------------------------------
-static double path_s(const aqc_path& p, double t) {
-  if (p.kind == AQC_PATH_LINEAR) return t / p.T;
-  const double v = std::sin(M_PI * t / (2.0 * p.T));
-  return v * v;
-}
-
-static double sched_value(const aqc_sched& s, const aqc_path& p, double t) {
-  switch (s.kind) {
-    case AQC_SCHED_CONST:
-      return 1.0;
-    case AQC_SCHED_POLY_S: {
-      const double x = path_s(p, t);
-      const bool inside = x >= s.s_lo && (s.hi_closed ? x <= s.s_hi : x < s.s_hi);
-      if (!inside) return 0.0;
-      double v = 0.0, pw = 1.0;
-      for (int d = 0; d <= s.degree; ++d) {
-        v += s.coef[d] * pw;
-        pw *= x;
-      }
-      return v;
-    }
-    case AQC_SCHED_PWL_S: {
-      const double x = path_s(p, t);
-      const double* k = s.coef;   // (s_i, v_i) pairs
-      if (x < k[0]) return k[1];
-      for (int i = 0; i < s.degree; ++i) {
-        // here x >= s_i; the first knot above x bounds its segment
-        if (x < k[2 * i + 2])
-          return k[2 * i + 1] + (k[2 * i + 3] - k[2 * i + 1]) * (x - k[2 * i]) / (k[2 * i + 2] - k[2 * i]);
-      }
-      return k[2 * s.degree + 1];
-    }
-    default:
-      return s.amp * std::cos(s.omega * t + s.phase);
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Hamiltonian
 // ---------------------------------------------------------------------------
@@ -299,6 +262,9 @@ struct aqc_ham {
   std::vector<HTerm> ident;      // x == 0, z == 0
   std::vector<GroupH> groups;    // x != 0
   Plan plans[2];
+  // tile passes only (no register passes, no stream groups), per dtype: the
+  // plan of the batch engine's resident solves, built when first needed
+  Plan tplans[2];
   // tiling chosen for this Hamiltonian (aqc_ham_set_tiling), per dtype
   bool tiling_set[2] = {false, false};
   int tiling[2][4] = {{0, 0, 0, 1}, {0, 0, 0, 1}};  // tbf, tbh, lh, register passes
@@ -339,6 +305,8 @@ extern "C" aqc_status aqc_ham_free(aqc_ham* h) {
   hipDeviceSynchronize();
   free_plan(h->plans[0]);
   free_plan(h->plans[1]);
+  free_plan(h->tplans[0]);
+  free_plan(h->tplans[1]);
   for (void* b : h->sec_bufs) hipFree(b);
   delete h;
   return AQC_OK;
@@ -603,7 +571,8 @@ static aqc_status build_diag_tables(Plan& p, const aqc_ham* h, hipStream_t s) {
 // Pass layout (host only): the last pass tiles the low tbf bits; every other
 // flip pattern goes to a high pass whose tile is [0, lh) plus at most tbh - lh
 // further bits.
-static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& out, int* tbf_out) {
+static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& out, int* tbf_out,
+                                bool tiles_only = false) {
   Tiling tl = default_tiling(dtype);
   tl.tbf = env_int(dtype == 0 ? "AQC_TBF_C64" : "AQC_TBF_C128", tl.tbf);
   tl.tbh = env_int(dtype == 0 ? "AQC_TBH_C64" : "AQC_TBH_C128", tl.tbh);
@@ -617,6 +586,10 @@ static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& 
     tl.lh = h->tiling[dtype][2];
     use_reg = h->tiling[dtype][3] & 3;
     use_stream = (h->tiling[dtype][3] & 4) != 0;
+  }
+  if (tiles_only) {
+    use_reg = 0;
+    use_stream = false;
   }
   const int maxtb = dtype == 0 ? 14 : 13;
   if (tl.tbf < 1 || tl.tbf > maxtb || tl.tbh < 2 || tl.tbh > maxtb || tl.lh < 1 || tl.lh >= tl.tbh)
@@ -758,9 +731,8 @@ static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& 
   return AQC_OK;
 }
 
-static aqc_status build_plan(aqc_ham* h, int dtype, hipStream_t s) {
+static aqc_status build_plan_into(aqc_ham* h, Plan& p, int dtype, hipStream_t s, bool tiles_only) {
   std::lock_guard<std::recursive_mutex> lk(h->mu);
-  Plan& p = h->plans[dtype];
   if (p.built) return AQC_OK;
   if (h->sector_w >= 0) {
     // one kernel per product; it reads partners anywhere in its source, so
@@ -774,7 +746,7 @@ static aqc_status build_plan(aqc_ham* h, int dtype, hipStream_t s) {
   HIPCHK(hipSetDevice(h->device));
   std::vector<Pass> passes;
   int tbf = 0;
-  STCHK(layout_passes(h, dtype, passes, &tbf));
+  STCHK(layout_passes(h, dtype, passes, &tbf, tiles_only));
   p.tbf = tbf;
   p.passes = passes;
   p.has_stream = false;
@@ -784,6 +756,10 @@ static aqc_status build_plan(aqc_ham* h, int dtype, hipStream_t s) {
   STCHK(build_diag_tables(p, h, s));
   p.built = true;
   return AQC_OK;
+}
+
+static aqc_status build_plan(aqc_ham* h, int dtype, hipStream_t s) {
+  return build_plan_into(h, h->plans[dtype], dtype, s, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -993,6 +969,11 @@ extern "C" aqc_status aqc_ham_set_tiling(aqc_ham* h, int dtype, int tbf, int tbh
     HIPCHK(hipSetDevice(h->device));
     HIPCHK(hipDeviceSynchronize());
     free_plan(h->plans[dtype]);
+  }
+  if (h->tplans[dtype].built) {
+    HIPCHK(hipSetDevice(h->device));
+    HIPCHK(hipDeviceSynchronize());
+    free_plan(h->tplans[dtype]);
   }
   if (h->n <= kEagerPlanMaxN) {
     // rebuilt now, as aqc_build_hamiltonian does, so that later calls need
@@ -1889,178 +1870,6 @@ namespace {
 
 constexpr double kMilne = 19.0 / 270.0;
 
-// Vectors of one running solve (device pointers; see aqc_evolve's workspace).
-struct SolveVecs {
-  void* y;       // the caller's state
-  void* yp;      // y^p (pc4) or the RK4 stage input u
-  void* yp2;     // second y^p buffer when the last pass reads other tiles of
-                 // its source (stream groups), so no stage updates it in place
-  void* B[4];    // f history (pc4, rotating); RK4 accumulator: B[3] (pc4 bootstrap) or B[0]
-  void* hbuf;    // partial product of the high passes
-  void* ycomp;   // complex64 compensated state: low part of y, or nullptr
-};
-
-// One H|psi> of a fixed-step segment: time, tile source and stage update.
-struct MatvecStage {
-  double t;
-  const void* src;
-  EpiDesc e;
-  bool ends_step;  // completes an integration step
-  bool pc4;        // a predictor-corrector step (Milne estimate defined)
-};
-
-// Walks the matvecs of a segment on the grid t_s + k h.  pc4: RK4 steps for
-// k = 0, 1, 2 (their first stages are f_0..f_2), then one evaluation at t_3 that
-// also forms the first prediction y^p_4, then one H|psi> per step.  The same
-// sequence serves aqc_evolve and the batch engine, so a solve performs the
-// same launches alone and in a batch.
-struct SegStepper {
-  int method = AQC_METHOD_PC4;
-  double ts = 0, h = 0;
-  int64_t k = 0;      // steps done
-  int sub = 0;        // RK4 stage 0..3; 4 = evaluation at t_3 pending (pc4)
-  int64_t k_end = 0;  // stop when k reaches this
-  bool more_after = false;  // the segment continues after k_end
-  bool dbl = false;   // y^p alternates between yp and yp2
-  int ypc = 0;        // which buffer holds the current y^p
-
-  bool rk_phase() const { return method == AQC_METHOD_RK4 || (k < 3 && sub < 4); }
-  void* yp_cur(const SolveVecs& v) const { return (dbl && ypc) ? v.yp2 : v.yp; }
-  void* yp_next(const SolveVecs& v) const { return dbl ? (ypc ? v.yp : v.yp2) : v.yp; }
-  // the stage next() describes reads y^p and writes its successor
-  bool swaps_yp() const {
-    if (rk_phase()) return sub == 1 || sub == 2;
-    if (sub == 4) return false;
-    return k + 1 < k_end || more_after;
-  }
-
-  MatvecStage next(const SolveVecs& v) const {
-    MatvecStage m;
-    m.e = epi_zero();
-    m.ends_step = false;
-    m.pc4 = false;
-    const int lo_in = v.ycomp ? 1 : 0;
-    EpiDesc& e = m.e;
-    e.comp = v.ycomp;
-    const double tk = ts + (double)k * h;
-    if (rk_phase()) {
-      void* fk = method == AQC_METHOD_PC4 ? v.B[k & 3] : nullptr;
-      void* acc = method == AQC_METHOD_PC4 ? v.B[3] : v.B[0];
-      if (sub == 0) {  // acc (or f_k) = F, u = y + h/2 F
-        m.t = tk;
-        m.src = v.y;
-        e.out[0] = fk ? fk : acc;
-        e.scale[0] = 1.0;
-        e.bi[0] = -1.0;
-        e.out[1] = yp_cur(v);
-        e.cu[1] = 1.0;
-        e.scale[1] = 0.5 * h;
-        e.bi[1] = -1.0;
-        e.comp_flags = lo_in << 1;
-      } else if (sub <= 2) {  // acc = acc_in + 2F, u = y + c h F
-        m.t = tk + 0.5 * h;
-        m.src = yp_cur(v);
-        e.in[0] = v.y;
-        e.in[1] = (sub == 1 && fk) ? fk : acc;
-        e.out[0] = acc;
-        e.scale[0] = 1.0;
-        e.a[0][0] = 1.0;
-        e.bi[0] = -2.0;
-        e.out[1] = yp_next(v);
-        e.c0[1] = 1.0;
-        e.scale[1] = sub == 1 ? 0.5 * h : h;
-        e.bi[1] = -1.0;
-        e.comp_flags = lo_in << 1;
-      } else {  // y = y + h/6 (acc + F)
-        m.t = tk + h;
-        m.src = yp_cur(v);
-        e.in[0] = v.y;
-        e.in[1] = acc;
-        e.out[0] = v.y;
-        e.c0[0] = 1.0;
-        e.scale[0] = h / 6.0;
-        e.a[0][0] = 1.0;
-        e.bi[0] = -1.0;
-        e.comp_flags = v.ycomp ? (1 | 8) : 0;
-        m.ends_step = true;
-      }
-      return m;
-    }
-    if (sub == 4) {
-      // f_3 = F(t_3, y_3) and y^p_4 = y_3 + h/24 (55 f_3 - 59 f_2 + 37 f_1 - 9 f_0)
-      m.t = ts + 3.0 * h;
-      m.src = v.y;
-      e.out[0] = v.B[3];
-      e.scale[0] = 1.0;
-      e.bi[0] = -1.0;
-      e.in[0] = v.y;
-      e.in[1] = v.B[2];
-      e.in[2] = v.B[1];
-      e.in[3] = v.B[0];
-      e.out[1] = yp_cur(v);
-      e.c0[1] = 1.0;
-      e.scale[1] = h / 24.0;
-      e.a[1][0] = -59.0;
-      e.a[1][1] = 37.0;
-      e.a[1][2] = -9.0;
-      e.bi[1] = -55.0;
-      e.comp_flags = lo_in << 1;
-      return m;
-    }
-    // predictor-corrector step k -> k+1: one H|psi> at t_{k+1} on y^p_{k+1}
-    const double c = h / 24.0;
-    m.t = ts + (double)(k + 1) * h;
-    m.src = yp_cur(v);
-    m.ends_step = true;
-    m.pc4 = true;
-    e.in[0] = v.y;
-    e.in[1] = v.B[k & 3];        // f_k
-    e.in[2] = v.B[(k - 1) & 3];  // f_{k-1}
-    e.in[3] = v.B[(k - 2) & 3];  // f_{k-2}
-    e.out[0] = v.y;              // y_{k+1} = y_k + h/24 (9 F + 19 f_k - 5 f_{k-1} + f_{k-2})
-    e.c0[0] = 1.0;
-    e.scale[0] = c;
-    e.a[0][0] = 19.0;
-    e.a[0][1] = -5.0;
-    e.a[0][2] = 1.0;
-    e.bi[0] = -9.0;
-    e.out[1] = v.B[(k + 1) & 3];  // f_{k+1} = F over f_{k-3}
-    e.scale[1] = 1.0;
-    e.bi[1] = -1.0;
-    if (k + 1 < k_end || more_after) {
-      e.out[2] = yp_next(v);  // y^p_{k+2} = y_k + h/24 (64 F - 40 f_k + 32 f_{k-1} - 8 f_{k-2})
-      e.c0[2] = 1.0;
-      e.scale[2] = c;
-      e.a[2][0] = -40.0;
-      e.a[2][1] = 32.0;
-      e.a[2][2] = -8.0;
-      e.bi[2] = -64.0;
-    }
-    e.comp_flags = v.ycomp ? (1 | 8 | 4) : 0;
-    return m;
-  }
-
-  void advance() {
-    if (dbl && swaps_yp()) ypc ^= 1;
-    if (rk_phase()) {
-      if (sub < 3) {
-        ++sub;
-        return;
-      }
-      sub = 0;
-      ++k;
-      // the pc4 bootstrap ends with the evaluation at t_3 when a pc4 step follows
-      if (method == AQC_METHOD_PC4 && k == 3 && (k < k_end || more_after)) sub = 4;
-      return;
-    }
-    if (sub == 4) {
-      sub = 0;
-      return;
-    }
-    ++k;
-  }
-};
-
 struct Evolver {
   aqc_ctx* ctx;
   const aqc_ham* h;
@@ -2136,7 +1945,8 @@ static size_t comp_bytes(const aqc_ham* h) {
 // the second y^p buffer when the last pass has stream groups, and the low part
 // of a compensated complex64 state.  Advances *w.
 aqc_status carve_workspace(const aqc_ham* h, int dtype, int method, bool compensated, void* psi,
-                           char** w, SolveVecs* v) {
+                           char** w, SolveVecs* v, const Plan* plan = nullptr) {
+  const Plan& pl = plan ? *plan : h->plans[dtype];
   const size_t vb = vec_bytes(h, dtype);
   v->y = psi;
   v->yp = *w;
@@ -2152,12 +1962,12 @@ aqc_status carve_workspace(const aqc_ham* h, int dtype, int method, bool compens
     }
   }
   v->hbuf = nullptr;
-  if (h->plans[dtype].passes.size() > 1) {
+  if (pl.passes.size() > 1) {
     v->hbuf = *w;
     *w += vb;
   }
   v->yp2 = nullptr;
-  if (h->plans[dtype].has_stream) {
+  if (pl.has_stream) {
     v->yp2 = *w;
     *w += vb;
   }
@@ -2482,6 +2292,8 @@ struct aqc_batch {
     double t0 = 0, t1 = 0, shift = 0;
     int64_t matvecs = 0;
     int nreg = 0, nwide = 0, nlds = 0;  // high passes of each kind in the slot's plan
+    bool resident = false;              // run by one workgroup of a resident launch
+    int64_t n_steps = 0;
   };
   std::vector<Slot> slots;
   // launch levels: register passes 0..R-1 (narrow, then wide), tile high
@@ -2512,11 +2324,26 @@ struct aqc_batch {
   hipEvent_t sync_ev = nullptr;
   std::map<std::pair<int, int>, hipGraphExec_t> gexec;
   int64_t ticks = 0;
+  // resident solves: admitted with n <= resident_max_n, launched together at
+  // the next step (one workgroup each) on their own stream
+  int resident_max_n = 0;
+  hipStream_t rs = nullptr;
+  hipEvent_t rs_ev = nullptr;        // orders rs after the context stream
+  std::vector<int> res_pending;      // admitted, not launched yet
+  struct ResLaunch {
+    hipEvent_t done = nullptr;
+    ResidentSolve* d = nullptr;      // device copy of the solves' descriptors
+    std::vector<ResidentSolve> host; // the host copy it was made from
+    std::vector<int> slots;
+  };
+  std::vector<ResLaunch> res_launches;
 };
 
 // ticks per launch group: arguments of up to this many ticks go up in one copy
 // and (with graphs) run as one graph
 constexpr int kBatchGroup = 32;
+// largest solve a batch runs as a resident solve (one workgroup per solve)
+constexpr int kResidentMaxN = 20;
 
 // launch level of a pass: 0 tile high pass, 1 narrow register pass, 2 last
 // pass, 3 wide register pass
@@ -2528,8 +2355,6 @@ static int level_kind(const Pass& ps) {
 
 static bool is_reg_level(int kind) { return kind == 1 || kind == 3; }
 
-// H|psi> evaluations a fixed-step pc4 solve of K steps takes
-static int64_t pc4_matvecs(int64_t K) { return K <= 3 ? 4 * K : 12 + 1 + (K - 3); }
 
 static void batch_drop_graphs(aqc_batch* b) {
   for (auto& kv : b->gexec) hipGraphExecDestroy(kv.second);
@@ -2552,6 +2377,8 @@ extern "C" aqc_status aqc_batch_create(aqc_ctx* ctx, int dtype, int capacity, aq
   HIPCHK(hipEventCreateWithFlags(&b->ev[1], hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&b->sync_ev, hipEventDisableTiming));
   HIPCHK(hipStreamCreateWithFlags(&b->bs, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&b->rs, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&b->rs_ev, hipEventDisableTiming));
   *out = b.release();
   return AQC_OK;
 }
@@ -2560,7 +2387,14 @@ extern "C" aqc_status aqc_batch_destroy(aqc_batch* b) {
   if (!b) return AQC_OK;
   hipSetDevice(b->ctx->device);
   hipStreamSynchronize(b->bs);
+  if (b->rs) hipStreamSynchronize(b->rs);
   hipStreamSynchronize(b->ctx->stream);
+  for (auto& L : b->res_launches) {
+    if (L.d) hipFree(L.d);
+    if (L.done) hipEventDestroy(L.done);
+  }
+  if (b->rs_ev) hipEventDestroy(b->rs_ev);
+  if (b->rs) hipStreamDestroy(b->rs);
   batch_drop_graphs(b);
   for (auto& L : b->levels)
     if (L.dmap) hipFree(L.dmap);
@@ -2579,6 +2413,14 @@ extern "C" aqc_status aqc_batch_set_graph(aqc_batch* b, int on) {
   if (!b) return fail(AQC_EINVAL, "aqc_batch_set_graph: NULL batch");
   b->use_graph = on != 0;
   batch_drop_graphs(b);
+  return AQC_OK;
+}
+
+extern "C" aqc_status aqc_batch_set_resident(aqc_batch* b, int max_n) {
+  if (!b) return fail(AQC_EINVAL, "aqc_batch_set_resident: NULL batch");
+  if (max_n < 0 || max_n > kResidentMaxN)
+    return fail(AQC_EINVAL, "aqc_batch_set_resident: max_n is 0.." + std::to_string(kResidentMaxN));
+  b->resident_max_n = max_n;
   return AQC_OK;
 }
 
@@ -2611,12 +2453,30 @@ extern "C" aqc_status aqc_batch_admit(aqc_batch* b, const aqc_ham* h, void* psi,
       break;
     }
   if (s < 0) return fail(AQC_EBUSY, "aqc_batch_admit: no free slot");
+  // a resident solve runs the tile-pass plan of the Hamiltonian, with at most
+  // kResMaxPass passes whose tiles fit the workgroup's LDS
+  bool resident = false;
+  if (b->resident_max_n > 0 && h->n <= b->resident_max_n) {
+    aqc_ham* hm = const_cast<aqc_ham*>(h);
+    if (build_plan_into(hm, hm->tplans[b->dtype], b->dtype, b->ctx->stream, true) == AQC_OK) {
+      const Plan& tp = h->tplans[b->dtype];
+      int max_tb = 0;
+      for (const Pass& ps : tp.passes) max_tb = std::max(max_tb, ps.tb);
+      resident = (int)tp.passes.size() <= kResMaxPass && !tp.has_stream &&
+                 pass_lds_bytes(max_tb, b->dtype) + 4096 <= b->ctx->lds_max;
+    } else {
+      g_last_error.clear();
+    }
+  }
   aqc_batch::Slot& sl = b->slots[s];
   sl = aqc_batch::Slot();
   sl.used = true;
   sl.h = h;
+  sl.resident = resident;
+  sl.n_steps = n_steps;
   char* w = reinterpret_cast<char*>(ws);
-  STCHK(carve_workspace(h, b->dtype, AQC_METHOD_PC4, true, psi, &w, &sl.v));
+  STCHK(carve_workspace(h, b->dtype, AQC_METHOD_PC4, true, psi, &w, &sl.v,
+                        resident ? &h->tplans[b->dtype] : nullptr));
   if (sl.v.ycomp) HIPCHK(launch_zero(sl.v.ycomp, comp_bytes(h), b->ctx->stream));
   sl.sg.method = AQC_METHOD_PC4;
   sl.sg.ts = t0;
@@ -2627,6 +2487,11 @@ extern "C" aqc_status aqc_batch_admit(aqc_batch* b, const aqc_ham* h, void* psi,
   sl.t0 = t0;
   sl.t1 = t1;
   sl.shift = shift;
+  if (resident) {
+    b->res_pending.push_back(s);
+    *slot = s;
+    return AQC_OK;
+  }
   for (const Pass& ps : h->plans[b->dtype].passes) {
     if (ps.final_pass) continue;
     const int k = level_kind(ps);
@@ -2653,7 +2518,7 @@ static aqc_status batch_rebuild(aqc_batch* b) {
   batch_drop_graphs(b);
   int maxr = 0, maxw = 0, maxl = 0;
   for (auto& sl : b->slots)
-    if (sl.used && !sl.done) {
+    if (sl.used && !sl.done && !sl.resident) {
       maxr = std::max(maxr, sl.nreg);
       maxw = std::max(maxw, sl.nwide);
       maxl = std::max(maxl, sl.nlds);
@@ -2664,7 +2529,7 @@ static aqc_status batch_rebuild(aqc_batch* b) {
     L.idx = idx;
     for (int s = 0; s < b->capacity; ++s) {
       const auto& sl = b->slots[s];
-      if (!sl.used || sl.done) continue;
+      if (!sl.used || sl.done || sl.resident) continue;
       const Plan& p = sl.h->plans[b->dtype];
       // find the pass of this kind and index
       int seen = 0;
@@ -2738,7 +2603,7 @@ static void batch_fill_args(aqc_batch* b, char* buf) {
   std::vector<Coefs> coef(b->capacity);
   for (int s = 0; s < b->capacity; ++s) {
     auto& sl = b->slots[s];
-    if (!sl.used || sl.done) continue;
+    if (!sl.used || sl.done || sl.resident) continue;
     stage[s] = sl.sg.next(sl.v);
     coef[s] = coefs_at(sl.h, stage[s].t);
   }
@@ -2836,31 +2701,112 @@ static aqc_status batch_launch_group(aqc_batch* b, hipStream_t s, const char* hb
   return AQC_OK;
 }
 
+// Launch the resident solves admitted since the last step: one workgroup
+// each, on the batch's resident stream, after the context stream's work so
+// far (the callers' initial states and the zeroed low parts).
+static aqc_status batch_launch_resident(aqc_batch* b) {
+  if (b->res_pending.empty()) return AQC_OK;
+  std::vector<ResidentSolve> host(b->res_pending.size());
+  int max_tb = 1;
+  for (size_t i = 0; i < b->res_pending.size(); ++i) {
+    const aqc_batch::Slot& sl = b->slots[b->res_pending[i]];
+    const aqc_ham* h = sl.h;
+    const Plan& tp = h->tplans[b->dtype];
+    ResidentSolve& r = host[i];
+    std::memset(&r, 0, sizeof(r));
+    r.n = h->n;
+    r.npass = (int)tp.passes.size();
+    r.nsched = (int)h->scheds.size();
+    r.dbl = 0;
+    r.path = h->path;
+    r.shift = sl.shift;
+    r.t0 = sl.t0;
+    r.t1 = sl.t1;
+    r.h = (sl.t1 - sl.t0) / (double)sl.n_steps;
+    r.K = sl.n_steps;
+    for (const HTerm& it : h->ident) r.ident_w[it.sid] += it.w;
+    for (int q = 0; q < r.nsched; ++q) r.sched[q] = h->scheds[q];
+    r.v = sl.v;
+    const Coefs zero{};
+    for (int p = 0; p < r.npass; ++p) {
+      const Pass& ps = tp.passes[p];
+      fill_common(r.pass[p].pa, h, tp, ps, zero, sl.shift);
+      r.pass[p].nblocks = (int64_t)1 << (h->n - ps.tb);
+      max_tb = std::max(max_tb, ps.tb);
+    }
+  }
+  aqc_batch::ResLaunch L;
+  const size_t bytes = host.size() * sizeof(ResidentSolve);
+  HIPCHK(hipMalloc(&L.d, bytes));
+  HIPCHK(hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
+  L.slots = b->res_pending;
+  b->res_pending.clear();
+  HIPCHK(hipEventRecord(b->rs_ev, b->ctx->stream));
+  HIPCHK(hipStreamWaitEvent(b->rs, b->rs_ev, 0));
+  // the transfer reads the host descriptors: they live in the launch record
+  // until the launch has finished
+  L.host = std::move(host);
+  HIPCHK(hipMemcpyAsync(L.d, L.host.data(), bytes, hipMemcpyHostToDevice, b->rs));
+  HIPCHK(launch_resident(L.d, (int)L.host.size(), max_tb, b->dtype, b->rs));
+  HIPCHK(hipEventRecord(L.done, b->rs));
+  b->res_launches.push_back(std::move(L));
+  return AQC_OK;
+}
+
+// Mark the solves of finished resident launches done (wait: block until the
+// oldest launch has finished first).
+static aqc_status batch_check_resident(aqc_batch* b, bool wait) {
+  if (wait && !b->res_launches.empty()) HIPCHK(hipEventSynchronize(b->res_launches.front().done));
+  for (size_t i = 0; i < b->res_launches.size();) {
+    aqc_batch::ResLaunch& L = b->res_launches[i];
+    const hipError_t q = hipEventQuery(L.done);
+    if (q == hipErrorNotReady) {
+      ++i;
+      continue;
+    }
+    HIPCHK(q);
+    for (int sidx : L.slots) {
+      aqc_batch::Slot& sl = b->slots[sidx];
+      sl.done = true;
+      sl.sg.k = sl.n_steps;
+      sl.matvecs = pc4_matvecs(sl.n_steps);
+    }
+    HIPCHK(hipFree(L.d));
+    HIPCHK(hipEventDestroy(L.done));
+    b->res_launches.erase(b->res_launches.begin() + (long)i);
+  }
+  return AQC_OK;
+}
+
 extern "C" aqc_status aqc_batch_step(aqc_batch* b, int ticks, int* n_active) {
   if (!b) return fail(AQC_EINVAL, "aqc_batch_step: NULL batch");
   HIPCHK(hipSetDevice(b->ctx->device));
   aqc_ctx* ctx = b->ctx;
   // order the private stream after the context stream's earlier work
+  STCHK(batch_launch_resident(b));
   HIPCHK(hipEventRecord(b->sync_ev, ctx->stream));
   HIPCHK(hipStreamWaitEvent(b->bs, b->sync_ev, 0));
   const hipStream_t s = b->bs;
   int t = 0;
+  bool ticked = false;
   while (t < ticks) {
     bool any = false;
-    for (auto& sl : b->slots) any |= (sl.used && !sl.done);
+    for (auto& sl : b->slots) any |= (sl.used && !sl.done && !sl.resident);
     if (!any) break;
+    ticked = true;
     if (b->dirty) STCHK(batch_rebuild(b));
     // ticks in this group: no solve may finish inside it
     int64_t G = std::min<int64_t>(ticks - t, kBatchGroup);
     for (auto& sl : b->slots)
-      if (sl.used && !sl.done) G = std::min<int64_t>(G, pc4_matvecs(sl.sg.k_end) - sl.matvecs);
+      if (sl.used && !sl.done && !sl.resident)
+        G = std::min<int64_t>(G, pc4_matvecs(sl.sg.k_end) - sl.matvecs);
     if (G < 1) G = 1;
     const int c = b->cur;
     if (b->ev_pending[c]) HIPCHK(hipEventSynchronize(b->ev[c]));
     for (int g = 0; g < (int)G; ++g) {
       batch_fill_args(b, b->hargs[c] + b->args_bytes * (size_t)g);
       for (auto& sl : b->slots)
-        if (sl.used && !sl.done) {
+        if (sl.used && !sl.done && !sl.resident) {
           sl.sg.advance();
           ++sl.matvecs;
         }
@@ -2883,7 +2829,7 @@ extern "C" aqc_status aqc_batch_step(aqc_batch* b, int ticks, int* n_active) {
     b->ticks += G;
     t += (int)G;
     for (auto& sl : b->slots) {
-      if (!sl.used || sl.done) continue;
+      if (!sl.used || sl.done || sl.resident) continue;
       if (sl.sg.k >= sl.sg.k_end) {
         sl.done = true;
         b->dirty = true;
@@ -2897,6 +2843,9 @@ extern "C" aqc_status aqc_batch_step(aqc_batch* b, int ticks, int* n_active) {
   // the context stream continues after this step's work
   HIPCHK(hipEventRecord(b->sync_ev, s));
   HIPCHK(hipStreamWaitEvent(ctx->stream, b->sync_ev, 0));
+  // resident solves: when there was nothing to tick, wait for the oldest
+  // resident launch rather than return at once (callers loop on step)
+  STCHK(batch_check_resident(b, !ticked));
   int na = 0;
   for (auto& sl : b->slots) na += (sl.used && !sl.done) ? 1 : 0;
   if (n_active) *n_active = na;
@@ -2905,6 +2854,8 @@ extern "C" aqc_status aqc_batch_step(aqc_batch* b, int ticks, int* n_active) {
 
 extern "C" aqc_status aqc_batch_poll(aqc_batch* b, int* slots, int cap, int* n_done) {
   if (!b || !n_done || (cap > 0 && !slots)) return fail(AQC_EINVAL, "aqc_batch_poll: NULL argument");
+  HIPCHK(hipSetDevice(b->ctx->device));
+  STCHK(batch_check_resident(b, false));
   int n = 0;
   for (int s = 0; s < b->capacity; ++s) {
     auto& sl = b->slots[s];

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/aqc.h"
+
 namespace aqc {
 
 constexpr int kMaxSched = 32;       // schedules per Hamiltonian
@@ -177,6 +179,246 @@ struct SectorArgs {
   EpiDesc epi;
 };
 
+// ---- schedules and the segment stepper (shared by host and device) ---------
+// Coefficient schedules (end of Sec. II.A) evaluated at time t, and the walk
+// over the H|psi> evaluations of a fixed-step segment (Sec. II.B).  The host
+// runs them for aqc_evolve and the batch engine's ticks; the resident batch
+// kernel runs the same code on the device.
+__host__ __device__ inline double path_s(const aqc_path& p, double t) {
+  if (p.kind == AQC_PATH_LINEAR) return t / p.T;
+  const double v = sin(3.14159265358979323846 * t / (2.0 * p.T));
+  return v * v;
+}
+
+__host__ __device__ inline double sched_value(const aqc_sched& s, const aqc_path& p, double t) {
+  switch (s.kind) {
+    case AQC_SCHED_CONST:
+      return 1.0;
+    case AQC_SCHED_POLY_S: {
+      const double x = path_s(p, t);
+      const bool inside = x >= s.s_lo && (s.hi_closed ? x <= s.s_hi : x < s.s_hi);
+      if (!inside) return 0.0;
+      double v = 0.0, pw = 1.0;
+      for (int d = 0; d <= s.degree; ++d) {
+        v += s.coef[d] * pw;
+        pw *= x;
+      }
+      return v;
+    }
+    case AQC_SCHED_PWL_S: {
+      const double x = path_s(p, t);
+      const double* k = s.coef;   // (s_i, v_i) pairs
+      if (x < k[0]) return k[1];
+      for (int i = 0; i < s.degree; ++i) {
+        // here x >= s_i; the first knot above x bounds its segment
+        if (x < k[2 * i + 2])
+          return k[2 * i + 1] + (k[2 * i + 3] - k[2 * i + 1]) * (x - k[2 * i]) / (k[2 * i + 2] - k[2 * i]);
+      }
+      return k[2 * s.degree + 1];
+    }
+    default:
+      return s.amp * cos(s.omega * t + s.phase);
+  }
+}
+
+
+// Vectors of one running solve (device pointers; see aqc_evolve's workspace).
+struct SolveVecs {
+  void* y;       // the caller's state
+  void* yp;      // y^p (pc4) or the RK4 stage input u
+  void* yp2;     // second y^p buffer when the last pass reads other tiles of
+                 // its source (stream groups), so no stage updates it in place
+  void* B[4];    // f history (pc4, rotating); RK4 accumulator: B[3] (pc4 bootstrap) or B[0]
+  void* hbuf;    // partial product of the high passes
+  void* ycomp;   // complex64 compensated state: low part of y, or nullptr
+};
+
+// One H|psi> of a fixed-step segment: time, tile source and stage update.
+struct MatvecStage {
+  double t;
+  const void* src;
+  EpiDesc e;
+  bool ends_step;  // completes an integration step
+  bool pc4;        // a predictor-corrector step (Milne estimate defined)
+};
+
+// Walks the matvecs of a segment on the grid t_s + k h.  pc4: RK4 steps for
+// k = 0, 1, 2 (their first stages are f_0..f_2), then one evaluation at t_3 that
+// also forms the first prediction y^p_4, then one H|psi> per step.  The same
+// sequence serves aqc_evolve and the batch engine, so a solve performs the
+// same launches alone and in a batch.
+struct SegStepper {
+  int method = AQC_METHOD_PC4;
+  double ts = 0, h = 0;
+  int64_t k = 0;      // steps done
+  int sub = 0;        // RK4 stage 0..3; 4 = evaluation at t_3 pending (pc4)
+  int64_t k_end = 0;  // stop when k reaches this
+  bool more_after = false;  // the segment continues after k_end
+  bool dbl = false;   // y^p alternates between yp and yp2
+  int ypc = 0;        // which buffer holds the current y^p
+
+  __host__ __device__ bool rk_phase() const { return method == AQC_METHOD_RK4 || (k < 3 && sub < 4); }
+  __host__ __device__ void* yp_cur(const SolveVecs& v) const { return (dbl && ypc) ? v.yp2 : v.yp; }
+  __host__ __device__ void* yp_next(const SolveVecs& v) const { return dbl ? (ypc ? v.yp : v.yp2) : v.yp; }
+  // the stage next() describes reads y^p and writes its successor
+  __host__ __device__ bool swaps_yp() const {
+    if (rk_phase()) return sub == 1 || sub == 2;
+    if (sub == 4) return false;
+    return k + 1 < k_end || more_after;
+  }
+
+  __host__ __device__ MatvecStage next(const SolveVecs& v) const {
+    MatvecStage m;
+    m.e = EpiDesc{};
+    m.ends_step = false;
+    m.pc4 = false;
+    const int lo_in = v.ycomp ? 1 : 0;
+    EpiDesc& e = m.e;
+    e.comp = v.ycomp;
+    const double tk = ts + (double)k * h;
+    if (rk_phase()) {
+      void* fk = method == AQC_METHOD_PC4 ? v.B[k & 3] : nullptr;
+      void* acc = method == AQC_METHOD_PC4 ? v.B[3] : v.B[0];
+      if (sub == 0) {  // acc (or f_k) = F, u = y + h/2 F
+        m.t = tk;
+        m.src = v.y;
+        e.out[0] = fk ? fk : acc;
+        e.scale[0] = 1.0;
+        e.bi[0] = -1.0;
+        e.out[1] = yp_cur(v);
+        e.cu[1] = 1.0;
+        e.scale[1] = 0.5 * h;
+        e.bi[1] = -1.0;
+        e.comp_flags = lo_in << 1;
+      } else if (sub <= 2) {  // acc = acc_in + 2F, u = y + c h F
+        m.t = tk + 0.5 * h;
+        m.src = yp_cur(v);
+        e.in[0] = v.y;
+        e.in[1] = (sub == 1 && fk) ? fk : acc;
+        e.out[0] = acc;
+        e.scale[0] = 1.0;
+        e.a[0][0] = 1.0;
+        e.bi[0] = -2.0;
+        e.out[1] = yp_next(v);
+        e.c0[1] = 1.0;
+        e.scale[1] = sub == 1 ? 0.5 * h : h;
+        e.bi[1] = -1.0;
+        e.comp_flags = lo_in << 1;
+      } else {  // y = y + h/6 (acc + F)
+        m.t = tk + h;
+        m.src = yp_cur(v);
+        e.in[0] = v.y;
+        e.in[1] = acc;
+        e.out[0] = v.y;
+        e.c0[0] = 1.0;
+        e.scale[0] = h / 6.0;
+        e.a[0][0] = 1.0;
+        e.bi[0] = -1.0;
+        e.comp_flags = v.ycomp ? (1 | 8) : 0;
+        m.ends_step = true;
+      }
+      return m;
+    }
+    if (sub == 4) {
+      // f_3 = F(t_3, y_3) and y^p_4 = y_3 + h/24 (55 f_3 - 59 f_2 + 37 f_1 - 9 f_0)
+      m.t = ts + 3.0 * h;
+      m.src = v.y;
+      e.out[0] = v.B[3];
+      e.scale[0] = 1.0;
+      e.bi[0] = -1.0;
+      e.in[0] = v.y;
+      e.in[1] = v.B[2];
+      e.in[2] = v.B[1];
+      e.in[3] = v.B[0];
+      e.out[1] = yp_cur(v);
+      e.c0[1] = 1.0;
+      e.scale[1] = h / 24.0;
+      e.a[1][0] = -59.0;
+      e.a[1][1] = 37.0;
+      e.a[1][2] = -9.0;
+      e.bi[1] = -55.0;
+      e.comp_flags = lo_in << 1;
+      return m;
+    }
+    // predictor-corrector step k -> k+1: one H|psi> at t_{k+1} on y^p_{k+1}
+    const double c = h / 24.0;
+    m.t = ts + (double)(k + 1) * h;
+    m.src = yp_cur(v);
+    m.ends_step = true;
+    m.pc4 = true;
+    e.in[0] = v.y;
+    e.in[1] = v.B[k & 3];        // f_k
+    e.in[2] = v.B[(k - 1) & 3];  // f_{k-1}
+    e.in[3] = v.B[(k - 2) & 3];  // f_{k-2}
+    e.out[0] = v.y;              // y_{k+1} = y_k + h/24 (9 F + 19 f_k - 5 f_{k-1} + f_{k-2})
+    e.c0[0] = 1.0;
+    e.scale[0] = c;
+    e.a[0][0] = 19.0;
+    e.a[0][1] = -5.0;
+    e.a[0][2] = 1.0;
+    e.bi[0] = -9.0;
+    e.out[1] = v.B[(k + 1) & 3];  // f_{k+1} = F over f_{k-3}
+    e.scale[1] = 1.0;
+    e.bi[1] = -1.0;
+    if (k + 1 < k_end || more_after) {
+      e.out[2] = yp_next(v);  // y^p_{k+2} = y_k + h/24 (64 F - 40 f_k + 32 f_{k-1} - 8 f_{k-2})
+      e.c0[2] = 1.0;
+      e.scale[2] = c;
+      e.a[2][0] = -40.0;
+      e.a[2][1] = 32.0;
+      e.a[2][2] = -8.0;
+      e.bi[2] = -64.0;
+    }
+    e.comp_flags = v.ycomp ? (1 | 8 | 4) : 0;
+    return m;
+  }
+
+  __host__ __device__ void advance() {
+    if (dbl && swaps_yp()) ypc ^= 1;
+    if (rk_phase()) {
+      if (sub < 3) {
+        ++sub;
+        return;
+      }
+      sub = 0;
+      ++k;
+      // the pc4 bootstrap ends with the evaluation at t_3 when a pc4 step follows
+      if (method == AQC_METHOD_PC4 && k == 3 && (k < k_end || more_after)) sub = 4;
+      return;
+    }
+    if (sub == 4) {
+      sub = 0;
+      return;
+    }
+    ++k;
+  }
+};
+
+
+// H|psi> evaluations a fixed-step pc4 solve of K steps takes
+__host__ __device__ inline int64_t pc4_matvecs(int64_t K) { return K <= 3 ? 4 * K : 12 + 1 + (K - 3); }
+
+// ---- resident solves of a batch (one workgroup runs a whole solve) ---------
+// A small solve is run start to end by one workgroup of one launch: the
+// workgroup walks the segment stepper, evaluates the schedules at each
+// stage's time and applies every tile pass of its plan tile by tile, with
+// workgroup barriers only (no other workgroup touches its vectors).
+constexpr int kResMaxPass = 4;
+struct ResPass {
+  int64_t nblocks;    // tiles of the pass
+  PassArgs pa;        // every field that does not depend on the stage
+};
+struct ResidentSolve {
+  int32_t n, npass, nsched, dbl;
+  aqc_path path;
+  double shift, t0, t1, h;
+  int64_t K;
+  double ident_w[kMaxSched];   // identity terms: weight per schedule
+  aqc_sched sched[kMaxSched];
+  SolveVecs v;
+  ResPass pass[kResMaxPass];
+};
+
 // ---- fixed device scratch (allocation-free entry point) ----------------------
 // A file-scope device array in aqc_kernels.hip, one copy per GPU, held until
 // the process ends.  aqc_energy_noalloc keeps the partial product of the high
@@ -208,6 +450,9 @@ hipError_t add_pass_batch_node(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_
                                int max_tb, int dtype);
 size_t pass_lds_bytes(int tb, int dtype);
 hipError_t prepare_kernels();
+// resident solves: workgroup b runs solves[b] to its end (max_tb: largest
+// tile of their tile passes, which sizes the dynamic LDS)
+hipError_t launch_resident(const ResidentSolve* solves, int count, int max_tb, int dtype, hipStream_t s);
 
 // red: per-block partials [k][nblocks] -> out[k] (k < nk), fixed-order sum
 hipError_t launch_reduce_sum(const double* parts, int64_t nblocks, int nk, double* out,

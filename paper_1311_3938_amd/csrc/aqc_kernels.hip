@@ -926,6 +926,92 @@ hipError_t launch_regpass(const RegPassArgs& a, int dtype, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Resident solves of a batch: workgroup b runs solves[b] from start to end.
+// Thread 0 walks the segment stepper and writes each pass's arguments into
+// LDS; all threads evaluate the passes (tile passes only) tile by tile,
+// separated by workgroup barriers, so no other workgroup is ever waited for.
+// The shift's phase is applied at the end.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_resident(const ResidentSolve* __restrict__ solves) {
+  using V = typename CT2<R>::V;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ PassArgs pa;
+  __shared__ EpiDesc epi;
+  __shared__ double fs[kMaxSched];
+  __shared__ double stage_t;
+  __shared__ const void* stage_src;
+  const ResidentSolve& S = solves[blockIdx.x];
+  const int tid = threadIdx.x;
+  SegStepper sg;
+  sg.method = AQC_METHOD_PC4;
+  sg.ts = S.t0;
+  sg.h = S.h;
+  sg.k_end = S.K;
+  sg.more_after = false;
+  sg.dbl = S.dbl != 0;
+  const int64_t total = pc4_matvecs(S.K);
+  for (int64_t m = 0; m < total; ++m) {
+    if (tid == 0) {
+      const MatvecStage st = sg.next(S.v);
+      stage_t = st.t;
+      stage_src = st.src;
+      epi = st.e;
+    }
+    if (tid == 0) sg.advance();
+    __syncthreads();
+    if (tid < kMaxSched) fs[tid] = tid < S.nsched ? sched_value(S.sched[tid], S.path, stage_t) : 0.0;
+    __syncthreads();
+    for (int p = 0; p < S.npass; ++p) {
+      const ResPass& P = S.pass[p];
+      const bool last = p + 1 == S.npass;
+      const uint64_t* from = reinterpret_cast<const uint64_t*>(&P.pa);
+      uint64_t* to = reinterpret_cast<uint64_t*>(&pa);
+      for (int i = tid; i < (int)(sizeof(PassArgs) / 8); i += kThreads) to[i] = from[i];
+      __syncthreads();
+      if (tid == 0) {
+        double ident = 0.0;
+        for (int q = 0; q < S.nsched; ++q) ident += S.ident_w[q] * fs[q];
+        for (int q = 0; q < kMaxSched; ++q) pa.f[q] = fs[q];
+        pa.dconst = ident - S.shift;
+        pa.src = stage_src;
+        if (!last) {
+          pa.acc_in = p > 0 ? S.v.hbuf : nullptr;
+          pa.acc_out = S.v.hbuf;
+        } else {
+          pa.acc_in = S.npass > 1 ? S.v.hbuf : nullptr;
+          pa.epi = epi;
+        }
+      }
+      __syncthreads();
+      for (int64_t b = 0; b < P.nblocks; ++b) {
+        if (last) pass_body<R, true>(pa, b, P.nblocks, smem);
+        else pass_body<R, false>(pa, b, P.nblocks, smem);
+        __syncthreads();
+      }
+    }
+  }
+  const double ph = -S.shift * (S.t1 - S.t0);
+  const R cr = (R)cos(ph), ci = (R)sin(ph);
+  V* y = reinterpret_cast<V*>(S.v.y);
+  const int64_t N = (int64_t)1 << S.n;
+  for (int64_t i = tid; i < N; i += kThreads) {
+    const V v = y[i];
+    y[i] = V{cr * v.x - ci * v.y, cr * v.y + ci * v.x};
+  }
+}
+
+hipError_t launch_resident(const ResidentSolve* solves, int count, int max_tb, int dtype, hipStream_t s) {
+  if (count < 1) return hipSuccess;
+  const size_t lds = pass_lds_bytes(max_tb, dtype);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_resident<float>, dim3((unsigned)count), dim3(kThreads), lds, s, solves);
+  else
+    hipLaunchKernelGGL(k_resident<double>, dim3((unsigned)count), dim3(kThreads), lds, s, solves);
+  return hipGetLastError();
+}
+
 template <typename R, bool FINAL>
 static hipError_t set_lds_attr() {
   const int bytes = (int)pass_lds_bytes(sizeof(R) == 4 ? 14 : 13, sizeof(R) == 4 ? 0 : 1);
@@ -945,6 +1031,12 @@ hipError_t prepare_kernels() {
   if ((e = set_lds_attr<float, true>()) != hipSuccess) return e;
   if ((e = set_lds_attr<double, false>()) != hipSuccess) return e;
   if ((e = set_lds_attr<double, true>()) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_resident<float>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)pass_lds_bytes(14, 0))) != hipSuccess)
+    return e;
+  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_resident<double>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)pass_lds_bytes(13, 1))) != hipSuccess)
+    return e;
   return hipSuccess;
 }
 

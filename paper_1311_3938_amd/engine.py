@@ -377,7 +377,7 @@ def profile_read(ctx):
 class Batch:
     """Many fixed-step predictor-corrector solves advanced together (aqc_batch_*)."""
 
-    def __init__(self, ctx: Context, dtype=torch.complex64, capacity=512, graph=True):
+    def __init__(self, ctx: Context, dtype=torch.complex64, capacity=512, graph=True, resident_max_n=0):
         self.ctx = ctx
         self.dtype = dtype
         self.dt = L.C64 if dtype == torch.complex64 else L.C128
@@ -386,10 +386,16 @@ class Batch:
         self._h = h
         self.capacity = capacity
         self.set_graph(graph)
+        self.set_resident(resident_max_n)
         self._keep = {}   # slot -> (psi, workspace, Hamiltonian) kept alive until retired
 
     def set_graph(self, on):
         check(lib().aqc_batch_set_graph(self._h, 1 if on else 0))
+
+    def set_resident(self, max_n):
+        """Solves admitted later with n <= max_n run as resident solves (one
+        workgroup each, all steps in one launch); 0 turns it off."""
+        check(lib().aqc_batch_set_resident(self._h, int(max_n)))
 
     def workspace_bytes(self, ham):
         return lib().aqc_batch_workspace_bytes(ham.handle, self.dt)

@@ -121,7 +121,8 @@ class _Class:
         self.max_n = max_n
         self.stream = torch.cuda.Stream(device=server.device)   # default priority
         self.ctx = engine.Context(server.device.index or 0, stream=self.stream)
-        self.batch = engine.Batch(self.ctx, server.dtype, capacity=capacity, graph=server.graph)
+        self.batch = engine.Batch(self.ctx, server.dtype, capacity=capacity, graph=server.graph,
+                                  resident_max_n=min(server.resident_max_n, max_n))
         self.queue = []
         self.live = {}      # slot -> (request, ham, bytes, admitted time)
         self.lock = threading.Lock()
@@ -187,11 +188,13 @@ class _Class:
 
 
 class Server:
-    """size_classes: ((max_n, capacity), ...) in increasing max_n."""
+    """size_classes: ((max_n, capacity), ...) in increasing max_n.
+    resident_max_n: solves of at most this many qubits run as resident solves
+    of their batch (aqc_batch_set_resident), 0 for none."""
 
     def __init__(self, device=0, dtype=torch.complex64, hbm_budget_bytes=200e9,
                  size_classes=((20, 256), (34, 8)), ticks=8, graph=True, keep_states=False,
-                 autotune=False, progress=0, wide_register_passes=True):
+                 autotune=False, progress=0, wide_register_passes=True, resident_max_n=0):
         self.device = torch.device("cuda", device)
         self.dtype = dtype
         self.budget = float(hbm_budget_bytes)
@@ -201,6 +204,8 @@ class Server:
         self.keep_states = keep_states
         self.autotune = autotune
         self.wide_register_passes = wide_register_passes
+        # solves up to this size run as resident solves (one workgroup each)
+        self.resident_max_n = resident_max_n
         self.progress = progress     # print a line every `progress` results (0: quiet)
         self.n_admitted = 0
         self._last_report = 0.0

@@ -243,6 +243,31 @@ def main():
         b.close()
         for h in hams:
             h.free()
+    # resident solves (one workgroup each) beside ticked ones, with solves
+    # retired and re-admitted between steps
+    for dt in (torch.complex64, torch.complex128):
+        b = engine.Batch(ctx, dt, capacity=6, resident_max_n=12)
+        hams = [engine.Hamiltonian(ctx, I.workload_batch_member(k, 10, 14)) for k in range(9)]
+        states = []
+        for k in range(6):
+            psi = torch.zeros(1 << hams[k].n, dtype=dt)
+            psi[0] = 1
+            states.append(psi)
+            b.admit(hams[k], psi, 0.0, 1.0, 4 + 2 * k, 0.2)
+        nxt = 6
+        while b.info()["active"] or nxt < 9:
+            b.step(6)
+            for slot in b.poll():
+                b.retire(slot)
+                if nxt < 9:
+                    psi = torch.zeros(1 << hams[nxt].n, dtype=dt)
+                    psi[0] = 1
+                    b.admit(hams[nxt], psi, 0.0, 1.0, 7, 0.1)
+                    nxt += 1
+        b.close()
+        for h in hams:
+            h.free()
+    expect(lambda: engine.Batch(ctx, torch.complex64, capacity=2, resident_max_n=21), L.AQC_EINVAL)
     for alg, n in (("x", 7), ("xy", 8), ("xy", 10)):
         insts = [I.workload_usa(n, k, alg) for k in range(3)]
         tsearch.energies(ctx, insts, [1.0, 2.0, 3.0], [I.plus_state(n)] * 3)

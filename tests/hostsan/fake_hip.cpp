@@ -43,6 +43,7 @@ hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { *e = (hipEvent_t)n
 hipError_t hipEventDestroy(hipEvent_t e) { delobj((void*)e, "event destroy"); return hipSuccess; }
 hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) { *ms = 1.0f; return hipSuccess; }
 hipError_t hipEventRecord(hipEvent_t e, hipStream_t) { if (!g_obj.count((void*)e)) die("event record", (void*)e); return hipSuccess; }
+hipError_t hipEventQuery(hipEvent_t e) { if (!g_obj.count((void*)e)) die("event query", (void*)e); return hipSuccess; }
 hipError_t hipEventSynchronize(hipEvent_t e) { if (!g_obj.count((void*)e)) die("event sync", (void*)e); return hipSuccess; }
 hipError_t hipFree(void* p) {
   if (!p) return hipSuccess;
@@ -136,6 +137,10 @@ hipError_t add_pass_batch_node(hipGraph_t g, hipGraphNode_t* nd, hipGraphNode_t,
 hipError_t scratch_address(void** p) {
   static void* s = calloc(1, kScratchBytes);
   *p = s;
+  return hipSuccess;
+}
+hipError_t launch_resident(const ResidentSolve* solves, int count, int, int, hipStream_t) {
+  need(solves, (size_t)count * sizeof(ResidentSolve), "resident descriptors");
   return hipSuccess;
 }
 size_t pass_lds_bytes(int tb, int dtype) { return ((size_t)1 << tb) * (dtype == 0 ? 8 : 16); }

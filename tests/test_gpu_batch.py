@@ -133,3 +133,78 @@ def test_batch_short_solves_and_empty_steps(eng):
         hm.free()
     assert b.step(4) == 0 and b.info()["active"] == 0
     b.close()
+
+
+def _resident_oracle(inst, psi0, t0, t1, K, sh):
+    from oracle import sqh
+    return integrate.evolve(inst, psi0, t0, t1, K, "pc4", sh, apply=sqh.apply_h_parallel)
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_resident_solves_match_oracle(eng, dt):
+    """Resident solves (one workgroup runs a whole solve in one launch) beside
+    ticked ones in one batch: every result against the oracle; the ticked
+    ones also bit for bit against solving alone.  Sizes 9-17: one tile (9,
+    12), a tile high pass (14-16), and 17 qubits above the resident limit."""
+    engine, ctx = eng
+    import torch
+    tdt = torch.complex64 if dt == "c64" else torch.complex128
+    mix = _mix()
+    b = engine.Batch(ctx, tdt, capacity=8, resident_max_n=16)
+    slots = {}
+    for j, (inst, t0, t1, K, sh) in enumerate(mix):
+        psi0 = I.random_state(inst.n, np.random.default_rng(70 + j)).astype(np.complex64).astype(np.complex128)
+        hm = engine.Hamiltonian(ctx, inst)
+        slots[b.admit(hm, to_dev(psi0, dt), t0, t1, K, sh)] = (inst, psi0, t0, t1, K, sh, hm)
+    got = {}
+    while b.step(8) > 0 or len(got) < len(slots):
+        for s in b.poll():
+            got[s] = to_host(b.retire(s)[0])
+    b.close()
+    for s, (inst, psi0, t0, t1, K, sh, hm) in slots.items():
+        ref = _resident_oracle(inst, psi0, t0, t1, K, sh)
+        err = float(np.linalg.norm(got[s] - ref))
+        print(f"resident batch {dt} n={inst.n} K={K}: |dpsi| = {err:.3e}", flush=True)
+        assert err < TOL[dt], (inst.n, err)
+        if inst.n > 16:
+            p = to_dev(psi0, dt)
+            engine.evolve(ctx, hm, p, t0, t1, method="pc4", n_steps=K, shift=sh)
+            assert np.array_equal(to_host(p), got[s])
+        hm.free()
+
+
+def test_resident_launches_while_others_run(eng):
+    """Solves admitted while an earlier resident launch is still running go
+    into a launch of their own; short and long, one to five steps included;
+    every result against the oracle (complex128)."""
+    engine, ctx = eng
+    import torch
+    b = engine.Batch(ctx, torch.complex128, capacity=4, resident_max_n=12)
+    rng = np.random.default_rng(11)
+    todo = []
+    for j, K in enumerate([400, 1, 2, 3, 5, 60, 17, 250]):
+        inst = I.workload_batch_member(20 + j, n_lo=8, n_hi=12)
+        todo.append((inst, I.random_state(inst.n, rng), K, 0.6 + 0.1 * j))
+    slots, got, nxt = {}, {}, 0
+
+    def admit():
+        nonlocal nxt
+        inst, psi0, K, sh = todo[nxt]
+        hm = engine.Hamiltonian(ctx, inst)
+        slots[b.admit(hm, to_dev(psi0, "c128"), 0.0, K * 0.002, K, sh)] = (nxt, hm)
+        nxt += 1
+
+    while nxt < 4:
+        admit()
+    while len(got) < len(todo):
+        b.step(4)
+        for s in b.poll():
+            j, hm = slots.pop(s)
+            got[j] = to_host(b.retire(s)[0])
+            hm.free()
+            if nxt < len(todo):
+                admit()
+    b.close()
+    for j, (inst, psi0, K, sh) in enumerate(todo):
+        ref = _resident_oracle(inst, psi0, 0.0, K * 0.002, K, sh)
+        assert np.linalg.norm(got[j] - ref) < TOL["c128"], (j, K)
