@@ -96,7 +96,14 @@ typedef struct aqc_ham aqc_ham;
 /* ---- context ------------------------------------------------------------ */
 /* Binds a device and a HIP stream (hipStream_t passed as void*, NULL = the
  * default stream).  The stream is borrowed, never destroyed.  The context owns
- * small device buffers for reduction partials (a few MB).                    */
+ * small device buffers for reduction partials (a few MB).
+ * aqc_destroy waits for the stream and releases the caller's hold on the
+ * context; each batch created on it holds it too, so its memory goes with
+ * the last of them, and batches and their context may be destroyed in either
+ * order (e.g. by finalizers).  A batch whose context was destroyed refuses
+ * admit, step, poll and retire (AQC_EINVAL) and can only be destroyed.
+ * Destroying a context twice is AQC_EINVAL while a batch still holds it, and
+ * undefined after that.                                                      */
 aqc_status aqc_create(int device, void* stream, aqc_ctx** out);
 aqc_status aqc_destroy(aqc_ctx* ctx);
 aqc_status aqc_set_stream(aqc_ctx* ctx, void* stream);
@@ -396,6 +403,9 @@ aqc_status aqc_hermitian_eigh(int n, const double* a, double* w, double* z);
  * caller and must stay allocated until the solve is retired.               */
 typedef struct aqc_batch aqc_batch;
 aqc_status aqc_batch_create(aqc_ctx* ctx, int dtype, int capacity, aqc_batch** out);
+/* aqc_batch_destroy: waits for the batch's streams (and for the context's
+ * stream while the context lives), frees the batch and drops its hold on the
+ * context.                                                                  */
 aqc_status aqc_batch_destroy(aqc_batch* batch);
 aqc_status aqc_batch_set_graph(aqc_batch* batch, int on);
 /* Resident solves.  With max_n > 0 (at most 20), a solve admitted later with

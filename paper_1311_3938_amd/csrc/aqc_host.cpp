@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <numeric>
@@ -50,7 +51,7 @@ extern "C" const char* aqc_version(void) { return "aqc 0.1 (gfx950)"; }
 // context
 // ---------------------------------------------------------------------------
 // largest dynamic LDS a workgroup may use (set by aqc_create)
-static size_t g_lds_max = 0;
+static std::atomic<size_t> g_lds_max{0};
 
 struct aqc_ctx {
   int device = 0;
@@ -75,6 +76,11 @@ struct aqc_ctx {
   double prof_bytes[2] = {0, 0};  // algorithmic bytes of the timed launches
   // device address of this device's fixed scratch array (aqc_energy_noalloc)
   void* scratch = nullptr;
+  // lifetime: one reference for the caller that created the context and one
+  // per batch created on it; the memory goes with the last one.  closed is set
+  // by aqc_destroy (the caller's release); a batch then refuses further work
+  std::atomic<int> refs{1};
+  std::atomic<bool> closed{false};
 };
 
 // Device address of the fixed scratch array, looked up once per device (each
@@ -175,7 +181,7 @@ extern "C" aqc_status aqc_create(int device, void* stream, aqc_ctx** out) {
   int lds = 0;
   HIPCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
   c->lds_max = (size_t)lds;
-  g_lds_max = (size_t)lds;
+  g_lds_max.store((size_t)lds, std::memory_order_relaxed);
   HIPCHK(prepare_kernels());
   STCHK(scratch_for_device(device, &c->scratch));
   HIPCHK(hipMalloc(&c->dres, 64 * sizeof(double)));
@@ -185,17 +191,27 @@ extern "C" aqc_status aqc_create(int device, void* stream, aqc_ctx** out) {
   return AQC_OK;
 }
 
-extern "C" aqc_status aqc_destroy(aqc_ctx* c) {
-  if (!c) return AQC_OK;
+// Drops one reference; the last one frees the context's buffers and memory.
+static void ctx_release(aqc_ctx* c) {
+  if (c->refs.fetch_sub(1, std::memory_order_acq_rel) != 1) return;
   hipSetDevice(c->device);
-  hipStreamSynchronize(c->stream);
   if (c->parts) hipFree(c->parts);
   if (c->dres) hipFree(c->dres);
   if (c->hres) hipHostFree(c->hres);
   if (c->didx) hipFree(c->didx);
-  prof_drain(c);
   for (hipEvent_t e : c->prof_pool) hipEventDestroy(e);
   delete c;
+}
+
+extern "C" aqc_status aqc_destroy(aqc_ctx* c) {
+  if (!c) return AQC_OK;
+  if (c->closed.exchange(true)) return fail(AQC_EINVAL, "aqc_destroy: context already destroyed");
+  hipSetDevice(c->device);
+  // everything queued on the borrowed stream (the batches' work there too)
+  // ends here; a batch still alive never touches that stream again
+  hipStreamSynchronize(c->stream);
+  prof_drain(c);
+  ctx_release(c);
   return AQC_OK;
 }
 
@@ -594,9 +610,10 @@ static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& 
   const int maxtb = dtype == 0 ? 14 : 13;
   if (tl.tbf < 1 || tl.tbf > maxtb || tl.tbh < 2 || tl.tbh > maxtb || tl.lh < 1 || tl.lh >= tl.tbh)
     return fail(AQC_EINVAL, "tiling parameters out of range");
-  if (g_lds_max > 0) {
-    while (tl.tbf > 1 && pass_lds_bytes(tl.tbf, dtype) > g_lds_max) --tl.tbf;
-    while (tl.tbh > tl.lh + 1 && pass_lds_bytes(tl.tbh, dtype) > g_lds_max) --tl.tbh;
+  const size_t lds_max = g_lds_max.load(std::memory_order_relaxed);
+  if (lds_max > 0) {
+    while (tl.tbf > 1 && pass_lds_bytes(tl.tbf, dtype) > lds_max) --tl.tbf;
+    while (tl.tbh > tl.lh + 1 && pass_lds_bytes(tl.tbh, dtype) > lds_max) --tl.tbh;
   }
   const int n = h->n;
   const uint64_t full = (1ull << n) - 1ull;
@@ -2365,6 +2382,7 @@ extern "C" aqc_status aqc_batch_create(aqc_ctx* ctx, int dtype, int capacity, aq
   if (!out) return fail(AQC_EINVAL, "aqc_batch_create: out is NULL");
   *out = nullptr;
   if (!ctx) return fail(AQC_EINVAL, "aqc_batch_create: ctx is NULL");
+  if (ctx->closed.load()) return fail(AQC_EINVAL, "aqc_batch_create: context destroyed");
   if (dtype != AQC_C64 && dtype != AQC_C128) return fail(AQC_ENOTSUP, "aqc_batch_create: dtype");
   if (capacity < 1 || capacity > 65536) return fail(AQC_EINVAL, "aqc_batch_create: capacity 1..65536");
   HIPCHK(hipSetDevice(ctx->device));
@@ -2379,7 +2397,14 @@ extern "C" aqc_status aqc_batch_create(aqc_ctx* ctx, int dtype, int capacity, aq
   HIPCHK(hipStreamCreateWithFlags(&b->bs, hipStreamNonBlocking));
   HIPCHK(hipStreamCreateWithFlags(&b->rs, hipStreamNonBlocking));
   HIPCHK(hipEventCreateWithFlags(&b->rs_ev, hipEventDisableTiming));
+  ctx->refs.fetch_add(1, std::memory_order_relaxed);  // released by aqc_batch_destroy
   *out = b.release();
+  return AQC_OK;
+}
+
+// The batch's context was destroyed by its creator: no further work.
+static aqc_status batch_ctx_live(const aqc_batch* b, const char* who) {
+  if (b->ctx->closed.load()) return fail(AQC_EINVAL, std::string(who) + ": the batch's context was destroyed");
   return AQC_OK;
 }
 
@@ -2388,7 +2413,9 @@ extern "C" aqc_status aqc_batch_destroy(aqc_batch* b) {
   hipSetDevice(b->ctx->device);
   hipStreamSynchronize(b->bs);
   if (b->rs) hipStreamSynchronize(b->rs);
-  hipStreamSynchronize(b->ctx->stream);
+  // the context stream is borrowed: once the context is destroyed it may be
+  // gone, and aqc_destroy has already waited for it
+  if (!b->ctx->closed.load()) hipStreamSynchronize(b->ctx->stream);
   for (auto& L : b->res_launches) {
     if (L.d) hipFree(L.d);
     if (L.done) hipEventDestroy(L.done);
@@ -2405,7 +2432,9 @@ extern "C" aqc_status aqc_batch_destroy(aqc_batch* b) {
   if (b->dargs) hipFree(b->dargs);
   if (b->sync_ev) hipEventDestroy(b->sync_ev);
   if (b->bs) hipStreamDestroy(b->bs);
+  aqc_ctx* ctx = b->ctx;
   delete b;
+  ctx_release(ctx);
   return AQC_OK;
 }
 
@@ -2438,6 +2467,7 @@ extern "C" aqc_status aqc_batch_admit(aqc_batch* b, const aqc_ham* h, void* psi,
                                       double shift, int* slot) {
   if (!b || !slot) return fail(AQC_EINVAL, "aqc_batch_admit: NULL argument");
   *slot = -1;
+  STCHK(batch_ctx_live(b, "aqc_batch_admit"));
   STCHK(check_common(b->ctx, h, b->dtype));
   if (h->sector_w >= 0) return fail(AQC_ENOTSUP, "aqc_batch_admit: sectors are solved with aqc_evolve");
   if (!psi || !ws) return fail(AQC_EINVAL, "aqc_batch_admit: NULL state or workspace");
@@ -2780,6 +2810,7 @@ static aqc_status batch_check_resident(aqc_batch* b, bool wait) {
 
 extern "C" aqc_status aqc_batch_step(aqc_batch* b, int ticks, int* n_active) {
   if (!b) return fail(AQC_EINVAL, "aqc_batch_step: NULL batch");
+  STCHK(batch_ctx_live(b, "aqc_batch_step"));
   HIPCHK(hipSetDevice(b->ctx->device));
   aqc_ctx* ctx = b->ctx;
   // order the private stream after the context stream's earlier work
@@ -2854,6 +2885,7 @@ extern "C" aqc_status aqc_batch_step(aqc_batch* b, int ticks, int* n_active) {
 
 extern "C" aqc_status aqc_batch_poll(aqc_batch* b, int* slots, int cap, int* n_done) {
   if (!b || !n_done || (cap > 0 && !slots)) return fail(AQC_EINVAL, "aqc_batch_poll: NULL argument");
+  STCHK(batch_ctx_live(b, "aqc_batch_poll"));
   HIPCHK(hipSetDevice(b->ctx->device));
   STCHK(batch_check_resident(b, false));
   int n = 0;
@@ -2877,6 +2909,7 @@ extern "C" aqc_status aqc_batch_retire(aqc_batch* b, int slot, aqc_evolve_stats*
   auto& sl = b->slots[slot];
   if (!sl.used) return fail(AQC_EINVAL, "aqc_batch_retire: slot not in use");
   if (!sl.done) return fail(AQC_EBUSY, "aqc_batch_retire: solve not finished");
+  STCHK(batch_ctx_live(b, "aqc_batch_retire"));
   HIPCHK(hipStreamSynchronize(b->bs));
   if (st) {
     std::memset(st, 0, sizeof(*st));

@@ -115,6 +115,33 @@ def host_error_paths(ctx):
     ham.free()
 
 
+def context_outlived_by_batch():
+    """A batch and its context destroyed in either order (finalizers of a
+    reference cycle run in no fixed order): the context's memory stays until
+    its last batch is gone, a batch whose context was destroyed refuses work,
+    and destroying that context again is refused."""
+    for first in ("ctx", "batch"):
+        c2 = CpuCtx()
+        b = engine.Batch(c2, torch.complex64, capacity=2)
+        ham = engine.Hamiltonian(c2, I.workload_batch_member(0, 10, 10))
+        psi = torch.zeros(1 << ham.n, dtype=torch.complex64)
+        psi[0] = 1
+        b.admit(ham, psi, 0.0, 1.0, 6, 0.1)
+        b.step(2)
+        if first == "ctx":
+            raw = c2.handle.value
+            c2.close()
+            assert status_of(lambda: b.step(1)) == L.AQC_EINVAL
+            assert status_of(lambda: b.poll()) == L.AQC_EINVAL
+            assert status_of(lambda: b.admit(ham, psi.clone(), 0.0, 1.0, 4, 0.0)) == L.AQC_EINVAL
+            assert lib().aqc_destroy(C.c_void_p(raw)) == L.AQC_EINVAL
+            b.close()
+        else:
+            b.close()
+            c2.close()
+        ham.free()
+
+
 def main():
     lib().fake_hip_live.restype = C.c_long
     base = lib().fake_hip_live()
@@ -277,6 +304,7 @@ def main():
     S = tsearch.search_rounds(ctx, insts, [I.plus_state(8)] * 4, tsearch.energies, T_max=64.0,
                               plan=lambda ham, T: (int(8 + T), 0.5))
     assert all(len(s.evals) == 7 for s in S)
+    context_outlived_by_batch()
     ctx.close()
     live = lib().fake_hip_live() - base
     assert live == 0, f"{live} runtime handles left alive"
