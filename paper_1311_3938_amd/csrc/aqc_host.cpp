@@ -1508,6 +1508,17 @@ extern "C" aqc_status aqc_sector_create(aqc_ctx* ctx, const aqc_ham* src, int we
     }
     hops.push_back(hp);
   }
+  // runs of hops with the same chunk pair share their per-state work in k_sector
+  std::stable_sort(hops.begin(), hops.end(), [](const SecHop& a, const SecHop& b) {
+    return std::make_tuple(a.bi >> 2, a.bj >> 2, a.bi, a.bj) < std::make_tuple(b.bi >> 2, b.bj >> 2, b.bi, b.bj);
+  });
+  for (size_t k = 0; k < hops.size();) {
+    size_t e = k + 1;
+    while (e < hops.size() && (hops[e].bi >> 2) == (hops[k].bi >> 2) && (hops[e].bj >> 2) == (hops[k].bj >> 2)) ++e;
+    hops[k].group = (int32_t)(e - k);
+    for (size_t j = k + 1; j < e; ++j) hops[j].group = 0;
+    k = e;
+  }
   if (hterms.size() > (size_t)kSecMaxHopTerms)
     return fail(AQC_ENOTSUP, "aqc_sector_create: more than 1024 pair terms");
   if (hops.size() > (size_t)kSecMaxHops)

@@ -133,7 +133,7 @@ struct RegPassArgs {
 // bits p_0 < p_1 < ... of z (increasing order of z).  Ranks fit in 32 bits for
 // n <= 34.
 constexpr int kSecThreads = 256;
-constexpr int kSecEPT = 4;          // consecutive ranks per thread and chunk
+constexpr int kSecEPT = 2;          // consecutive ranks per thread and chunk
 constexpr int kSecMaxN = 34;
 constexpr int kSecBinom = 35;       // binomial table C(p, k), p, k <= 34
 constexpr int kSecMaxChunks = 9;    // 4-bit chunks of the rank table
@@ -148,7 +148,9 @@ struct SecHop {
   int32_t bi, bj;  // the two flipped bits, bi < bj
   int32_t fast;    // 1: every Z string lies inside x, so the coefficient of
                    // a state with differing bits depends only on bit bi
-  int32_t pad;
+  int32_t group;   // hops are sorted by the 4-bit chunks (bi / 4, bj / 4); the
+                   // first hop of each run of equal chunk pairs holds the
+                   // run's length, the others 0
 };
 constexpr int kSecMaxHops = 600;
 // The diagonal terms sharing one mask of one or two bits (q < 0: one bit p).

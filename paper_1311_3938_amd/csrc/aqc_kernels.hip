@@ -1025,8 +1025,11 @@ static hipError_t set_lds_attr() {
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
+static hipError_t set_sector_lds_attr();
+
 hipError_t prepare_kernels() {
   hipError_t e;
+  if ((e = set_sector_lds_attr()) != hipSuccess) return e;
   if ((e = set_lds_attr<float, false>()) != hipSuccess) return e;
   if ((e = set_lds_attr<float, true>()) != hipSuccess) return e;
   if ((e = set_lds_attr<double, false>()) != hipSuccess) return e;
@@ -1375,20 +1378,29 @@ __device__ void sector_setup(const SectorArgs& a, SecLds& L) {
   __syncthreads();
 }
 
-__device__ __forceinline__ double sector_diag(const SectorArgs& a, const SecLds& L, uint64_t z) {
+// number of trailing zeros, count of 1-bits and a 4-bit field of a state word
+__device__ __forceinline__ int sw_ctz(uint32_t v) { return __builtin_ctz(v); }
+__device__ __forceinline__ int sw_ctz(uint64_t v) { return __builtin_ctzll(v); }
+__device__ __forceinline__ uint32_t sw_popc(uint32_t v) { return __builtin_popcount(v); }
+__device__ __forceinline__ uint32_t sw_popc(uint64_t v) { return __builtin_popcountll(v); }
+__device__ __forceinline__ uint32_t sw_nib(uint32_t v, int c) { return __builtin_amdgcn_ubfe(v, 4 * c, 4); }
+__device__ __forceinline__ uint32_t sw_nib(uint64_t v, int c) { return (uint32_t)(v >> (4 * c)) & 15u; }
+
+template <typename W>
+__device__ __forceinline__ double sector_diag(const SectorArgs& a, const SecLds& L, W z) {
   const SectorDev& s = a.s;
-  const uint64_t full = (1ull << s.n) - 1ull;
-  const uint64_t S = s.zero_bits ? (~z & full) : z;
+  const W full = s.n >= (int)(8 * sizeof(W)) ? ~W(0) : (W(1) << s.n) - W(1);
+  const W S = s.zero_bits ? (~z & full) : z;
   double d = L.c0, pj = 0.0;
-  uint64_t m = S;
+  W m = S;
   while (m) {
-    const int p = __builtin_ctzll(m);
-    m &= m - 1ull;
+    const int p = sw_ctz(m);
+    m &= m - W(1);
     d += L.a[p];
-    uint64_t nb = L.nbr[p] & S;
+    W nb = (W)L.nbr[p] & S;
     while (nb) {
-      const int q = __builtin_ctzll(nb);
-      nb &= nb - 1ull;
+      const int q = sw_ctz(nb);
+      nb &= nb - W(1);
       pj += L.J[p * s.n + q];
     }
   }
@@ -1396,20 +1408,21 @@ __device__ __forceinline__ double sector_diag(const SectorArgs& a, const SecLds&
   for (int k = 0; k < s.nres; ++k) {
     const DevTerm t = s.res[k];
     const double mm = t.w * L.fsh[t.sid];
-    d += (__popcll(z & t.z) & 1) ? -mm : mm;
+    d += (__popcll((uint64_t)z & t.z) & 1) ? -mm : mm;
   }
   return d;
 }
 
 // the basis state of weight w at rank r (largest C(p, k) <= r, bit by bit)
-__device__ __forceinline__ uint64_t sector_unrank(const uint32_t* binom, int n, int w, int64_t r) {
-  uint64_t z = 0;
+template <typename W = uint64_t>
+__device__ __forceinline__ W sector_unrank(const uint32_t* binom, int n, int w, int64_t r) {
+  W z = 0;
   int p = n - 1;
   uint32_t rr = (uint32_t)r;
   for (int k = w; k >= 1; --k) {
     // stops at p >= k - 1, where C(k - 1, k) = 0
     while (binom[p * kSecBinom + k] > rr) --p;
-    z |= 1ull << p;
+    z |= W(1) << p;
     rr -= binom[p * kSecBinom + k];
     --p;
   }
@@ -1417,10 +1430,11 @@ __device__ __forceinline__ uint64_t sector_unrank(const uint32_t* binom, int n, 
 }
 
 // the next larger integer with the same number of 1-bits (Gosper)
-__device__ __forceinline__ uint64_t next_same_weight(uint64_t z) {
-  const uint64_t c = z & (0ull - z);
-  const uint64_t r = z + c;
-  return (((r ^ z) >> 2) >> __builtin_ctzll(c)) | r;
+template <typename W>
+__device__ __forceinline__ W next_same_weight(W z) {
+  const W c = z & (W(0) - z);
+  const W r = z + c;
+  return (((r ^ z) >> 2) >> sw_ctz(c)) | r;
 }
 
 int64_t sector_blocks(int64_t dim) {
@@ -1462,25 +1476,191 @@ __device__ __forceinline__ void sector_hop_setup(const SectorDev& s, const SecLd
   }
 }
 
-// the rank table's share of k_sector's dynamic LDS, padded to 16 bytes
+// the rank table's share of k_sector's dynamic LDS: the table, one spare row
+// of 16 words (a lane whose two bits are both 0 reads one row past its count,
+// and its result is not used) and padding to 16 bytes
 __host__ __device__ __forceinline__ size_t sector_rtab_lds_bytes(const SectorDev& sd) {
-  return ((size_t)sd.nch * 16 * (sd.w + 1) * sizeof(uint32_t) + 15) & ~(size_t)15;
+  return (((size_t)sd.nch * 16 * (sd.w + 1) + 16) * sizeof(uint32_t) + 15) & ~(size_t)15;
 }
 
+// hr + i hi += (cr + i ci) * pv for each state
 template <typename R>
-__global__ __launch_bounds__(kSecThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_sector(const SectorArgs a) {
+__device__ __forceinline__ void sector_hop_fma(R (&hr)[kSecEPT], R (&hi)[kSecEPT], const typename CT2<R>::V (&pv)[kSecEPT],
+                                               const R (&cr)[kSecEPT], const R (&ci)[kSecEPT]) {
+#pragma unroll
+  for (int u = 0; u < kSecEPT; ++u) {
+    hr[u] = hr[u] + cr[u] * pv[u].x;
+    hr[u] = hr[u] - ci[u] * pv[u].y;
+    hi[u] = hi[u] + cr[u] * pv[u].y;
+    hi[u] = hi[u] + ci[u] * pv[u].x;
+  }
+}
+
+// The off-diagonal sum over one run of pair hops that share their chunk pair
+// (ca, cb), for kSecEPT states per lane.  The partner z ^ x of a state z
+// (x = bits bi < bj, which differ in z) differs from z in the nibbles of
+// chunks ca and cb only; the chunks in between keep their nibble but see one
+// 1-bit more (z_bi = 0) or one less (z_bi = 1) below them, so their table row
+// moves by +-1.  Its rank is therefore
+//   r + T_ca[k_a][np_a] - T_ca[k_a][nz_a] + M(+-1) + T_cb[k_b +- 1][np_b] - T_cb[k_b][nz_b]
+// where only the two partner nibbles depend on the hop: everything else is
+// computed once per run and state.  Every lane runs the same instructions
+// whether or not its states' bits differ; only the gathers are masked, and a
+// hop that no state of the wave needs is skipped.  A hop's term is added one
+// hop later (qv, qr, qi hold it), so that its gathers overlap the next hop's
+// rank arithmetic.
+template <typename R, typename W>
+__device__ __forceinline__ void sector_group(const SectorDev& s, const uint32_t* rtab, const uint32_t* hrec,
+                                             int g0, int gn, const W (&zs)[kSecEPT], const bool (&ok)[kSecEPT],
+                                             uint32_t r0, uint32_t last, const R* hc, const R* tm,
+                                             const typename CT2<R>::V* __restrict__ src,
+                                             R (&hr)[kSecEPT], R (&hi)[kSecEPT], typename CT2<R>::V (&qv)[kSecEPT],
+                                             R (&qr)[kSecEPT], R (&qi)[kSecEPT]) {
+  using V = typename CT2<R>::V;
+  const uint32_t rec0 = __builtin_amdgcn_readfirstlane(hrec[g0]);
+  const int ca = (int)((rec0 & 255u) >> 2), cb = (int)(((rec0 >> 8) & 255u) >> 2);
+  const int rs = 16 * (s.w + 1);                 // words per chunk of the table
+  // per state: table rows (word offsets) at ca and cb, the nibbles there, and
+  // the hop-independent part of the partner rank for z_bi = 0 / 1
+  uint32_t ra[kSecEPT], rb[kSecEPT], na[kSecEPT], nb[kSecEPT], cp[kSecEPT], cm[kSecEPT];
+  const W below = (W(1) << (4 * ca)) - W(1);
+#pragma unroll
+  for (int u = 0; u < kSecEPT; ++u) {
+    const uint32_t ka = sw_popc(zs[u] & below);
+    na[u] = sw_nib(zs[u], ca);
+    ra[u] = (uint32_t)(ca * rs) + ka * 16u;
+    cp[u] = r0 + (uint32_t)u - rtab[ra[u] + na[u]];
+    rb[u] = ka + sw_popc(na[u]);                  // 1-bits below the next chunk
+  }
+  if (cb > ca) {
+#pragma unroll
+    for (int u = 0; u < kSecEPT; ++u) cm[u] = cp[u];
+    for (int c = ca + 1; c < cb; ++c) {
+#pragma unroll
+      for (int u = 0; u < kSecEPT; ++u) {
+        const uint32_t m = sw_nib(zs[u], c);
+        // a lane whose partner goes one row down has a 1-bit below, so the row
+        // above zero is never needed by it; its index is in range regardless
+        const uint32_t* rw = rtab + (uint32_t)(c * rs) + rb[u] * 16u + m;
+        const uint32_t t = rw[0];
+        cp[u] += rw[16] - t;
+        cm[u] += rw[-16] - t;
+        rb[u] += sw_popc(m);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kSecEPT; ++u) {
+      nb[u] = sw_nib(zs[u], cb);
+      const uint32_t row = (uint32_t)(cb * rs) + rb[u] * 16u;
+      const uint32_t t = rtab[row + nb[u]];
+      cp[u] -= t;
+      cm[u] -= t;
+      rb[u] = row;
+    }
+  }
+  for (int k = g0; k < g0 + gn; ++k) {
+    const uint32_t rec = __builtin_amdgcn_readfirstlane(hrec[k]);
+    const int bi = (int)(rec & 255u), bj = (int)((rec >> 8) & 255u);
+    const bool fast = ((rec >> 16) & 1u) != 0u;
+    const W x = (W(1) << bi) | (W(1) << bj);
+    bool act[kSecEPT], z1[kSecEPT];
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < kSecEPT; ++u) {
+      const W t = zs[u] & x;
+      act[u] = ok[u] && t != W(0) && t != x;
+      z1[u] = ((t >> bi) & W(1)) != W(0);
+      any = any || act[u];
+    }
+    // consecutive ranks share their high bits, so for a hop between two of
+    // them no state of the wave may need a partner
+    if (!__any(any)) continue;
+    uint32_t rp[kSecEPT];
+    if (cb == ca) {
+      const uint32_t fa = (1u << (bi & 3)) | (1u << (bj & 3));
+#pragma unroll
+      for (int u = 0; u < kSecEPT; ++u) rp[u] = cp[u] + rtab[ra[u] + (na[u] ^ fa)];
+    } else {
+      const uint32_t fa = 1u << (bi & 3), fb = 1u << (bj & 3);
+#pragma unroll
+      for (int u = 0; u < kSecEPT; ++u) {
+        const uint32_t rbp = z1[u] ? rb[u] - 16u : rb[u] + 16u;
+        rp[u] = (z1[u] ? cm[u] : cp[u]) + rtab[ra[u] + (na[u] ^ fa)] + rtab[rbp + (nb[u] ^ fb)];
+      }
+    }
+    V pv[kSecEPT];
+#pragma unroll
+    for (int u = 0; u < kSecEPT; ++u) {
+      // a weight-w state has a rank below dim; the clamp only guards the read
+      pv[u] = V{0, 0};
+      if (act[u]) pv[u] = src[min(rp[u], last)];
+    }
+    R cr[kSecEPT], ci[kSecEPT];
+    if (fast) {
+      // the coefficient depends only on the partner's bit bi (= 1 - z_bi)
+      const R* hk = hc + 4 * k;
+      const R a0 = hk[0], a1 = hk[1], b0 = hk[2], b1 = hk[3];
+#pragma unroll
+      for (int u = 0; u < kSecEPT; ++u) {
+        cr[u] = z1[u] ? a0 : b0;
+        ci[u] = z1[u] ? a1 : b1;
+      }
+    } else {
+      // Z strings reach outside the two bits: sum the terms with the partner's signs
+      const int t0 = s.hops[k].t0, nt = s.hops[k].nt;
+#pragma unroll
+      for (int u = 0; u < kSecEPT; ++u) cr[u] = ci[u] = 0;
+      for (int t = 0; t < nt; ++t) {
+        const DevTerm tt = s.hterms[t0 + t];
+        const R m0 = tm[t0 + t];
+#pragma unroll
+        for (int u = 0; u < kSecEPT; ++u) {
+          const R m = (sw_popc((zs[u] ^ x) & (W)tt.z) & 1u) ? -m0 : m0;
+          switch (tt.p & 3) {
+            case 0: cr[u] += m; break;
+            case 1: ci[u] += m; break;
+            case 2: cr[u] -= m; break;
+            default: ci[u] -= m; break;
+          }
+        }
+      }
+    }
+    // the previous hop's term, whose gathers have had this hop's work to land
+    sector_hop_fma<R>(hr, hi, qv, qr, qi);
+#pragma unroll
+    for (int u = 0; u < kSecEPT; ++u) {
+      qv[u] = pv[u];
+      qr[u] = cr[u];
+      qi[u] = ci[u];
+    }
+  }
+}
+
+// five waves per SIMD where the registers allow it (complex64, 32-bit
+// states), four otherwise, so that nothing spills
+template <typename R, typename W>
+__global__ __launch_bounds__(kSecThreads) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && sizeof(W) == 4 ? 5 : 4)))
+void k_sector(const SectorArgs a) {
   using V = typename CT2<R>::V;
   __shared__ SecLds L;
-  // the rank table, the hop coefficients (4 per hop) and per-term values of
-  // the other hops, sized to this sector at launch (sector_dyn_lds_bytes) so
-  // that more workgroups share a compute unit
+  // the rank table, the hop coefficients (4 per hop), per-term values of the
+  // other hops and one word per hop (bi | bj << 8 | fast << 16 | run length
+  // << 17), sized to this
+  // sector at launch (sector_dyn_lds_bytes) so that more workgroups share a
+  // compute unit
   extern __shared__ __align__(16) unsigned char smem[];
   const SectorDev& s = a.s;
   const int nrt = s.nch * 16 * (s.w + 1);
   uint32_t* rtab = reinterpret_cast<uint32_t*>(smem);
   R* hc = reinterpret_cast<R*>(smem + sector_rtab_lds_bytes(s));
   R* tm = hc + 4 * s.nhops;
+  uint32_t* hrec = reinterpret_cast<uint32_t*>(tm + s.nhterms);
   for (int i = threadIdx.x; i < nrt; i += kSecThreads) rtab[i] = s.rtab[i];
+  for (int k = threadIdx.x; k < s.nhops; k += kSecThreads) {
+    const SecHop hp = s.hops[k];
+    hrec[k] = (uint32_t)hp.bi | ((uint32_t)hp.bj << 8) | ((uint32_t)(hp.fast != 0) << 16) |
+              ((uint32_t)hp.group << 17);
+  }
   sector_setup(a, L);
   sector_hop_setup<R>(s, L, tm, hc);
   __syncthreads();
@@ -1488,15 +1668,15 @@ __global__ __launch_bounds__(kSecThreads) __attribute__((amdgpu_waves_per_eu(5))
   const EpiDesc& e = a.epi;
   const bool has_comp = e.comp != nullptr;
   uint32_t* __restrict__ compv = reinterpret_cast<uint32_t*>(e.comp);
-  const int w1 = s.w + 1;
+  const uint32_t last = (uint32_t)(s.dim - 1);
   double r0 = 0.0, r1 = 0.0, r2 = 0.0;
   const int64_t per = (int64_t)kSecThreads * kSecEPT;
   for (int64_t base = (int64_t)blockIdx.x * per; base < s.dim; base += (int64_t)gridDim.x * per) {
     const int64_t rf = base + (int64_t)threadIdx.x * kSecEPT;
-    uint64_t zs[kSecEPT];
+    W zs[kSecEPT];
     bool ok[kSecEPT];
     {
-      uint64_t z = rf < s.dim ? sector_unrank(L.binom, s.n, s.w, rf) : 0ull;
+      W z = rf < s.dim ? sector_unrank<W>(L.binom, s.n, s.w, rf) : W(0);
 #pragma unroll
       for (int u = 0; u < kSecEPT; ++u) {
         ok[u] = rf + u < s.dim;
@@ -1504,65 +1684,28 @@ __global__ __launch_bounds__(kSecThreads) __attribute__((amdgpu_waves_per_eu(5))
         if (u + 1 < kSecEPT && rf + u + 1 < s.dim) z = next_same_weight(z);
       }
     }
-    R hr[kSecEPT], hi[kSecEPT];
+    R hr[kSecEPT], hi[kSecEPT], qr[kSecEPT], qi[kSecEPT];
+    V qv[kSecEPT];
 #pragma unroll
-    for (int u = 0; u < kSecEPT; ++u) hr[u] = hi[u] = 0;
-    for (int k = 0; k < s.nhops; ++k) {
-      const SecHop hp = s.hops[k];
-      // the chunks of the two bits and the bits below the first (uniform)
-      const int ca = hp.bi >> 2, cb = hp.bj >> 2;
-      const uint64_t below = (1ull << (4 * ca)) - 1ull;
-#pragma unroll
-      for (int u = 0; u < kSecEPT; ++u) {
-        const uint64_t z = zs[u];
-        const uint32_t zi = (uint32_t)(z >> hp.bi) & 1u, zj = (uint32_t)(z >> hp.bj) & 1u;
-        if (!ok[u] || zi == zj) continue;
-        const uint64_t zp = z ^ hp.x;
-        // rank of the partner: only the chunks from bi's to bj's change, and
-        // above bi's chunk the number of 1-bits below moves by zp_bi - z_bi;
-        // the chunk loop is the same for every lane
-        const int delta = zi ? -1 : 1;
-        int cn = __popcll(z & below);
-        uint32_t rp = (uint32_t)(rf + u);
-        for (int c = ca; c <= cb; ++c) {
-          const uint32_t nz = (uint32_t)(z >> (4 * c)) & 15u, np = (uint32_t)(zp >> (4 * c)) & 15u;
-          const uint32_t* row = rtab + c * w1 * 16;
-          rp += row[(cn + (c > ca ? delta : 0)) * 16 + (int)np] - row[cn * 16 + (int)nz];
-          cn += __popc(nz);
-        }
-        // a weight-w state has a rank below dim; the clamp only guards the read
-        const V pv = src[min((int64_t)rp, s.dim - 1)];
-        R cr, ci;
-        if (hp.fast) {
-          const int q = 4 * k + 2 * (int)(1u - zi);
-          cr = hc[q];
-          ci = hc[q + 1];
-        } else {
-          cr = 0;
-          ci = 0;
-          for (int t = 0; t < hp.nt; ++t) {
-            const DevTerm tt = s.hterms[hp.t0 + t];
-            R m = tm[hp.t0 + t];
-            if (__popcll(zp & tt.z) & 1) m = -m;
-            switch (tt.p & 3) {
-              case 0: cr += m; break;
-              case 1: ci += m; break;
-              case 2: cr -= m; break;
-              default: ci -= m; break;
-            }
-          }
-        }
-        hr[u] += cr * pv.x - ci * pv.y;
-        hi[u] += cr * pv.y + ci * pv.x;
-      }
+    for (int u = 0; u < kSecEPT; ++u) {
+      hr[u] = hi[u] = qr[u] = qi[u] = 0;
+      qv[u] = V{0, 0};
     }
+    for (int g0 = 0; g0 < s.nhops;) {
+      // the run length (host-built) is at least 1 and ends at the last hop; the
+      // clamps keep the loop finite and the reads inside the hop table
+      const int gn = min(s.nhops - g0, max(1, (int)(__builtin_amdgcn_readfirstlane(hrec[g0]) >> 17)));
+      sector_group<R, W>(s, rtab, hrec, g0, gn, zs, ok, (uint32_t)rf, last, hc, tm, src, hr, hi, qv, qr, qi);
+      g0 += gn;
+    }
+    sector_hop_fma<R>(hr, hi, qv, qr, qi);
     // epilogue: the same update as the last tile pass (see EpiDesc)
 #pragma unroll
     for (int u = 0; u < kSecEPT; ++u) {
       if (!ok[u]) continue;
       const int64_t g = rf + u;
       const V uq = src[g];
-      const double d = sector_diag(a, L, zs[u]);
+      const double d = sector_diag<W>(a, L, zs[u]);
       const R hrr = (R)(d * (double)uq.x + (double)hr[u]);
       const R hii = (R)(d * (double)uq.y + (double)hi[u]);
       V xin[4];
@@ -1615,11 +1758,33 @@ __global__ __launch_bounds__(kSecThreads) __attribute__((amdgpu_waves_per_eu(5))
   if (e.red_flags) block_reduce3<kSecThreads>(r0, r1, r2, e.red_flags, L.red, e.red, gridDim.x, blockIdx.x);
 }
 
-// dynamic LDS of k_sector: the rank table, then 4 coefficients per hop and
-// one value per hop term
+// dynamic LDS of k_sector: the rank table, then 4 coefficients per hop, one
+// value per hop term and one word per hop
 static size_t sector_dyn_lds_bytes(const SectorDev& sd, int dtype) {
   return sector_rtab_lds_bytes(sd) +
-         (size_t)(4 * sd.nhops + sd.nhterms) * (dtype == 0 ? sizeof(float) : sizeof(double));
+         (size_t)(4 * sd.nhops + sd.nhterms) * (dtype == 0 ? sizeof(float) : sizeof(double)) +
+         (size_t)sd.nhops * sizeof(uint32_t);
+}
+
+// the largest dynamic LDS of k_sector (34 qubits, weight 17, complex128, the
+// most hops and hop terms) exceeds the default limit together with SecLds
+static hipError_t set_sector_lds_attr() {
+  SectorDev big{};
+  big.n = kSecMaxN;
+  big.w = kSecMaxN / 2;
+  big.nch = kSecMaxChunks;
+  big.nhops = kSecMaxHops;
+  big.nhterms = kSecMaxHopTerms;
+  const int dyn = (int)sector_dyn_lds_bytes(big, 1);
+  const void* fns[4] = {reinterpret_cast<const void*>(&k_sector<float, uint32_t>),
+                        reinterpret_cast<const void*>(&k_sector<float, uint64_t>),
+                        reinterpret_cast<const void*>(&k_sector<double, uint32_t>),
+                        reinterpret_cast<const void*>(&k_sector<double, uint64_t>)};
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_sector_matvec(const SectorArgs& a, int dtype, hipStream_t s) {
@@ -1628,8 +1793,15 @@ hipError_t launch_sector_matvec(const SectorArgs& a, int dtype, hipStream_t s) {
     return hipErrorInvalidValue;
   const dim3 grid((unsigned)sector_blocks(a.s.dim)), block(kSecThreads);
   const size_t dyn = sector_dyn_lds_bytes(a.s, dtype);
-  if (dtype == 0) hipLaunchKernelGGL(k_sector<float>, grid, block, dyn, s, a);
-  else hipLaunchKernelGGL(k_sector<double>, grid, block, dyn, s, a);
+  // states of at most 32 qubits fit a 32-bit word
+  const bool w32 = a.s.n <= 32;
+  if (dtype == 0) {
+    if (w32) hipLaunchKernelGGL((k_sector<float, uint32_t>), grid, block, dyn, s, a);
+    else hipLaunchKernelGGL((k_sector<float, uint64_t>), grid, block, dyn, s, a);
+  } else {
+    if (w32) hipLaunchKernelGGL((k_sector<double, uint32_t>), grid, block, dyn, s, a);
+    else hipLaunchKernelGGL((k_sector<double, uint64_t>), grid, block, dyn, s, a);
+  }
   return hipGetLastError();
 }
 
