@@ -1468,30 +1468,41 @@ extern "C" aqc_status aqc_sector_create(aqc_ctx* ctx, const aqc_ham* src, int we
   sd.n = n;
   sd.w = weight;
   sd.zero_bits = weight > n - weight ? 1 : 0;
-  sd.nch = (n + 3) / 4;
+  sd.nch = (n + kSecChunkBits - 1) / kSecChunkBits;
   sd.dim = h->dim;
   std::vector<uint32_t> binom(kSecBinom * kSecBinom, 0u);
   for (int p = 0; p < kSecBinom; ++p)
     for (int k = 0; k < kSecBinom; ++k) binom[p * kSecBinom + k] = (uint32_t)binom64(p, k);
-  // rank part of chunk c holding `nib` when `cnt` 1-bits lie below it:
-  // sum over its set bits b (local order j) of C(4c + b, cnt + j + 1)
-  const int w1 = weight + 1;
-  std::vector<uint32_t> rtab((size_t)sd.nch * 16 * w1, 0u);
-  for (int c = 0; c < sd.nch; ++c)
-    for (int nib = 0; nib < 16; ++nib)
-      for (int cnt = 0; cnt <= weight; ++cnt) {
-        if (cnt + popc((uint64_t)nib) > weight) continue;
+  // Rank part of chunk c holding the pattern `pat` when `cnt` 1-bits lie
+  // below it: the sum over its set bits b (local order j) of
+  // C(6c + b, cnt + j + 1), the combinatorial number system's terms of those
+  // bits.  A weight-w state has between max(0, w - (n - 6c)) and min(6c, w)
+  // 1-bits below chunk c; the rows cover that range and one spare row on each
+  // side (a partner's count is one more or one less; lanes whose bits agree
+  // read the spare rows and discard the result).
+  const int CB = kSecChunkBits, CW = 1 << kSecChunkBits;
+  std::vector<uint32_t> rtab;
+  for (int c = 0; c < sd.nch; ++c) {
+    const int lo = std::max(0, weight - (n - CB * c)), hi = std::min(CB * c, weight);
+    const size_t off = rtab.size();
+    sd.cbase[c] = (int32_t)off - (lo - 1) * CW;
+    rtab.resize(off + (size_t)(hi - lo + 3) * CW, 0u);
+    for (int cnt = lo; cnt <= hi; ++cnt)
+      for (int pat = 0; pat < CW; ++pat) {
+        if (cnt + popc((uint64_t)pat) > weight) continue;
         uint64_t v = 0;
         int j = 0;
         bool valid = true;
-        for (int b = 0; b < 4; ++b) {
-          if (!((nib >> b) & 1)) continue;
-          if (4 * c + b >= n) valid = false;
-          v += binom64(4 * c + b, cnt + j + 1);
+        for (int b = 0; b < CB; ++b) {
+          if (!((pat >> b) & 1)) continue;
+          if (CB * c + b >= n) valid = false;
+          v += binom64(CB * c + b, cnt + j + 1);
           ++j;
         }
-        if (valid && v <= 0xFFFFFFFFull) rtab[((size_t)c * w1 + cnt) * 16 + nib] = (uint32_t)v;
+        if (valid && v <= 0xFFFFFFFFull) rtab[off + (size_t)(cnt - lo + 1) * CW + pat] = (uint32_t)v;
       }
+  }
+  sd.rwords = (int32_t)rtab.size();
   std::vector<SecHop> hops;
   std::vector<DevTerm> hterms;
   for (const GroupH& g : src->groups) {
@@ -1509,12 +1520,13 @@ extern "C" aqc_status aqc_sector_create(aqc_ctx* ctx, const aqc_ham* src, int we
     hops.push_back(hp);
   }
   // runs of hops with the same chunk pair share their per-state work in k_sector
-  std::stable_sort(hops.begin(), hops.end(), [](const SecHop& a, const SecHop& b) {
-    return std::make_tuple(a.bi >> 2, a.bj >> 2, a.bi, a.bj) < std::make_tuple(b.bi >> 2, b.bj >> 2, b.bi, b.bj);
+  auto chunk = [](int b) { return b / kSecChunkBits; };
+  std::stable_sort(hops.begin(), hops.end(), [&](const SecHop& a, const SecHop& b) {
+    return std::make_tuple(chunk(a.bi), chunk(a.bj), a.bi, a.bj) < std::make_tuple(chunk(b.bi), chunk(b.bj), b.bi, b.bj);
   });
   for (size_t k = 0; k < hops.size();) {
     size_t e = k + 1;
-    while (e < hops.size() && (hops[e].bi >> 2) == (hops[k].bi >> 2) && (hops[e].bj >> 2) == (hops[k].bj >> 2)) ++e;
+    while (e < hops.size() && chunk(hops[e].bi) == chunk(hops[k].bi) && chunk(hops[e].bj) == chunk(hops[k].bj)) ++e;
     hops[k].group = (int32_t)(e - k);
     for (size_t j = k + 1; j < e; ++j) hops[j].group = 0;
     k = e;

@@ -136,7 +136,8 @@ constexpr int kSecThreads = 256;
 constexpr int kSecEPT = 2;          // consecutive ranks per thread and chunk
 constexpr int kSecMaxN = 34;
 constexpr int kSecBinom = 35;       // binomial table C(p, k), p, k <= 34
-constexpr int kSecMaxChunks = 9;    // 4-bit chunks of the rank table
+constexpr int kSecChunkBits = 6;    // bits per chunk of the rank table
+constexpr int kSecMaxChunks = 6;    // chunks of at most kSecMaxN bits
 constexpr int kSecMaxHopTerms = 1024;
 constexpr int kSecGrid = 3840;      // at most this many workgroups per launch: three rounds of
                                      // 256 compute units x 5 resident workgroups of k_sector
@@ -148,7 +149,7 @@ struct SecHop {
   int32_t bi, bj;  // the two flipped bits, bi < bj
   int32_t fast;    // 1: every Z string lies inside x, so the coefficient of
                    // a state with differing bits depends only on bit bi
-  int32_t group;   // hops are sorted by the 4-bit chunks (bi / 4, bj / 4); the
+  int32_t group;   // hops are sorted by their chunks (bi / 6, bj / 6); the
                    // first hop of each run of equal chunk pairs holds the
                    // run's length, the others 0
 };
@@ -161,12 +162,16 @@ struct SecMask {
 struct SectorDev {
   int32_t n, w;
   int32_t zero_bits;   // 1: the diagonal is summed over the 0-bits of z
-  int32_t nch;         // 4-bit chunks of n
+  int32_t nch;         // 6-bit chunks of n
+  int32_t rwords;      // words of the rank table
+  int32_t cbase[kSecMaxChunks];  // word offset of chunk c's row for 0 1-bits below it
   int32_t nhops, nhterms;
   int32_t nmasks, nres;
   int64_t dim;         // C(n, w)
   const uint32_t* binom;   // [kSecBinom][kSecBinom]
-  const uint32_t* rtab;    // [nch][w + 1][16]: rank part of a chunk given the 1-bits below it
+  const uint32_t* rtab;    // per chunk, rows of 64 words (one per 6-bit pattern) for the counts of
+                           // 1-bits below it that a weight-w state can have, plus one spare row
+                           // on each side: the rank part of the chunk's pattern given that count
   const SecHop* hops;
   const DevTerm* hterms;
   const SecMask* masks;

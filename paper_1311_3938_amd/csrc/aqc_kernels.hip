@@ -1310,7 +1310,7 @@ hipError_t launch_copy(void* dst, const void* src, int dtype, int64_t N, hipStre
 // consecutive ranks; each thread unranks its first rank once and steps to the
 // next states of the same weight with Gosper's successor.  A weight-preserving
 // hop of two differing bits reaches the partner at rank r(z ^ x), read from
-// the 4-bit chunk table; the diagonal is summed over the set bits (or the
+// the 6-bit chunk table; the diagonal is summed over the set bits (or the
 // zero bits, whichever are fewer) from per-bit and pairwise coefficients.
 // ---------------------------------------------------------------------------
 struct SecLds {
@@ -1378,13 +1378,17 @@ __device__ void sector_setup(const SectorArgs& a, SecLds& L) {
   __syncthreads();
 }
 
-// number of trailing zeros, count of 1-bits and a 4-bit field of a state word
+// number of trailing zeros, count of 1-bits and a chunk of a state word
 __device__ __forceinline__ int sw_ctz(uint32_t v) { return __builtin_ctz(v); }
 __device__ __forceinline__ int sw_ctz(uint64_t v) { return __builtin_ctzll(v); }
 __device__ __forceinline__ uint32_t sw_popc(uint32_t v) { return __builtin_popcount(v); }
 __device__ __forceinline__ uint32_t sw_popc(uint64_t v) { return __builtin_popcountll(v); }
-__device__ __forceinline__ uint32_t sw_nib(uint32_t v, int c) { return __builtin_amdgcn_ubfe(v, 4 * c, 4); }
-__device__ __forceinline__ uint32_t sw_nib(uint64_t v, int c) { return (uint32_t)(v >> (4 * c)) & 15u; }
+__device__ __forceinline__ uint32_t sw_nib(uint32_t v, int c) {
+  return __builtin_amdgcn_ubfe(v, kSecChunkBits * c, kSecChunkBits);
+}
+__device__ __forceinline__ uint32_t sw_nib(uint64_t v, int c) {
+  return (uint32_t)(v >> (kSecChunkBits * c)) & ((1u << kSecChunkBits) - 1u);
+}
 
 template <typename W>
 __device__ __forceinline__ double sector_diag(const SectorArgs& a, const SecLds& L, W z) {
@@ -1476,11 +1480,9 @@ __device__ __forceinline__ void sector_hop_setup(const SectorDev& s, const SecLd
   }
 }
 
-// the rank table's share of k_sector's dynamic LDS: the table, one spare row
-// of 16 words (a lane whose two bits are both 0 reads one row past its count,
-// and its result is not used) and padding to 16 bytes
+// the rank table's share of k_sector's dynamic LDS, padded to 16 bytes
 __host__ __device__ __forceinline__ size_t sector_rtab_lds_bytes(const SectorDev& sd) {
-  return (((size_t)sd.nch * 16 * (sd.w + 1) + 16) * sizeof(uint32_t) + 15) & ~(size_t)15;
+  return ((size_t)sd.rwords * sizeof(uint32_t) + 15) & ~(size_t)15;
 }
 
 // hr + i hi += (cr + i ci) * pv for each state
@@ -1497,13 +1499,13 @@ __device__ __forceinline__ void sector_hop_fma(R (&hr)[kSecEPT], R (&hi)[kSecEPT
 }
 
 // The off-diagonal sum over one run of pair hops that share their chunk pair
-// (ca, cb), for kSecEPT states per lane.  The partner z ^ x of a state z
-// (x = bits bi < bj, which differ in z) differs from z in the nibbles of
-// chunks ca and cb only; the chunks in between keep their nibble but see one
-// 1-bit more (z_bi = 0) or one less (z_bi = 1) below them, so their table row
-// moves by +-1.  Its rank is therefore
+// (ca, cb) of the rank table, for kSecEPT states per lane.  The partner z ^ x
+// of a state z (x = bits bi < bj, which differ in z) differs from z in the
+// patterns of chunks ca and cb only; the chunks in between keep their pattern
+// but see one 1-bit more (z_bi = 0) or one less (z_bi = 1) below them, so
+// their table row moves by +-1.  Its rank is therefore
 //   r + T_ca[k_a][np_a] - T_ca[k_a][nz_a] + M(+-1) + T_cb[k_b +- 1][np_b] - T_cb[k_b][nz_b]
-// where only the two partner nibbles depend on the hop: everything else is
+// where only the two partner patterns depend on the hop: everything else is
 // computed once per run and state.  Every lane runs the same instructions
 // whether or not its states' bits differ; only the gathers are masked, and a
 // hop that no state of the wave needs is skipped.  A hop's term is added one
@@ -1517,18 +1519,18 @@ __device__ __forceinline__ void sector_group(const SectorDev& s, const uint32_t*
                                              R (&hr)[kSecEPT], R (&hi)[kSecEPT], typename CT2<R>::V (&qv)[kSecEPT],
                                              R (&qr)[kSecEPT], R (&qi)[kSecEPT]) {
   using V = typename CT2<R>::V;
+  constexpr uint32_t CW = 1u << kSecChunkBits;     // words per table row
   const uint32_t rec0 = __builtin_amdgcn_readfirstlane(hrec[g0]);
-  const int ca = (int)((rec0 & 255u) >> 2), cb = (int)(((rec0 >> 8) & 255u) >> 2);
-  const int rs = 16 * (s.w + 1);                 // words per chunk of the table
-  // per state: table rows (word offsets) at ca and cb, the nibbles there, and
+  const int ca = (int)((rec0 >> 12) & 7u), cb = (int)((rec0 >> 15) & 7u);
+  // per state: table rows (word offsets) at ca and cb, the patterns there, and
   // the hop-independent part of the partner rank for z_bi = 0 / 1
   uint32_t ra[kSecEPT], rb[kSecEPT], na[kSecEPT], nb[kSecEPT], cp[kSecEPT], cm[kSecEPT];
-  const W below = (W(1) << (4 * ca)) - W(1);
+  const W below = (W(1) << (kSecChunkBits * ca)) - W(1);
 #pragma unroll
   for (int u = 0; u < kSecEPT; ++u) {
     const uint32_t ka = sw_popc(zs[u] & below);
     na[u] = sw_nib(zs[u], ca);
-    ra[u] = (uint32_t)(ca * rs) + ka * 16u;
+    ra[u] = (uint32_t)s.cbase[ca] + ka * CW;
     cp[u] = r0 + (uint32_t)u - rtab[ra[u] + na[u]];
     rb[u] = ka + sw_popc(na[u]);                  // 1-bits below the next chunk
   }
@@ -1541,17 +1543,17 @@ __device__ __forceinline__ void sector_group(const SectorDev& s, const uint32_t*
         const uint32_t m = sw_nib(zs[u], c);
         // a lane whose partner goes one row down has a 1-bit below, so the row
         // above zero is never needed by it; its index is in range regardless
-        const uint32_t* rw = rtab + (uint32_t)(c * rs) + rb[u] * 16u + m;
+        const uint32_t* rw = rtab + ((uint32_t)s.cbase[c] + rb[u] * CW + m);
         const uint32_t t = rw[0];
-        cp[u] += rw[16] - t;
-        cm[u] += rw[-16] - t;
+        cp[u] += rw[CW] - t;
+        cm[u] += rw[-(int)CW] - t;
         rb[u] += sw_popc(m);
       }
     }
 #pragma unroll
     for (int u = 0; u < kSecEPT; ++u) {
       nb[u] = sw_nib(zs[u], cb);
-      const uint32_t row = (uint32_t)(cb * rs) + rb[u] * 16u;
+      const uint32_t row = (uint32_t)s.cbase[cb] + rb[u] * CW;
       const uint32_t t = rtab[row + nb[u]];
       cp[u] -= t;
       cm[u] -= t;
@@ -1560,8 +1562,8 @@ __device__ __forceinline__ void sector_group(const SectorDev& s, const uint32_t*
   }
   for (int k = g0; k < g0 + gn; ++k) {
     const uint32_t rec = __builtin_amdgcn_readfirstlane(hrec[k]);
-    const int bi = (int)(rec & 255u), bj = (int)((rec >> 8) & 255u);
-    const bool fast = ((rec >> 16) & 1u) != 0u;
+    const int bi = (int)(rec & 63u), bj = (int)((rec >> 6) & 63u);
+    const bool fast = ((rec >> 18) & 1u) != 0u;
     const W x = (W(1) << bi) | (W(1) << bj);
     bool act[kSecEPT], z1[kSecEPT];
     bool any = false;
@@ -1577,14 +1579,14 @@ __device__ __forceinline__ void sector_group(const SectorDev& s, const uint32_t*
     if (!__any(any)) continue;
     uint32_t rp[kSecEPT];
     if (cb == ca) {
-      const uint32_t fa = (1u << (bi & 3)) | (1u << (bj & 3));
+      const uint32_t fa = (1u << (bi - kSecChunkBits * ca)) | (1u << (bj - kSecChunkBits * ca));
 #pragma unroll
       for (int u = 0; u < kSecEPT; ++u) rp[u] = cp[u] + rtab[ra[u] + (na[u] ^ fa)];
     } else {
-      const uint32_t fa = 1u << (bi & 3), fb = 1u << (bj & 3);
+      const uint32_t fa = 1u << (bi - kSecChunkBits * ca), fb = 1u << (bj - kSecChunkBits * cb);
 #pragma unroll
       for (int u = 0; u < kSecEPT; ++u) {
-        const uint32_t rbp = z1[u] ? rb[u] - 16u : rb[u] + 16u;
+        const uint32_t rbp = z1[u] ? rb[u] - CW : rb[u] + CW;
         rp[u] = (z1[u] ? cm[u] : cp[u]) + rtab[ra[u] + (na[u] ^ fa)] + rtab[rbp + (nb[u] ^ fb)];
       }
     }
@@ -1644,13 +1646,12 @@ void k_sector(const SectorArgs a) {
   using V = typename CT2<R>::V;
   __shared__ SecLds L;
   // the rank table, the hop coefficients (4 per hop), per-term values of the
-  // other hops and one word per hop (bi | bj << 8 | fast << 16 | run length
-  // << 17), sized to this
-  // sector at launch (sector_dyn_lds_bytes) so that more workgroups share a
-  // compute unit
+  // other hops and one word per hop (bi | bj << 6 | chunk of bi << 12 | chunk
+  // of bj << 15 | fast << 18 | run length << 19), sized to this sector at
+  // launch (sector_dyn_lds_bytes) so that more workgroups share a compute unit
   extern __shared__ __align__(16) unsigned char smem[];
   const SectorDev& s = a.s;
-  const int nrt = s.nch * 16 * (s.w + 1);
+  const int nrt = s.rwords;
   uint32_t* rtab = reinterpret_cast<uint32_t*>(smem);
   R* hc = reinterpret_cast<R*>(smem + sector_rtab_lds_bytes(s));
   R* tm = hc + 4 * s.nhops;
@@ -1658,8 +1659,9 @@ void k_sector(const SectorArgs a) {
   for (int i = threadIdx.x; i < nrt; i += kSecThreads) rtab[i] = s.rtab[i];
   for (int k = threadIdx.x; k < s.nhops; k += kSecThreads) {
     const SecHop hp = s.hops[k];
-    hrec[k] = (uint32_t)hp.bi | ((uint32_t)hp.bj << 8) | ((uint32_t)(hp.fast != 0) << 16) |
-              ((uint32_t)hp.group << 17);
+    hrec[k] = (uint32_t)hp.bi | ((uint32_t)hp.bj << 6) | ((uint32_t)(hp.bi / kSecChunkBits) << 12) |
+              ((uint32_t)(hp.bj / kSecChunkBits) << 15) | ((uint32_t)(hp.fast != 0) << 18) |
+              ((uint32_t)hp.group << 19);
   }
   sector_setup(a, L);
   sector_hop_setup<R>(s, L, tm, hc);
@@ -1676,7 +1678,9 @@ void k_sector(const SectorArgs a) {
     W zs[kSecEPT];
     bool ok[kSecEPT];
     {
-      W z = rf < s.dim ? sector_unrank<W>(L.binom, s.n, s.w, rf) : W(0);
+      // past the end a lane walks the last state (its results are dropped),
+      // so that every table row it reads is one a weight-w state can reach
+      W z = sector_unrank<W>(L.binom, s.n, s.w, min(rf, s.dim - 1));
 #pragma unroll
       for (int u = 0; u < kSecEPT; ++u) {
         ok[u] = rf + u < s.dim;
@@ -1694,7 +1698,7 @@ void k_sector(const SectorArgs a) {
     for (int g0 = 0; g0 < s.nhops;) {
       // the run length (host-built) is at least 1 and ends at the last hop; the
       // clamps keep the loop finite and the reads inside the hop table
-      const int gn = min(s.nhops - g0, max(1, (int)(__builtin_amdgcn_readfirstlane(hrec[g0]) >> 17)));
+      const int gn = min(s.nhops - g0, max(1, (int)(__builtin_amdgcn_readfirstlane(hrec[g0]) >> 19)));
       sector_group<R, W>(s, rtab, hrec, g0, gn, zs, ok, (uint32_t)rf, last, hc, tm, src, hr, hi, qv, qr, qi);
       g0 += gn;
     }
@@ -1773,6 +1777,7 @@ static hipError_t set_sector_lds_attr() {
   big.n = kSecMaxN;
   big.w = kSecMaxN / 2;
   big.nch = kSecMaxChunks;
+  big.rwords = kSecMaxChunks * (kSecMaxN + 3) << kSecChunkBits;
   big.nhops = kSecMaxHops;
   big.nhterms = kSecMaxHopTerms;
   const int dyn = (int)sector_dyn_lds_bytes(big, 1);
@@ -1789,7 +1794,8 @@ static hipError_t set_sector_lds_attr() {
 
 hipError_t launch_sector_matvec(const SectorArgs& a, int dtype, hipStream_t s) {
   if (a.s.nhops < 0 || a.s.nhops > kSecMaxHops || a.s.nhterms < 0 || a.s.nhterms > kSecMaxHopTerms ||
-      a.s.nch < 1 || a.s.nch > kSecMaxChunks || a.s.w < 0 || a.s.w > kSecMaxN)
+      a.s.nch < 1 || a.s.nch > kSecMaxChunks || a.s.w < 0 || a.s.w > kSecMaxN || a.s.rwords < 1 ||
+      a.s.rwords > (kSecMaxChunks * (kSecMaxN + 3) << kSecChunkBits))
     return hipErrorInvalidValue;
   const dim3 grid((unsigned)sector_blocks(a.s.dim)), block(kSecThreads);
   const size_t dyn = sector_dyn_lds_bytes(a.s, dtype);

@@ -157,8 +157,8 @@ def test_sector_apply_sampled_rows_full_size(eng):
 
 @pytest.mark.parametrize("w", [3, 31, 17])
 def test_sector_apply_sampled_rows_max_qubits(eng, w):
-    """The largest sectors the library takes: n = 34 (nine 4-bit chunks, the
-    last one above bit 31) on the clause-by-clause XY path with 27 clauses,
+    """The largest sectors the library takes: n = 34 (six 6-bit chunks of the
+    rank table, states in 64-bit words) on the clause-by-clause XY path with 27 clauses,
     at weights 3 and 31 (the diagonal over the one bits and over the zero
     bits) and 17 (C(34, 17) = 2 333 606 220 states, ranks above 2^31,
     complex64): sampled rows of H psi against the oracle's row-wise product."""
