@@ -490,6 +490,11 @@ static aqc_status build_pass_tables(Pass& ps, const aqc_ham* h, int dtype, hipSt
       d.fslot = nfast++;
       const int bi = __builtin_ctzll(g.x), bj = 63 - __builtin_clzll(g.x);
       d.bij = bi | (bj << 8);
+      if (!(g.x & ~tmask)) {
+        // the bits' positions in tile-local coordinates (the tile's bits in order)
+        const int li = popc(tmask & ((1ull << bi) - 1ull)), lj = popc(tmask & ((1ull << bj) - 1ull));
+        d.lij = li | (lj << 8);
+      }
     }
     dg.push_back(d);
   }

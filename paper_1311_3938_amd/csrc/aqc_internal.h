@@ -39,6 +39,8 @@ struct DevGroup {
                    // inside x, so c_x depends only on the source's bits bi,
                    // bj: a 4-entry table, slot fslot of the pass (else -1)
   int32_t bij;     // bi | bj << 8 (fast groups)
+  int32_t lij;     // li | lj << 8: the tile-local positions of bi and bj (fast
+                   // groups inside the tile)
 };
 // fast-group tables per pass: 4 complex values each, in the LDS bytes of the
 // per-term float64 coefficients (free once the set-up has used them)

@@ -26,6 +26,10 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 // Streaming (non-temporal) access for vectors that are touched once per pass.
+// a * b + c with one rounding
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 __device__ __forceinline__ float2 ldnt(const float2* p) {
   const f32x2 e = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p));
   return float2{e.x, e.y};
@@ -366,6 +370,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
   __syncthreads();
 
   // ---- 3. products and epilogue --------------------------------------------
+  // a tile smaller than the workgroup: the threads past it stand in for one
+  // inside (their results are dropped)
+  const uint32_t tidc = ntile >= (uint32_t)kThreads ? (uint32_t)tid : ((uint32_t)tid & (ntile - 1u));
   const double cprime = FINAL ? cps[0] : 0.0;
   const EpiDesc& e = a.epi;
   const bool has_comp = FINAL && e.comp != nullptr;
@@ -402,12 +409,17 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
     constexpr bool kDiagLate = sizeof(R) == 4;
     // element u of the block: tile index tid + kThreads (jb + u); its global
     // index and tile value are recomputed / re-read from LDS where needed
-    // rather than held in registers
+    // rather than held in registers.  An element past the tile (small tiles
+    // only: ok[u] false) is computed as element min(jb + u, E - 1) of thread
+    // tidc, so that the products run without per-element branches and every
+    // index they read lies inside the tile and the state; its results are
+    // dropped.
+    auto jc_of = [&](int u) -> uint32_t { return min(jb + (uint32_t)u, E - 1u); };
     auto gidx_of = [&](int u) -> uint64_t {
-      if constexpr (FINAL) return base | edep_tid | ((uint64_t)kThreads * (jb + u));
+      if constexpr (FINAL) return base | (uint64_t)tidc | ((uint64_t)kThreads * jc_of(u));
       else return base | edep_tid | eou[u];
     };
-    auto tile_of = [&](int u) -> V { return tile[tid + kThreads * (jb + u)]; };
+    auto tile_of = [&](int u) -> V { return tile[tidc + kThreads * jc_of(u)]; };
     R hr[EB], hi[EB];
     bool ok[EB];
 #pragma unroll
@@ -444,7 +456,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
         const DevGroup gr = a.groups[k];
         V pv[EB];
 #pragma unroll
-        for (int u = 0; u < EB; ++u) pv[u] = ok[u] ? src[gidx_of(u) ^ gr.x] : V{0, 0};
+        for (int u = 0; u < EB; ++u) pv[u] = src[gidx_of(u) ^ gr.x];
         if (!(gx >> 31)) {
           const R c = gco[k];
 #pragma unroll
@@ -457,17 +469,15 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
           const R* fc = ftab + 8 * gr.fslot;
 #pragma unroll
           for (int u = 0; u < EB; ++u) {
-            if (!ok[u]) continue;
             const uint64_t src_idx = gidx_of(u) ^ gr.x;
             const int q = 2 * ((int)((src_idx >> bi) & 1ull) | ((int)((src_idx >> bj) & 1ull) << 1));
             const R cr = fc[q], ci = fc[q + 1];
-            hr[u] += cr * pv[u].x - ci * pv[u].y;
-            hi[u] += cr * pv[u].y + ci * pv[u].x;
+            hr[u] = fma_r(cr, pv[u].x, fma_r(-ci, pv[u].y, hr[u]));
+            hi[u] = fma_r(cr, pv[u].y, fma_r(ci, pv[u].x, hi[u]));
           }
         } else {
 #pragma unroll
           for (int u = 0; u < EB; ++u) {
-            if (!ok[u]) continue;
             const uint64_t src_idx = gidx_of(u) ^ gr.x;
             R cr = 0, ci = 0;
             for (int t = 0; t < gr.nt; ++t) {
@@ -481,52 +491,49 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
                 default: ci -= m; break;
               }
             }
-            hr[u] += cr * pv[u].x - ci * pv[u].y;
-            hi[u] += cr * pv[u].y + ci * pv[u].x;
+            hr[u] = fma_r(cr, pv[u].x, fma_r(-ci, pv[u].y, hr[u]));
+            hi[u] = fma_r(cr, pv[u].y, fma_r(ci, pv[u].x, hi[u]));
           }
         }
         continue;
       }
+      // The tile index of element u is l = tid | (jb + u) << 9 (2^9 threads),
+      // so its partner's, l ^ xl, splits into a part fixed per thread, tid ^
+      // (xl's low 9 bits), and a part shared by the wave, (jb + u) ^ (xl >> 9):
+      // per element one OR forms the address.
+      constexpr int kTidBits = 9;
       if (!(gx >> 31)) {
         const R c = gco[k];
+        const uint32_t at = tidc ^ (gx & (kThreads - 1u));
 #pragma unroll
         for (int u = 0; u < EB; ++u) {
-          if (!ok[u]) continue;
-          const uint32_t l = tid + kThreads * (jb + u);
-          const V v = tile[l ^ gx];
+          const uint32_t jx = jc_of(u) ^ (gx >> kTidBits);
+          const V v = tile[at | (jx << kTidBits)];
           hr[u] += c * v.x;
           hi[u] += c * v.y;
         }
       } else {
         const DevGroup gr = a.groups[k];
         if (gr.fslot >= 0) {
-          const int bi = gr.bij & 255, bj = gr.bij >> 8;
+          // the table entry is 2 (s_i + 2 s_j) for the source's bits s_i, s_j,
+          // bits li, lj of the partner's tile index
+          const uint32_t li = (uint32_t)gr.lij & 255u, lj = (uint32_t)gr.lij >> 8;
+          const uint32_t at = tidc ^ (gr.xl & (kThreads - 1u));
           const R* fc = ftab + 8 * gr.fslot;
 #pragma unroll
           for (int u = 0; u < EB; ++u) {
-            if (!ok[u]) continue;
-            const uint32_t l = tid + kThreads * (jb + u);
-            int q;
-            if constexpr (FINAL) {
-              // the last pass's tile is the low tb bits: the source's bits
-              // bi, bj are those of its tile index
-              const uint32_t sl = l ^ gr.xl;
-              q = 2 * (int)(((sl >> bi) & 1u) | (((sl >> bj) & 1u) << 1));
-            } else {
-              const uint64_t src_idx = gidx_of(u) ^ gr.x;
-              q = 2 * ((int)((src_idx >> bi) & 1ull) | ((int)((src_idx >> bj) & 1ull) << 1));
-            }
+            const uint32_t sl = at | ((jc_of(u) ^ (gr.xl >> kTidBits)) << kTidBits);
+            const uint32_t q = 2u * (__builtin_amdgcn_ubfe(sl, li, 1) | (__builtin_amdgcn_ubfe(sl, lj, 1) << 1));
             const R cr = fc[q], ci = fc[q + 1];
-            const V v = tile[l ^ gr.xl];
-            hr[u] += cr * v.x - ci * v.y;
-            hi[u] += cr * v.y + ci * v.x;
+            const V v = tile[sl];
+            hr[u] = fma_r(cr, v.x, fma_r(-ci, v.y, hr[u]));
+            hi[u] = fma_r(cr, v.y, fma_r(ci, v.x, hi[u]));
           }
           continue;
         }
 #pragma unroll
         for (int u = 0; u < EB; ++u) {
-          if (!ok[u]) continue;
-          const uint32_t l = tid + kThreads * (jb + u);
+          const uint32_t l = tidc + kThreads * jc_of(u);
           const uint64_t src_idx = gidx_of(u) ^ gr.x;
           R cr = 0, ci = 0;
           for (int t = 0; t < gr.nt; ++t) {
@@ -541,8 +548,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
             }
           }
           const V v = tile[l ^ gr.xl];
-          hr[u] += cr * v.x - ci * v.y;
-          hi[u] += cr * v.y + ci * v.x;
+          hr[u] = fma_r(cr, v.x, fma_r(-ci, v.y, hr[u]));
+          hi[u] = fma_r(cr, v.y, fma_r(ci, v.x, hi[u]));
         }
       }
     }
