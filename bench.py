@@ -21,7 +21,7 @@ whole path at n = 24, the first window at n = 30); a compact batched run and a
 compact served run (continuous batching, Poisson arrivals) on the generators
 of the batched and serving workloads, each against the plain single-instance
 complex128 path on the same solves (solves/s, p50/p99 latency, |dF|); and the
-oracle timed on the host on a whole 12-qubit solve, with the library's
+oracle timed on the host on a whole 13-qubit solve, with the library's
 complex64 and complex128 errors against it.
 
 Prints one JSON line (rank 0, N = 1 only)."""
@@ -43,9 +43,9 @@ def sk_plan(ham, T):
     return int(math.ceil(T * 0.5 * (hi - lo) / 0.1)), 0.5 * (lo + hi)
 
 
-def cpu_baseline(ctx, n=12, T=30.0):
+def cpu_baseline(ctx, n=13, T=30.0):
     """The oracle (NumPy complex128, one thread) on a whole solve of the same
-    workload family at n = 12 (the full path from |+>, fixed-step pc4 with the
+    workload family at n = 13 (the full path from |+>, fixed-step pc4 with the
     library's step and shift), timed; the library solves the same problem in
     complex64 and complex128, and their errors against the oracle's state and
     ground-state mass at T are reported with it."""
@@ -670,7 +670,7 @@ def accuracy_checks(ctx, inst30, W, h, opts):
       at T, where F is not small;
     * the first window of the 30-qubit run: ||dpsi|| (F is ~1e-9 there, so no
       fidelity figure is taken from it).
-    The errors against the oracle itself come with the CPU baseline (n = 12)."""
+    The errors against the oracle itself come with the CPU baseline (n = 13)."""
     import torch
     from paper_1311_3938_amd import engine
     from paper_1311_3938_amd import instances as I
