@@ -146,9 +146,17 @@ def run_batch_mode(args):
     srv.close()
     log(f"batch done in {wall:.1f} s")
     sub = reqs[:args.baseline_subset]
+    # the same subset as a batch of its own, for a like-for-like rate
+    srv_sub = serve.Server(dtype=torch.complex64, hbm_budget_bytes=args.hbm_budget * 1e9,
+                           size_classes=((34, max(1, len(sub))),), ticks=args.ticks, graph=True,
+                           autotune=not args.no_autotune, resident_max_n=args.resident_max_n)
+    res_sub, wall_sub = srv_sub.run([serve.Request(q.rid, q.inst) for q in sub])
+    srv_sub.close()
+    log(f"the first {len(sub)} solves as a batch of their own: {wall_sub:.1f} s")
     log(f"sequential complex128 on {len(sub)} of the solves")
     seq = serve.sequential_plain(sub, progress=True)
     seq_time = sum(s[0] for s in seq) or float("nan")
+    seq_lat = serve.fifo_latencies([0.0] * len(sub), [s_[0] for s_ in seq])
     dFs = [abs(seq[i][1] - res[i].fidelity) for i in range(len(sub))]
     dF = max(dFs) if dFs else None
     out = {
@@ -164,7 +172,10 @@ def run_batch_mode(args):
         "autotune_s_before_timing": tune_s,
         "baseline_plain_c128_sequential": {
             "solves": len(sub), "seconds": seq_time, "solves_per_s": len(sub) / seq_time,
-            "batched_solves_per_s_on_same": None},
+            "latency_s": {"p50": serve.percentile(seq_lat, 50), "p99": serve.percentile(seq_lat, 99)},
+            "batched_solves_per_s_on_same": len(res_sub) / wall_sub,
+            "batched_latency_s_on_same": {"p50": serve.percentile([r.latency for r in res_sub], 50),
+                                          "p99": serve.percentile([r.latency for r in res_sub], 99)}},
         "max_abs_dF_vs_c128_plain": dF,
         "dF_vs_c128_plain": error_summary(dFs, sub, res) if dFs else None,
         "latency_s": {"p50": serve.percentile([r.latency for r in res], 50),
