@@ -197,6 +197,48 @@ def test_sector_apply_sampled_rows_max_qubits(eng, w):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("w", [16, 29])
+def test_sector_apply_sampled_rows_word_limit(eng, w):
+    """n = 32, the largest size whose states fit the kernel's 32-bit words
+    (bit 31 set in half of the states, the last 6-bit chunk two bits wide):
+    weight 16 (C(32, 16) = 601 080 390 states) and 29 (the diagonal over the
+    zero bits), complex64, sampled rows of H psi against the oracle's
+    row-wise product."""
+    engine, ctx, torch = eng
+    n = 32
+    inst = I.workload_ec3_paths(n=n, m=26, T=20.0, kind="cbc", seed=I.seed_for(5))
+    ham = engine.Hamiltonian(ctx, inst)
+    sec = engine.Sector(ctx, ham, w)
+    assert sec.dim == math.comb(n, w)
+    g = torch.Generator(device="cuda").manual_seed(13)
+    psi = torch.randn(sec.dim, dtype=torch.complex64, device="cuda", generator=g)
+    out = engine.apply(ctx, sec, 11.0, psi)
+    rng = np.random.default_rng(14)
+    rows = []
+    while len(rows) < 200:
+        rows.append(int(sum(1 << int(q) for q in rng.choice(n, w, replace=False))))
+    rows += [(1 << w) - 1, ((1 << w) - 1) << (n - w)]   # the first and the last state
+    rows = np.unique(np.array(rows, dtype=np.int64))
+
+    def values_at(idx):
+        idx = np.asarray(idx, dtype=np.int64)
+        keep = np.array([bin(int(z)).count("1") == w for z in idx])
+        vals = np.zeros(idx.shape, dtype=np.complex128)
+        if keep.any():
+            ranks = torch.tensor([_colex_rank(int(z)) for z in idx[keep]], dtype=torch.int64, device="cuda")
+            vals[keep] = psi.index_select(0, ranks).cpu().to(torch.complex128).numpy()
+        return vals
+
+    want = sqh.apply_h_rows(inst, 11.0, values_at, rows)
+    ranks = torch.tensor([_colex_rank(int(z)) for z in rows], dtype=torch.int64, device="cuda")
+    got = out.index_select(0, ranks).cpu().to(torch.complex128).numpy()
+    assert np.max(np.abs(got - want)) / np.abs(want).max() < 5e-6
+    del out, psi
+    sec.free()
+    ham.free()
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("n", [32, 33])
 def test_apply_sampled_rows_past_32bit_indices(eng, n):
     """H psi of the SK workload with amplitude indices past 2^31 (n = 32) and
