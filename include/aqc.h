@@ -106,7 +106,15 @@ typedef struct aqc_ham aqc_ham;
  * undefined after that.                                                      */
 aqc_status aqc_create(int device, void* stream, aqc_ctx** out);
 aqc_status aqc_destroy(aqc_ctx* ctx);
+/* aqc_set_stream waits for the context's current stream before switching.  */
 aqc_status aqc_set_stream(aqc_ctx* ctx, void* stream);
+/* aqc_trim: the device buffers of released Hamiltonian tables (aqc_ham_free,
+ * a replaced plan) are kept and reused by later Hamiltonians once every
+ * stream the library launches on has passed the release, because freeing
+ * device memory waits for every stream of the device; up to 1 GiB per device
+ * is kept.  aqc_trim waits for those releases and frees the kept buffers of
+ * `device`.  AQC_EINVAL for a device index outside 0..63.                   */
+aqc_status aqc_trim(int device);
 const char* aqc_last_error(void);
 const char* aqc_version(void);
 
@@ -128,6 +136,9 @@ aqc_status aqc_build_hamiltonian(aqc_ctx* ctx, int n_qubits, int64_t n_terms,
                                  const double* weight, const int32_t* sched_id,
                                  int n_sched, const aqc_sched* scheds,
                                  const aqc_path* path, aqc_ham** out);
+/* aqc_ham_free returns without waiting for the device: launches already
+ * queued may still read the tables, whose buffers go to the pool that
+ * aqc_trim describes.  NULL is a no-op.                                     */
 aqc_status aqc_ham_free(aqc_ham* ham);
 
 typedef struct {

@@ -84,6 +84,7 @@ SZ = C.c_size_t
 SIGNATURES = {
     "aqc_create": (I32, [C.c_int, P, C.POINTER(P)]),
     "aqc_destroy": (I32, [P]),
+    "aqc_trim": (I32, [I32]),
     "aqc_set_stream": (I32, [P, P]),
     "aqc_last_error": (C.c_char_p, []),
     "aqc_version": (C.c_char_p, []),

@@ -103,6 +103,171 @@ static aqc_status scratch_for_device(int device, void** out) {
   return AQC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Device buffers of Hamiltonian tables.  Freeing device memory waits for
+// every stream of the device, so a finished solve that frees its Hamiltonian
+// would stall the solves running beside it.  Table buffers of released
+// Hamiltonians and replaced plans are kept per device instead, and handed out
+// again once every stream the library launches on has passed an event
+// recorded at the release (no launch queued before it can still read them);
+// otherwise a fresh buffer is allocated.  The cache holds at most
+// kTabCacheBytes per device; aqc_trim empties it.
+// ---------------------------------------------------------------------------
+struct TabEv {
+  hipStream_t s;
+  hipEvent_t e;
+};
+struct TabBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  std::vector<TabEv> ev;   // recorded at the release, one per stream
+};
+constexpr size_t kTabCacheBytes = size_t(1) << 30;
+static std::mutex g_tab_mu;
+static std::vector<TabBuf> g_tab_free[kMaxDevices];      // released, maybe still read
+static std::map<void*, size_t> g_tab_size[kMaxDevices];  // buffers handed out
+static size_t g_tab_cached[kMaxDevices] = {};
+static std::map<hipStream_t, int> g_tab_streams[kMaxDevices];  // streams launched on
+
+static void tab_stream_add(int dev, hipStream_t s) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_tab_mu);
+  ++g_tab_streams[dev][s];
+}
+
+// The caller has synchronized `s`: every event recorded on it has completed.
+// Its last user gone, the stream may be destroyed next, so the kept buffers
+// drop their events on it (no event outlives the stream it was recorded on).
+static void tab_stream_remove(int dev, hipStream_t s) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_tab_mu);
+  auto it = g_tab_streams[dev].find(s);
+  if (it == g_tab_streams[dev].end() || --it->second > 0) return;
+  g_tab_streams[dev].erase(it);
+  for (TabBuf& b : g_tab_free[dev]) {
+    auto keep = b.ev.begin();
+    for (auto e = b.ev.begin(); e != b.ev.end(); ++e) {
+      if (e->s == s)
+        hipEventDestroy(e->e);
+      else
+        *keep++ = *e;
+    }
+    b.ev.erase(keep, b.ev.end());
+  }
+}
+
+// Every launch queued before the release has ended.  A query that reports
+// anything but success or not-ready counts as not ready, and the error it
+// leaves behind is consumed here rather than by the next launch check.
+static bool tab_ready(const TabBuf& b) {
+  for (const TabEv& e : b.ev) {
+    const hipError_t r = hipEventQuery(e.e);
+    if (r == hipSuccess) continue;
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
+}
+
+// `bytes` of device memory on the current device (the caller has set it)
+static aqc_status tab_alloc(void** p, size_t bytes) {
+  *p = nullptr;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(AQC_ENOTSUP, "device index above 63");
+  {
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    auto& fl = g_tab_free[dev];
+    int best = -1;
+    for (int i = 0; i < (int)fl.size(); ++i) {
+      const size_t c = fl[i].cap;
+      if (c < bytes || c > 2 * bytes + 65536) continue;
+      if (best >= 0 && c >= fl[best].cap) continue;
+      if (!tab_ready(fl[i])) continue;
+      best = i;
+    }
+    if (best >= 0) {
+      TabBuf b = fl[best];
+      fl.erase(fl.begin() + best);
+      for (const TabEv& e : b.ev) hipEventDestroy(e.e);
+      g_tab_cached[dev] -= b.cap;
+      g_tab_size[dev][b.p] = b.cap;
+      *p = b.p;
+      return AQC_OK;
+    }
+  }
+  HIPCHK(hipMalloc(p, bytes));
+  std::lock_guard<std::mutex> lk(g_tab_mu);
+  g_tab_size[dev][*p] = bytes;
+  return AQC_OK;
+}
+
+// Releases a buffer of tab_alloc on device `dev` (null: nothing).
+static void tab_release(int dev, void* p) {
+  if (!p || dev < 0 || dev >= kMaxDevices) return;
+  std::unique_lock<std::mutex> lk(g_tab_mu);
+  auto it = g_tab_size[dev].find(p);
+  const size_t cap = it != g_tab_size[dev].end() ? it->second : 0;
+  if (it != g_tab_size[dev].end()) g_tab_size[dev].erase(it);
+  if (cap == 0 || g_tab_cached[dev] + cap > kTabCacheBytes) {
+    lk.unlock();
+    hipSetDevice(dev);
+    hipFree(p);   // waits for the device
+    return;
+  }
+  TabBuf b;
+  b.p = p;
+  b.cap = cap;
+  int cur = 0;
+  hipGetDevice(&cur);
+  hipSetDevice(dev);
+  bool ok = true;
+  for (const auto& kv : g_tab_streams[dev]) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      ok = false;
+      break;
+    }
+    b.ev.push_back({kv.first, e});
+    if (hipEventRecord(e, kv.first) != hipSuccess) {
+      ok = false;
+      break;
+    }
+  }
+  if (!ok) {
+    // no proof that the queued launches are done with it: free instead
+    (void)hipGetLastError();
+    lk.unlock();
+    for (const TabEv& e : b.ev) hipEventDestroy(e.e);
+    hipFree(p);   // waits for the device
+    hipSetDevice(cur);
+    return;
+  }
+  hipSetDevice(cur);
+  g_tab_cached[dev] += cap;
+  g_tab_free[dev].push_back(std::move(b));
+}
+
+extern "C" aqc_status aqc_trim(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(AQC_EINVAL, "aqc_trim: bad device index");
+  std::vector<TabBuf> fl;
+  {
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    fl.swap(g_tab_free[device]);
+    g_tab_cached[device] = 0;
+  }
+  if (fl.empty()) return AQC_OK;
+  HIPCHK(hipSetDevice(device));
+  for (TabBuf& b : fl) {
+    for (const TabEv& e : b.ev) {
+      hipEventSynchronize(e.e);
+      hipEventDestroy(e.e);
+    }
+    HIPCHK(hipFree(b.p));
+  }
+  return AQC_OK;
+}
+
 static aqc_status prof_drain(aqc_ctx* c) {
   if (c->prof_pending.empty()) return AQC_OK;
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -178,6 +343,7 @@ extern "C" aqc_status aqc_create(int device, void* stream, aqc_ctx** out) {
   std::unique_ptr<aqc_ctx> c(new aqc_ctx());
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(stream);
+  tab_stream_add(device, c->stream);
   int lds = 0;
   HIPCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
   c->lds_max = (size_t)lds;
@@ -211,12 +377,19 @@ extern "C" aqc_status aqc_destroy(aqc_ctx* c) {
   // ends here; a batch still alive never touches that stream again
   hipStreamSynchronize(c->stream);
   prof_drain(c);
+  tab_stream_remove(c->device, c->stream);
   ctx_release(c);
   return AQC_OK;
 }
 
 extern "C" aqc_status aqc_set_stream(aqc_ctx* c, void* stream) {
   if (!c) return fail(AQC_EINVAL, "aqc_set_stream: ctx is NULL");
+  // work queued on the old stream may read tables released later, which are
+  // reused once the streams in use have passed the release: finish it first
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  tab_stream_add(c->device, reinterpret_cast<hipStream_t>(stream));
+  tab_stream_remove(c->device, c->stream);
   c->stream = reinterpret_cast<hipStream_t>(stream);
   return AQC_OK;
 }
@@ -301,29 +474,29 @@ struct aqc_ham {
 // tables are small there); larger ones are built on first use
 constexpr int kEagerPlanMaxN = 26;
 
-static void free_plan(Plan& p) {
+// Releases a plan's table buffers (they are reused only after every stream
+// the library launches on has passed this point).
+static void free_plan(Plan& p, int dev) {
   for (auto& ps : p.passes) {
-    if (ps.dgroups) hipFree(ps.dgroups);
-    if (ps.dterms) hipFree(ps.dterms);
+    tab_release(dev, ps.dgroups);
+    tab_release(dev, ps.dterms);
   }
   p.passes.clear();
-  if (p.dCT) hipFree(p.dCT);
-  if (p.dLT) hipFree(p.dLT);
-  if (p.dTAB64) hipFree(p.dTAB64);
-  if (p.dTAB32) hipFree(p.dTAB32);
-  if (p.dres) hipFree(p.dres);
+  tab_release(dev, p.dCT);
+  tab_release(dev, p.dLT);
+  tab_release(dev, p.dTAB64);
+  tab_release(dev, p.dTAB32);
+  tab_release(dev, p.dres);
   p = Plan();
 }
 
 extern "C" aqc_status aqc_ham_free(aqc_ham* h) {
   if (!h) return AQC_OK;
-  hipSetDevice(h->device);
-  hipDeviceSynchronize();
-  free_plan(h->plans[0]);
-  free_plan(h->plans[1]);
-  free_plan(h->tplans[0]);
-  free_plan(h->tplans[1]);
-  for (void* b : h->sec_bufs) hipFree(b);
+  free_plan(h->plans[0], h->device);
+  free_plan(h->plans[1], h->device);
+  free_plan(h->tplans[0], h->device);
+  free_plan(h->tplans[1], h->device);
+  for (void* b : h->sec_bufs) tab_release(h->device, b);
   delete h;
   return AQC_OK;
 }
@@ -414,7 +587,7 @@ extern "C" aqc_status aqc_build_hamiltonian(aqc_ctx* ctx, int n, int64_t n_terms
       // a Hamiltonian the default tiling cannot hold is still returned: the
       // error then comes from the first use (or aqc_ham_set_tiling fixes it)
       if (build_plan(h.get(), d, ctx->stream) != AQC_OK) {
-        free_plan(h->plans[d]);
+        free_plan(h->plans[d], h->device);
         g_last_error.clear();
       }
     }
@@ -452,7 +625,7 @@ static aqc_status upload(void** dst, const void* src, size_t bytes, hipStream_t 
     *dst = nullptr;
     return AQC_OK;
   }
-  HIPCHK(hipMalloc(dst, bytes));
+  STCHK(tab_alloc(dst, bytes));
   HIPCHK(hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   return AQC_OK;
@@ -986,20 +1159,14 @@ extern "C" aqc_status aqc_ham_set_tiling(aqc_ham* h, int dtype, int tbf, int tbh
     std::memcpy(h->tiling[dtype], old, sizeof(old));
     return st;
   }
-  if (h->plans[dtype].built) {
-    // the old plan's tables may still be read by queued launches
-    HIPCHK(hipSetDevice(h->device));
-    HIPCHK(hipDeviceSynchronize());
-    free_plan(h->plans[dtype]);
-  }
-  if (h->tplans[dtype].built) {
-    HIPCHK(hipSetDevice(h->device));
-    HIPCHK(hipDeviceSynchronize());
-    free_plan(h->tplans[dtype]);
-  }
+  // the old plan's tables may still be read by queued launches: they are
+  // released, not freed (see tab_release)
+  if (h->plans[dtype].built) free_plan(h->plans[dtype], h->device);
+  if (h->tplans[dtype].built) free_plan(h->tplans[dtype], h->device);
   if (h->n <= kEagerPlanMaxN) {
     // rebuilt now, as aqc_build_hamiltonian does, so that later calls need
-    // no allocation (uploads on the null stream: the device is idle here)
+    // no allocation (uploads on the null stream, into buffers that no queued
+    // launch reads)
     HIPCHK(hipSetDevice(h->device));
     STCHK(build_plan(h, dtype, nullptr));
   }
@@ -1441,7 +1608,7 @@ static aqc_status sector_upload(aqc_ham* h, const std::vector<T>& v, const T** d
   *dst = nullptr;
   if (v.empty()) return AQC_OK;
   void* d = nullptr;
-  HIPCHK(hipMalloc(&d, v.size() * sizeof(T)));
+  STCHK(tab_alloc(&d, v.size() * sizeof(T)));
   h->sec_bufs.push_back(d);
   HIPCHK(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
   *dst = reinterpret_cast<const T*>(d);
@@ -2349,11 +2516,15 @@ struct aqc_batch {
     int max_tb = 0;
     std::vector<int> part;     // participating slots, in argument order
     std::vector<int2> map;     // block -> (participant, local block)
-    int2* dmap = nullptr;
-    size_t dmap_cap = 0;
+    int2* dmap = nullptr;      // this level's part of dmaps
     size_t arg_off = 0;        // byte offset of this level's arguments
   };
   std::vector<Level> levels;
+  // the block maps of all levels, kept across rebuilds and only ever grown:
+  // freeing device memory waits for every stream of the device, and a batch
+  // rebuilds at every admission and retirement
+  int2* dmaps = nullptr;
+  size_t dmaps_cap = 0;        // int2 elements
   bool dirty = true;
   size_t args_bytes = 0;
   char* hargs[2] = {nullptr, nullptr};  // pinned
@@ -2425,6 +2596,8 @@ extern "C" aqc_status aqc_batch_create(aqc_ctx* ctx, int dtype, int capacity, aq
   HIPCHK(hipStreamCreateWithFlags(&b->bs, hipStreamNonBlocking));
   HIPCHK(hipStreamCreateWithFlags(&b->rs, hipStreamNonBlocking));
   HIPCHK(hipEventCreateWithFlags(&b->rs_ev, hipEventDisableTiming));
+  tab_stream_add(ctx->device, b->bs);
+  tab_stream_add(ctx->device, b->rs);
   ctx->refs.fetch_add(1, std::memory_order_relaxed);  // released by aqc_batch_destroy
   *out = b.release();
   return AQC_OK;
@@ -2449,10 +2622,11 @@ extern "C" aqc_status aqc_batch_destroy(aqc_batch* b) {
     if (L.done) hipEventDestroy(L.done);
   }
   if (b->rs_ev) hipEventDestroy(b->rs_ev);
+  tab_stream_remove(b->ctx->device, b->bs);
+  tab_stream_remove(b->ctx->device, b->rs);
   if (b->rs) hipStreamDestroy(b->rs);
   batch_drop_graphs(b);
-  for (auto& L : b->levels)
-    if (L.dmap) hipFree(L.dmap);
+  if (b->dmaps) hipFree(b->dmaps);
   for (int i = 0; i < 2; ++i) {
     if (b->hargs[i]) hipHostFree(b->hargs[i]);
     if (b->ev[i]) hipEventDestroy(b->ev[i]);
@@ -2564,14 +2738,11 @@ extern "C" aqc_status aqc_batch_admit(aqc_batch* b, const aqc_ham* h, void* psi,
 
 // Rebuild the launch levels and their block maps for the active slots.
 static aqc_status batch_rebuild(aqc_batch* b) {
-  for (auto& L : b->levels)
-    if (L.dmap) {
-      HIPCHK(hipStreamSynchronize(b->ctx->stream));
-      HIPCHK(hipStreamSynchronize(b->bs));
-      break;
-    }
-  for (auto& L : b->levels)
-    if (L.dmap) hipFree(L.dmap);
+  // the previous launches read the block maps (and their host copies)
+  if (b->dmaps) {
+    HIPCHK(hipStreamSynchronize(b->ctx->stream));
+    HIPCHK(hipStreamSynchronize(b->bs));
+  }
   b->levels.clear();
   batch_drop_graphs(b);
   int maxr = 0, maxw = 0, maxl = 0;
@@ -2619,13 +2790,27 @@ static aqc_status batch_rebuild(aqc_batch* b) {
   for (int r = 0; r < maxw; ++r) add_level(3, r);
   for (int l = 0; l < maxl; ++l) add_level(0, l);
   add_level(2, 0);
-  size_t off = 0;
+  size_t off = 0, moff = 0;
   for (auto& L : b->levels) {
     L.arg_off = off;
     off += L.part.size() * (is_reg_level(L.kind) ? sizeof(RegPassArgs) : sizeof(PassArgs));
     off = (off + 255) & ~(size_t)255;
     if (L.map.size() >= (size_t)INT32_MAX) return fail(AQC_ENOTSUP, "batch too large");
-    HIPCHK(hipMalloc(&L.dmap, L.map.size() * sizeof(int2)));
+    moff += (L.map.size() + 31) & ~(size_t)31;   // 256-byte aligned parts
+  }
+  if (moff > b->dmaps_cap) {
+    // (nothing reads the old maps any more: see above)
+    if (b->dmaps) HIPCHK(hipFree(b->dmaps));
+    b->dmaps = nullptr;
+    b->dmaps_cap = 0;
+    const size_t cap = moff + moff / 2;
+    HIPCHK(hipMalloc(&b->dmaps, cap * sizeof(int2)));
+    b->dmaps_cap = cap;
+  }
+  moff = 0;
+  for (auto& L : b->levels) {
+    L.dmap = b->dmaps + moff;
+    moff += (L.map.size() + 31) & ~(size_t)31;
     // ordered before the batch's launches; L.map outlives the copy (the next
     // rebuild synchronises the stream first)
     HIPCHK(hipMemcpyAsync(L.dmap, L.map.data(), L.map.size() * sizeof(int2), hipMemcpyHostToDevice,

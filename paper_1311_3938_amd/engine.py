@@ -58,6 +58,11 @@ class Context:
             pass
 
 
+def trim(device: int = 0):
+    """Free the kept device buffers of released Hamiltonian tables (aqc_trim)."""
+    check(lib().aqc_trim(int(device)))
+
+
 class Hamiltonian:
     """Compiled form of an ``instances.Instance`` (terms, schedules, path)."""
 

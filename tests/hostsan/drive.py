@@ -304,8 +304,19 @@ def main():
     S = tsearch.search_rounds(ctx, insts, [I.plus_state(8)] * 4, tsearch.energies, T_max=64.0,
                               plan=lambda ham, T: (int(8 + T), 0.5))
     assert all(len(s.evals) == 7 for s in S)
+    # a table buffer released while a batch lives (its release is marked on
+    # the batch's streams), reused once the batch and its streams are gone
+    b = engine.Batch(ctx, torch.complex64, capacity=2)
+    h = engine.Hamiltonian(ctx, I.workload_batch_member(0, 10, 14))
+    h.free()
+    b.close()
+    h = engine.Hamiltonian(ctx, I.workload_batch_member(0, 10, 14))
+    h.free()
     context_outlived_by_batch()
     ctx.close()
+    # released table buffers are kept for reuse until trimmed
+    assert lib().aqc_trim(64) == L.AQC_EINVAL
+    engine.trim(0)
     live = lib().fake_hip_live() - base
     assert live == 0, f"{live} runtime handles left alive"
     print("host paths done", flush=True)

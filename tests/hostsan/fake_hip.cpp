@@ -19,6 +19,10 @@ static std::recursive_mutex g_mu;
 
 static std::map<void*, size_t> g_dev, g_host;
 static std::set<void*> g_obj;
+// the stream each event was last recorded on, and the events whose stream has
+// since been destroyed: the library never waits on or queries those
+static std::map<void*, void*> g_ev_stream;
+static std::set<void*> g_ev_orphan;
 static void die(const char* what, void* p) { FAKE_LOCK;
   fprintf(stderr, "fake_hip: %s %p\n", what, p);
   abort();
@@ -45,11 +49,27 @@ hipError_t hipDeviceGetAttribute(int* pi, hipDeviceAttribute_t, int) { FAKE_LOCK
 hipError_t hipDeviceSynchronize(void) { FAKE_LOCK; return hipSuccess; }
 hipError_t hipEventCreate(hipEvent_t* e) { FAKE_LOCK; *e = (hipEvent_t)newobj(); return hipSuccess; }
 hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { FAKE_LOCK; *e = (hipEvent_t)newobj(); return hipSuccess; }
-hipError_t hipEventDestroy(hipEvent_t e) { FAKE_LOCK; delobj((void*)e, "event destroy"); return hipSuccess; }
+hipError_t hipEventDestroy(hipEvent_t e) { FAKE_LOCK;
+  g_ev_stream.erase((void*)e);
+  g_ev_orphan.erase((void*)e);
+  delobj((void*)e, "event destroy");
+  return hipSuccess;
+}
 hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) { FAKE_LOCK; *ms = 1.0f; return hipSuccess; }
-hipError_t hipEventRecord(hipEvent_t e, hipStream_t) { FAKE_LOCK; if (!g_obj.count((void*)e)) die("event record", (void*)e); return hipSuccess; }
-hipError_t hipEventQuery(hipEvent_t e) { FAKE_LOCK; if (!g_obj.count((void*)e)) die("event query", (void*)e); return hipSuccess; }
-hipError_t hipEventSynchronize(hipEvent_t e) { FAKE_LOCK; if (!g_obj.count((void*)e)) die("event sync", (void*)e); return hipSuccess; }
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t s) { FAKE_LOCK;
+  if (!g_obj.count((void*)e)) die("event record", (void*)e);
+  if (s && !g_obj.count((void*)s)) die("event record on unknown stream", (void*)s);
+  g_ev_stream[(void*)e] = (void*)s;
+  g_ev_orphan.erase((void*)e);
+  return hipSuccess;
+}
+static void live_event(hipEvent_t e, const char* what) {
+  if (!g_obj.count((void*)e)) die(what, (void*)e);
+  if (g_ev_orphan.count((void*)e)) die("event used after the stream it was recorded on was destroyed", (void*)e);
+}
+hipError_t hipEventQuery(hipEvent_t e) { FAKE_LOCK; live_event(e, "event query"); return hipSuccess; }
+hipError_t hipEventSynchronize(hipEvent_t e) { FAKE_LOCK; live_event(e, "event sync"); return hipSuccess; }
+hipError_t hipGetLastError(void) { FAKE_LOCK; return hipSuccess; }
 hipError_t hipFree(void* p) { FAKE_LOCK;
   if (!p) return hipSuccess;
   auto it = g_dev.find(p);
@@ -59,6 +79,7 @@ hipError_t hipFree(void* p) { FAKE_LOCK;
   return hipSuccess;
 }
 hipError_t hipGetDeviceCount(int* c) { FAKE_LOCK; *c = 1; return hipSuccess; }
+hipError_t hipGetDevice(int* d) { FAKE_LOCK; *d = 0; return hipSuccess; }
 const char* hipGetErrorString(hipError_t) { FAKE_LOCK; return "fake error"; }
 hipError_t hipGraphAddMemcpyNode1D(hipGraphNode_t* nd, hipGraph_t g, const hipGraphNode_t*, size_t, void* dst,
                                    const void* src, size_t count, hipMemcpyKind) {
@@ -97,9 +118,14 @@ hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) { FAKE_LOC
 hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t) { FAKE_LOCK; memcpy(d, s, n); return hipSuccess; }
 hipError_t hipSetDevice(int) { FAKE_LOCK; return hipSuccess; }
 hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) { FAKE_LOCK; *s = (hipStream_t)newobj(); return hipSuccess; }
-hipError_t hipStreamDestroy(hipStream_t s) { FAKE_LOCK; delobj((void*)s, "stream destroy"); return hipSuccess; }
+hipError_t hipStreamDestroy(hipStream_t s) { FAKE_LOCK;
+  for (auto& kv : g_ev_stream)
+    if (kv.second == (void*)s) g_ev_orphan.insert(kv.first);
+  delobj((void*)s, "stream destroy");
+  return hipSuccess;
+}
 hipError_t hipStreamSynchronize(hipStream_t s) { FAKE_LOCK; if (s && !g_obj.count((void*)s)) die("stream sync", (void*)s); return hipSuccess; }
-hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t e, unsigned) { FAKE_LOCK; if (!g_obj.count((void*)e)) die("wait event", (void*)e); return hipSuccess; }
+hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t e, unsigned) { FAKE_LOCK; live_event(e, "wait event"); return hipSuccess; }
 }
 
 // every byte range a launcher is handed must lie in a live allocation
