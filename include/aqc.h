@@ -354,7 +354,11 @@ aqc_status aqc_overlap_len(aqc_ctx* ctx, const void* phi, const void* psi, int d
  * exactly over the terms' Z bits, at most 16 besides the pair, else
  * AQC_ENOTSUP).  n <= 34, at most 600 flip pairs and 1024 pair terms
  * (AQC_ENOTSUP).
- * Device tables: a few tens of KB, allocated here.                          */
+ * Device tables: a few tens of KB, allocated here.  When the diagonal terms
+ * use at most two schedules and 8 C(n, w) bytes per schedule come to at most
+ * 16 GiB, the diagonal is also kept per state, split by schedule (float64,
+ * computed here on the context's stream, which is synchronised): products
+ * then read it instead of summing the terms per state.                     */
 aqc_status aqc_sector_create(aqc_ctx* ctx, const aqc_ham* ham, int weight, aqc_ham** out);
 /* amplitudes of a state of `ham`: 2^n, or C(n, w) for a sector            */
 int64_t aqc_ham_dim(const aqc_ham* ham);

@@ -1443,6 +1443,17 @@ static aqc_status diag_minmax(aqc_ctx* ctx, const aqc_ham* h, const Plan& p, con
   return AQC_OK;
 }
 
+// the arguments of a sector kernel for schedule values f and constant dconst
+static SectorArgs sector_args(const aqc_ham* h, const double* f, double dconst) {
+  SectorArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.s = h->sd;
+  for (int i = 0; i < kMaxSched; ++i) a.f[i] = f[i];
+  a.dconst = dconst;
+  for (int k = 0; k < h->sd.dstore; ++k) a.dstore_f[k] = f[h->sd.dstore_sid[k]];
+  return a;
+}
+
 extern "C" aqc_status aqc_ground_mass(aqc_ctx* ctx, const aqc_ham* h, double t, const void* psi,
                                       int dtype, double rel_tol, double* mass, double* e_min) {
   STCHK(check_common(ctx, h, dtype));
@@ -1456,11 +1467,7 @@ extern "C" aqc_status aqc_ground_mass(aqc_ctx* ctx, const aqc_ham* h, double t, 
   STCHK(diag_minmax(ctx, h, p, c.f, c.ident, &mn, &mx));
   const double thr = mn + rel_tol * std::max(1.0, std::fabs(mn));
   if (h->sector_w >= 0) {
-    SectorArgs sa;
-    std::memset(&sa, 0, sizeof(sa));
-    sa.s = h->sd;
-    for (int i = 0; i < kMaxSched; ++i) sa.f[i] = c.f[i];
-    sa.dconst = c.ident;
+    const SectorArgs sa = sector_args(h, c.f, c.ident);
     const int64_t nb = sector_blocks(h->dim);
     STCHK(ensure_parts(ctx, (size_t)nb));
     HIPCHK(launch_sector_diag(sa, 1, thr, psi, dtype, ctx->parts, ctx->stream));
@@ -1734,6 +1741,36 @@ extern "C" aqc_status aqc_sector_create(aqc_ctx* ctx, const aqc_ham* src, int we
   STCHK(sector_upload(h.get(), masks, &sd.masks));
   STCHK(sector_upload(h.get(), mterms, &sd.mterms));
   STCHK(sector_upload(h.get(), res, &sd.res));
+  // the diagonal is linear in the schedule values: with few schedules it is
+  // kept per state, one part per schedule (each the diagonal with that
+  // schedule at 1 and the others at 0), so that a product reads it instead
+  // of summing the terms again
+  std::vector<int> dsid;
+  for (const HTerm& t : src->diag)
+    if (std::find(dsid.begin(), dsid.end(), t.sid) == dsid.end()) dsid.push_back(t.sid);
+  std::sort(dsid.begin(), dsid.end());
+  sd.dstore = -1;
+  sd.dtab = nullptr;
+  if (dsid.size() <= (size_t)kSecDiagStore &&
+      (double)dsid.size() * (double)h->dim * sizeof(double) <= (double)kSecDiagStoreBytes) {
+    sd.dstore = (int32_t)dsid.size();
+    for (size_t k = 0; k < dsid.size(); ++k) sd.dstore_sid[k] = dsid[k];
+    if (!dsid.empty()) {
+      void* d = nullptr;
+      STCHK(tab_alloc(&d, dsid.size() * (size_t)h->dim * sizeof(double)));
+      h->sec_bufs.push_back(d);
+      double* dt = reinterpret_cast<double*>(d);
+      for (size_t k = 0; k < dsid.size(); ++k) {
+        SectorArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.s = sd;
+        a.f[dsid[k]] = 1.0;
+        HIPCHK(launch_sector_dtab(a, dt + k * (size_t)h->dim, ctx->stream));
+      }
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      sd.dtab = dt;
+    }
+  }
   // a sector's plan is one kernel per product and needs no tables
   STCHK(build_plan(h.get(), 0, ctx->stream));
   STCHK(build_plan(h.get(), 1, ctx->stream));
@@ -1747,13 +1784,9 @@ extern "C" int aqc_ham_sector_weight(const aqc_ham* h) { return h ? h->sector_w 
 
 static aqc_status run_sector_matvec(aqc_ctx* ctx, const aqc_ham* h, int dtype, double t,
                                     double shift, const void* u, const EpiDesc& epi) {
-  SectorArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.s = h->sd;
-  a.src = u;
   const Coefs c = coefs_at(h, t);
-  for (int i = 0; i < kMaxSched; ++i) a.f[i] = c.f[i];
-  a.dconst = c.ident - shift;
+  SectorArgs a = sector_args(h, c.f, c.ident - shift);
+  a.src = u;
   a.epi = epi;
   if (ctx->prof_on) {
     aqc_ctx::Rec r;
@@ -1768,7 +1801,9 @@ static aqc_status run_sector_matvec(aqc_ctx* ctx, const aqc_ham* h, int dtype, d
     for (int i = 0; i < 4; ++i) nvec += epi.in[i] ? 1 : 0;
     for (int i = 0; i < 3; ++i) nvec += epi.out[i] ? 1 : 0;
     const int nlo = epi.comp ? ((epi.comp_flags & 8) ? 2 : 1) : 0;
-    ctx->prof_bytes[r.kind] += ((double)nvec * (dtype == 0 ? 8.0 : 16.0) + 4.0 * nlo) * (double)h->dim;
+    const int ndiag = std::max(0, (int)h->sd.dstore);   // stored diagonal parts, float64
+    ctx->prof_bytes[r.kind] +=
+        ((double)nvec * (dtype == 0 ? 8.0 : 16.0) + 4.0 * nlo + 8.0 * ndiag) * (double)h->dim;
     if (ctx->prof_pending.size() >= 4096) STCHK(prof_drain(ctx));
     return AQC_OK;
   }
@@ -1778,11 +1813,7 @@ static aqc_status run_sector_matvec(aqc_ctx* ctx, const aqc_ham* h, int dtype, d
 
 static aqc_status sector_diag_minmax(aqc_ctx* ctx, const aqc_ham* h, const double* f,
                                      double dconst, double* mn, double* mx) {
-  SectorArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.s = h->sd;
-  for (int i = 0; i < kMaxSched; ++i) a.f[i] = f[i];
-  a.dconst = dconst;
+  const SectorArgs a = sector_args(h, f, dconst);
   const int64_t nb = sector_blocks(h->dim);
   STCHK(ensure_parts(ctx, 2 * (size_t)nb));
   HIPCHK(launch_sector_diag(a, 0, 0.0, nullptr, 1, ctx->parts, ctx->stream));

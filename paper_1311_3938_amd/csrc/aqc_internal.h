@@ -156,6 +156,11 @@ struct SecHop {
                    // run's length, the others 0
 };
 constexpr int kSecMaxHops = 600;
+// A sector whose diagonal terms use at most this many schedules keeps its
+// diagonal per state, split by schedule, when that takes at most
+// kSecDiagStoreBytes of device memory.
+constexpr int kSecDiagStore = 2;
+constexpr size_t kSecDiagStoreBytes = size_t(16) << 30;
 // The diagonal terms sharing one mask of one or two bits (q < 0: one bit p).
 struct SecMask {
   int32_t p, q;
@@ -179,12 +184,18 @@ struct SectorDev {
   const SecMask* masks;
   const DevTerm* mterms;
   const DevTerm* res;      // diagonal terms with three or more bits
+  // the diagonal kept per state: -1 not kept (summed from the terms per
+  // state), else the number of schedules of the diagonal terms (0: none)
+  int32_t dstore;
+  int32_t dstore_sid[kSecDiagStore];
+  const double* dtab;      // [dstore][dim]: the part under schedule dstore_sid[k]
 };
 struct SectorArgs {
   SectorDev s;
   const void* src;
   double f[kMaxSched];
   double dconst;       // identity terms minus the shift
+  double dstore_f[kSecDiagStore];   // f[dstore_sid[k]]
   EpiDesc epi;
 };
 
@@ -490,6 +501,9 @@ hipError_t launch_zero(void* dst, size_t bytes, hipStream_t s);
 // reductions into a.epi.red over sector_blocks() blocks
 int64_t sector_blocks(int64_t dim);
 hipError_t launch_sector_matvec(const SectorArgs& a, int dtype, hipStream_t s);
+// out[r] = the diagonal at the state of rank r for the coefficients of `a`
+// (used with one schedule set to 1, the others 0, and dconst 0)
+hipError_t launch_sector_dtab(const SectorArgs& a, double* out, hipStream_t s);
 // sector diagonal: mode 0 per-block min and max -> parts[2][nb]; mode 1
 // mass of psi where the diagonal is <= thr -> parts[nb]
 hipError_t launch_sector_diag(const SectorArgs& a, int mode, double thr, const void* psi, int dtype,

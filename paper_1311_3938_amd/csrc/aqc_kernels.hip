@@ -1647,7 +1647,9 @@ __device__ __forceinline__ void sector_group(const SectorDev& s, const uint32_t*
 
 // five waves per SIMD where the registers allow it (complex64, 32-bit
 // states), four otherwise, so that nothing spills
-template <typename R, typename W>
+// DS: the diagonal is read from the sector's per-schedule parts (dstore >= 0)
+// instead of summed from the terms
+template <typename R, typename W, bool DS>
 __global__ __launch_bounds__(kSecThreads) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && sizeof(W) == 4 ? 5 : 4)))
 void k_sector(const SectorArgs a) {
   using V = typename CT2<R>::V;
@@ -1716,7 +1718,15 @@ void k_sector(const SectorArgs a) {
       if (!ok[u]) continue;
       const int64_t g = rf + u;
       const V uq = src[g];
-      const double d = sector_diag<W>(a, L, zs[u]);
+      double d;
+      if constexpr (DS) {
+        d = a.dconst;
+#pragma unroll
+        for (int k = 0; k < kSecDiagStore; ++k)
+          if (k < s.dstore) d += a.dstore_f[k] * __builtin_nontemporal_load(s.dtab + k * s.dim + g);
+      } else {
+        d = sector_diag<W>(a, L, zs[u]);
+      }
       const R hrr = (R)(d * (double)uq.x + (double)hr[u]);
       const R hii = (R)(d * (double)uq.y + (double)hi[u]);
       V xin[4];
@@ -1788,10 +1798,14 @@ static hipError_t set_sector_lds_attr() {
   big.nhops = kSecMaxHops;
   big.nhterms = kSecMaxHopTerms;
   const int dyn = (int)sector_dyn_lds_bytes(big, 1);
-  const void* fns[4] = {reinterpret_cast<const void*>(&k_sector<float, uint32_t>),
-                        reinterpret_cast<const void*>(&k_sector<float, uint64_t>),
-                        reinterpret_cast<const void*>(&k_sector<double, uint32_t>),
-                        reinterpret_cast<const void*>(&k_sector<double, uint64_t>)};
+  const void* fns[8] = {reinterpret_cast<const void*>(&k_sector<float, uint32_t, false>),
+                        reinterpret_cast<const void*>(&k_sector<float, uint64_t, false>),
+                        reinterpret_cast<const void*>(&k_sector<double, uint32_t, false>),
+                        reinterpret_cast<const void*>(&k_sector<double, uint64_t, false>),
+                        reinterpret_cast<const void*>(&k_sector<float, uint32_t, true>),
+                        reinterpret_cast<const void*>(&k_sector<float, uint64_t, true>),
+                        reinterpret_cast<const void*>(&k_sector<double, uint32_t, true>),
+                        reinterpret_cast<const void*>(&k_sector<double, uint64_t, true>)};
   for (const void* f : fns) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     if (e != hipSuccess) return e;
@@ -1806,15 +1820,49 @@ hipError_t launch_sector_matvec(const SectorArgs& a, int dtype, hipStream_t s) {
     return hipErrorInvalidValue;
   const dim3 grid((unsigned)sector_blocks(a.s.dim)), block(kSecThreads);
   const size_t dyn = sector_dyn_lds_bytes(a.s, dtype);
+  if (a.s.dstore > kSecDiagStore || (a.s.dstore > 0 && !a.s.dtab)) return hipErrorInvalidValue;
   // states of at most 32 qubits fit a 32-bit word
   const bool w32 = a.s.n <= 32;
+  const bool ds = a.s.dstore >= 0;
   if (dtype == 0) {
-    if (w32) hipLaunchKernelGGL((k_sector<float, uint32_t>), grid, block, dyn, s, a);
-    else hipLaunchKernelGGL((k_sector<float, uint64_t>), grid, block, dyn, s, a);
+    if (w32) {
+      if (ds) hipLaunchKernelGGL((k_sector<float, uint32_t, true>), grid, block, dyn, s, a);
+      else hipLaunchKernelGGL((k_sector<float, uint32_t, false>), grid, block, dyn, s, a);
+    } else {
+      if (ds) hipLaunchKernelGGL((k_sector<float, uint64_t, true>), grid, block, dyn, s, a);
+      else hipLaunchKernelGGL((k_sector<float, uint64_t, false>), grid, block, dyn, s, a);
+    }
   } else {
-    if (w32) hipLaunchKernelGGL((k_sector<double, uint32_t>), grid, block, dyn, s, a);
-    else hipLaunchKernelGGL((k_sector<double, uint64_t>), grid, block, dyn, s, a);
+    if (w32) {
+      if (ds) hipLaunchKernelGGL((k_sector<double, uint32_t, true>), grid, block, dyn, s, a);
+      else hipLaunchKernelGGL((k_sector<double, uint32_t, false>), grid, block, dyn, s, a);
+    } else {
+      if (ds) hipLaunchKernelGGL((k_sector<double, uint64_t, true>), grid, block, dyn, s, a);
+      else hipLaunchKernelGGL((k_sector<double, uint64_t, false>), grid, block, dyn, s, a);
+    }
   }
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kSecThreads) void k_sector_dtab(const SectorArgs a, double* out) {
+  __shared__ SecLds L;
+  sector_setup(a, L);
+  const SectorDev& s = a.s;
+  const int64_t per = (int64_t)kSecThreads * kSecEPT;
+  for (int64_t base = (int64_t)blockIdx.x * per; base < s.dim; base += (int64_t)gridDim.x * per) {
+    const int64_t rf = base + (int64_t)threadIdx.x * kSecEPT;
+    if (rf >= s.dim) continue;
+    uint64_t z = sector_unrank(L.binom, s.n, s.w, rf);
+    for (int u = 0; u < kSecEPT && rf + u < s.dim; ++u) {
+      if (u > 0) z = next_same_weight(z);
+      out[rf + u] = sector_diag(a, L, z);
+    }
+  }
+}
+
+hipError_t launch_sector_dtab(const SectorArgs& a, double* out, hipStream_t s) {
+  const dim3 grid((unsigned)sector_blocks(a.s.dim)), block(kSecThreads);
+  hipLaunchKernelGGL(k_sector_dtab, grid, block, 0, s, a, out);
   return hipGetLastError();
 }
 

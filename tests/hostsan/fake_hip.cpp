@@ -212,7 +212,14 @@ hipError_t launch_scale(void*, int, int64_t, double, double, hipStream_t) { FAKE
 hipError_t launch_copy(void*, const void*, int, int64_t, hipStream_t) { FAKE_LOCK; return hipSuccess; }
 hipError_t launch_zero(void* d, size_t n, hipStream_t) { FAKE_LOCK; need(d, n, "zero"); memset(d, 0, n); return hipSuccess; }
 int64_t sector_blocks(int64_t dim) { FAKE_LOCK; return (dim + 1023) / 1024; }
-hipError_t launch_sector_matvec(const SectorArgs&, int, hipStream_t) { FAKE_LOCK; return hipSuccess; }
+hipError_t launch_sector_matvec(const SectorArgs& a, int, hipStream_t) { FAKE_LOCK;
+  if (a.s.dstore > 0) need(a.s.dtab, (size_t)a.s.dstore * (size_t)a.s.dim * sizeof(double), "sector diagonal parts");
+  return hipSuccess;
+}
+hipError_t launch_sector_dtab(const SectorArgs& a, double* out, hipStream_t) { FAKE_LOCK;
+  need(out, (size_t)a.s.dim * sizeof(double), "sector diagonal part");
+  return hipSuccess;
+}
 hipError_t launch_sector_diag(const SectorArgs&, int, double, const void*, int, double*, hipStream_t) { FAKE_LOCK; return hipSuccess; }
 hipError_t launch_sector_expand(const SectorDev&, const void*, void*, int, hipStream_t) { FAKE_LOCK; return hipSuccess; }
 hipError_t launch_fill(void*, int, int64_t, double, double, hipStream_t) { FAKE_LOCK; return hipSuccess; }

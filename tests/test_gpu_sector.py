@@ -71,6 +71,46 @@ def test_sector_apply(eng, n, w, dt):
     ham.free()
 
 
+def _diag_forms(n, seed, form):
+    """The Hamiltonian of _mixed with its diagonal spread over 0 schedules (no
+    diagonal terms at all), 2 schedules or 3 schedules: a sector keeps its
+    diagonal per state for up to two schedules and sums it from the terms for
+    more, and both forms must give the oracle's product."""
+    if form == "none":
+        rng = np.random.default_rng(seed)
+        clauses = I.ec3_random_clauses(n, max(3, (4 * n) // 5), rng)
+        return I.xy_initial_terms(n, clauses).instance([I.SCHED_CONST], I.linear_path(2.0))
+    inst = _mixed(n, seed)
+    t = I.TermList(n)
+    for x, z, w, sid in zip(inst.x, inst.z, inst.w, inst.sid):
+        t.add_masks(int(x), int(z), float(w), int(sid))
+    t.add({2: "Z", 5: "Z"}, 0.3, 2)                  # a diagonal term under the trig schedule
+    if form == "three":
+        t.add({3: "Z"}, -0.4, 0)                     # and one under 1 - s
+    return t.instance(inst.scheds, inst.path)
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("form", ["none", "two", "three"])
+@pytest.mark.parametrize("n,w", [(14, 5), (16, 8)])
+def test_sector_apply_diagonal_forms(eng, n, w, form, dt):
+    engine, ctx = eng
+    import torch
+    inst = _diag_forms(n, 20 + n, form)
+    ham = engine.Hamiltonian(ctx, inst)
+    sec = engine.Sector(ctx, ham, w)
+    rng = np.random.default_rng(w + 1)
+    v = rng.normal(size=sec.dim) + 1j * rng.normal(size=sec.dim)
+    dv = to_dev(v, dt)
+    out = torch.empty_like(dv)
+    tol = 1e-12 if dt == "c128" else 5e-6
+    for t in (0.0, 0.55, 1.3, 2.0):
+        engine.apply(ctx, sec, t, dv, out)
+        assert rel_err(to_host(out), subspace.apply_h(inst, t, v, w)) < tol, t
+    sec.free()
+    ham.free()
+
+
 def test_sector_dicke_expand_energy_mass(eng):
     engine, ctx = eng
     import torch
