@@ -1492,6 +1492,14 @@ __host__ __device__ __forceinline__ size_t sector_rtab_lds_bytes(const SectorDev
   return ((size_t)sd.rwords * sizeof(uint32_t) + 15) & ~(size_t)15;
 }
 
+// A hop's gathered partners and coefficients, added to the product one hop
+// that needs partners later
+template <typename R>
+struct SecPend {
+  typename CT2<R>::V v[kSecEPT];
+  R cr[kSecEPT], ci[kSecEPT];
+};
+
 // hr + i hi += (cr + i ci) * pv for each state
 template <typename R>
 __device__ __forceinline__ void sector_hop_fma(R (&hr)[kSecEPT], R (&hi)[kSecEPT], const typename CT2<R>::V (&pv)[kSecEPT],
@@ -1514,17 +1522,23 @@ __device__ __forceinline__ void sector_hop_fma(R (&hr)[kSecEPT], R (&hi)[kSecEPT
 //   r + T_ca[k_a][np_a] - T_ca[k_a][nz_a] + M(+-1) + T_cb[k_b +- 1][np_b] - T_cb[k_b][nz_b]
 // where only the two partner patterns depend on the hop: everything else is
 // computed once per run and state.  Every lane runs the same instructions
-// whether or not its states' bits differ; only the gathers are masked, and a
-// hop that no state of the wave needs is skipped.  A hop's term is added one
-// hop later (qv, qr, qi hold it), so that its gathers overlap the next hop's
-// rank arithmetic.
+// whether or not its states' bits differ: a lane whose state has no partner
+// gathers its own state (in bounds, and in the lines the stage update reads
+// anyway) with coefficient zero, and a hop that no state of the wave needs is
+// skipped.  A hop's term is added one hop later, from one of two buffers
+// taken in turn (pa, pb; par names the next one to fill), so that its gathers
+// overlap the next hop's rank arithmetic.  (With a single buffer, the compiler
+// copied each gathered value into it at the end of the hop, which waits for
+// the gathers there.  With two it still copies those gathered into pb, not
+// knowing that the buffers alternate: half of the hops overlap.)
 template <typename R, typename W>
 __device__ __forceinline__ void sector_group(const SectorDev& s, const uint32_t* rtab, const uint32_t* hrec,
                                              int g0, int gn, const W (&zs)[kSecEPT], const bool (&ok)[kSecEPT],
                                              uint32_t r0, uint32_t last, const R* hc, const R* tm,
                                              const typename CT2<R>::V* __restrict__ src,
-                                             R (&hr)[kSecEPT], R (&hi)[kSecEPT], typename CT2<R>::V (&qv)[kSecEPT],
-                                             R (&qr)[kSecEPT], R (&qi)[kSecEPT]) {
+                                             const typename CT2<R>::V* __restrict__ srcb,
+                                             R (&hr)[kSecEPT], R (&hi)[kSecEPT], SecPend<R>& pa, SecPend<R>& pb,
+                                             int& par) {
   using V = typename CT2<R>::V;
   constexpr uint32_t CW = 1u << kSecChunkBits;     // words per table row
   const uint32_t rec0 = __builtin_amdgcn_readfirstlane(hrec[g0]);
@@ -1597,13 +1611,10 @@ __device__ __forceinline__ void sector_group(const SectorDev& s, const uint32_t*
         rp[u] = (z1[u] ? cm[u] : cp[u]) + rtab[ra[u] + (na[u] ^ fa)] + rtab[rbp + (nb[u] ^ fb)];
       }
     }
-    V pv[kSecEPT];
+    // a weight-w state has a rank below dim; the clamp only guards the read
+    uint32_t gi[kSecEPT];
 #pragma unroll
-    for (int u = 0; u < kSecEPT; ++u) {
-      // a weight-w state has a rank below dim; the clamp only guards the read
-      pv[u] = V{0, 0};
-      if (act[u]) pv[u] = src[min(rp[u], last)];
-    }
+    for (int u = 0; u < kSecEPT; ++u) gi[u] = act[u] ? min(rp[u], last) : min(r0 + (uint32_t)u, last);
     R cr[kSecEPT], ci[kSecEPT];
     if (fast) {
       // the coefficient depends only on the partner's bit bi (= 1 - z_bi)
@@ -1634,14 +1645,31 @@ __device__ __forceinline__ void sector_group(const SectorDev& s, const uint32_t*
         }
       }
     }
-    // the previous hop's term, whose gathers have had this hop's work to land
-    sector_hop_fma<R>(hr, hi, qv, qr, qi);
 #pragma unroll
     for (int u = 0; u < kSecEPT; ++u) {
-      qv[u] = pv[u];
-      qr[u] = cr[u];
-      qi[u] = ci[u];
+      cr[u] = act[u] ? cr[u] : R(0);
+      ci[u] = act[u] ? ci[u] : R(0);
     }
+    // gather into one buffer, then add the previous hop's term from the other,
+    // whose gathers have had this hop's work to land
+    if (par == 0) {
+#pragma unroll
+      for (int u = 0; u < kSecEPT; ++u) {
+        pa.v[u] = src[gi[u]];
+        pa.cr[u] = cr[u];
+        pa.ci[u] = ci[u];
+      }
+      sector_hop_fma<R>(hr, hi, pb.v, pb.cr, pb.ci);
+    } else {
+#pragma unroll
+      for (int u = 0; u < kSecEPT; ++u) {
+        pb.v[u] = srcb[gi[u]];
+        pb.cr[u] = cr[u];
+        pb.ci[u] = ci[u];
+      }
+      sector_hop_fma<R>(hr, hi, pa.v, pa.cr, pa.ci);
+    }
+    par ^= 1;
   }
 }
 
@@ -1676,6 +1704,12 @@ void k_sector(const SectorArgs a) {
   sector_hop_setup<R>(s, L, tm, hc);
   __syncthreads();
   const V* __restrict__ src = reinterpret_cast<const V*>(a.src);
+  // the same address, opaque to the compiler: the two pending buffers gather
+  // through different pointers, so that their loads stay apart (merged into
+  // one load, each would be copied into its buffer, waiting for the gather)
+  const __attribute__((address_space(1))) V* srcg = (const __attribute__((address_space(1))) V*)src;
+  asm("" : "+s"(srcg));
+  const V* srcb = (const V*)srcg;
   const EpiDesc& e = a.epi;
   const bool has_comp = e.comp != nullptr;
   uint32_t* __restrict__ compv = reinterpret_cast<uint32_t*>(e.comp);
@@ -1697,21 +1731,26 @@ void k_sector(const SectorArgs a) {
         if (u + 1 < kSecEPT && rf + u + 1 < s.dim) z = next_same_weight(z);
       }
     }
-    R hr[kSecEPT], hi[kSecEPT], qr[kSecEPT], qi[kSecEPT];
-    V qv[kSecEPT];
+    R hr[kSecEPT], hi[kSecEPT];
+    SecPend<R> pa, pb;
+    int par = 0;
 #pragma unroll
     for (int u = 0; u < kSecEPT; ++u) {
-      hr[u] = hi[u] = qr[u] = qi[u] = 0;
-      qv[u] = V{0, 0};
+      hr[u] = hi[u] = 0;
+      pa.cr[u] = pa.ci[u] = pb.cr[u] = pb.ci[u] = 0;
+      pa.v[u] = pb.v[u] = V{0, 0};
     }
     for (int g0 = 0; g0 < s.nhops;) {
       // the run length (host-built) is at least 1 and ends at the last hop; the
       // clamps keep the loop finite and the reads inside the hop table
       const int gn = min(s.nhops - g0, max(1, (int)(__builtin_amdgcn_readfirstlane(hrec[g0]) >> 19)));
-      sector_group<R, W>(s, rtab, hrec, g0, gn, zs, ok, (uint32_t)rf, last, hc, tm, src, hr, hi, qv, qr, qi);
+      sector_group<R, W>(s, rtab, hrec, g0, gn, zs, ok, (uint32_t)rf, last, hc, tm, src, srcb, hr, hi, pa, pb,
+                         par);
       g0 += gn;
     }
-    sector_hop_fma<R>(hr, hi, qv, qr, qi);
+    // the last filled buffer
+    if (par) sector_hop_fma<R>(hr, hi, pa.v, pa.cr, pa.ci);
+    else sector_hop_fma<R>(hr, hi, pb.v, pb.cr, pb.ci);
     // epilogue: the same update as the last tile pass (see EpiDesc)
 #pragma unroll
     for (int u = 0; u < kSecEPT; ++u) {
