@@ -561,29 +561,26 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
     }
 #pragma unroll
     for (int u0 = 0; u0 < EB; u0 += U) {
-      V ain[U], xin[U][4], lo[U];
+      // every element's loads are issued before any is used (an element past
+      // the tile reads its stand-in's values, which are inside the state; its
+      // results are dropped), and the low part is unpacked where it is used,
+      // so that no element's loads wait for an earlier element's
+      V ain[U], xin[U][4];
+      uint32_t lop[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int q = u0 + u;
-        ain[u] = V{0, 0};
-        lo[u] = V{0, 0};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) xin[u][i] = V{0, 0};
-        if (!ok[q]) continue;
-        const uint64_t gq = gidx_of(q);
-        if (accin) ain[u] = ldnt(accin + gq);
+        const uint64_t gq = gidx_of(u0 + u);
+        ain[u] = accin ? ldnt(accin + gq) : V{0, 0};
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          if (e.in[i]) xin[u][i] = ldnt(reinterpret_cast<const V*>(e.in[i]) + gq);
-        if (has_comp) {
-          const uint32_t p = __builtin_nontemporal_load(compv + gq);
-          lo[u] = V{(R)bf16_lo(p), (R)bf16_hi(p)};
-        }
+          xin[u][i] = e.in[i] ? ldnt(reinterpret_cast<const V*>(e.in[i]) + gq) : V{0, 0};
+        lop[u] = has_comp ? __builtin_nontemporal_load(compv + gq) : 0u;
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int q = u0 + u;
         if (!ok[q]) continue;
+        const V lo_u = V{(R)bf16_lo(lop[u]), (R)bf16_hi(lop[u])};
         const uint64_t g = gidx_of(q);
         const V uq = tile_of(q);
         // H u = diagonal term + flip sum + partial product of the high passes,
@@ -610,8 +607,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
           R vr = shh * ir + sll * ir;
           R vi = shh * ii + sll * ii;
           if (e.comp_flags & (1 << o)) {
-            vr += lo[u].x;
-            vi += lo[u].y;
+            vr += lo_u.x;
+            vi += lo_u.y;
           }
           const R bre = (R)e.c0[o] * xin[u][0].x + (R)e.cu[o] * uq.x;
           const R bim = (R)e.c0[o] * xin[u][0].y + (R)e.cu[o] * uq.y;
@@ -1751,32 +1748,38 @@ void k_sector(const SectorArgs a) {
     // the last filled buffer
     if (par) sector_hop_fma<R>(hr, hi, pa.v, pa.cr, pa.ci);
     else sector_hop_fma<R>(hr, hi, pb.v, pb.cr, pb.ci);
-    // epilogue: the same update as the last tile pass (see EpiDesc)
-#pragma unroll
-    for (int u = 0; u < kSecEPT; ++u) {
-      if (!ok[u]) continue;
-      const int64_t g = rf + u;
-      const V uq = src[g];
-      double d;
-      if constexpr (DS) {
-        d = a.dconst;
-#pragma unroll
-        for (int k = 0; k < kSecDiagStore; ++k)
-          if (k < s.dstore) d += a.dstore_f[k] * __builtin_nontemporal_load(s.dtab + k * s.dim + g);
-      } else {
-        d = sector_diag<W>(a, L, zs[u]);
-      }
-      const R hrr = (R)(d * (double)uq.x + (double)hr[u]);
-      const R hii = (R)(d * (double)uq.y + (double)hi[u]);
-      V xin[4];
+    // epilogue: the same update as the last tile pass (see EpiDesc).  With
+    // the diagonal kept per state, the streamed values of all the lane's
+    // states are loaded before any is used (a state past the end reads the
+    // last one; its results are dropped), so that no state's loads wait for
+    // another's; with the summed diagonal, whose loop needs the registers,
+    // state by state.  The low part is unpacked where it is used.
+    // (load_state is the first form's; its diagonal parts are read there.)
+    V uqv[kSecEPT], xinv[kSecEPT][4];
+    uint32_t lop[kSecEPT];
+    double dd[kSecEPT];
+    auto load_state = [&](int u) {
+      const int64_t g = min(rf + u, s.dim - 1);
+      uqv[u] = src[g];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
-        xin[i] = e.in[i] ? ldnt(reinterpret_cast<const V*>(e.in[i]) + g) : V{0, 0};
-      V lo{0, 0};
-      if (has_comp) {
-        const uint32_t pk = __builtin_nontemporal_load(compv + g);
-        lo = V{(R)bf16_lo(pk), (R)bf16_hi(pk)};
+        xinv[u][i] = e.in[i] ? ldnt(reinterpret_cast<const V*>(e.in[i]) + g) : V{0, 0};
+      lop[u] = has_comp ? __builtin_nontemporal_load(compv + g) : 0u;
+      if constexpr (DS) {
+        dd[u] = a.dconst;
+#pragma unroll
+        for (int k = 0; k < kSecDiagStore; ++k)
+          if (k < s.dstore) dd[u] += a.dstore_f[k] * __builtin_nontemporal_load(s.dtab + k * s.dim + g);
       }
+    };
+    auto update_state = [&](int u) {
+      const int64_t g = rf + u;
+      const V uq = uqv[u];
+      const double d = dd[u];
+      const R hrr = (R)(d * (double)uq.x + (double)hr[u]);
+      const R hii = (R)(d * (double)uq.y + (double)hi[u]);
+      const V (&xin)[4] = xinv[u];
+      const V lo = V{(R)bf16_lo(lop[u]), (R)bf16_hi(lop[u])};
 #pragma unroll
       for (int o = 0; o < 3; ++o) {
         if (!e.out[o]) continue;
@@ -1813,6 +1816,28 @@ void k_sector(const SectorArgs a) {
         }
       }
       if (e.red_flags & 4) r2 += (double)uq.x * (double)hrr + (double)uq.y * (double)hii;
+    };
+    if constexpr (DS) {
+#pragma unroll
+      for (int u = 0; u < kSecEPT; ++u) load_state(u);
+#pragma unroll
+      for (int u = 0; u < kSecEPT; ++u)
+        if (ok[u]) update_state(u);
+    } else {
+#pragma unroll
+      for (int u = 0; u < kSecEPT; ++u) {
+        if (!ok[u]) continue;
+        // the summed diagonal between the first load and the others, as its
+        // loop needs the registers
+        const int64_t g = rf + u;
+        uqv[u] = src[g];
+        dd[u] = sector_diag<W>(a, L, zs[u]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          xinv[u][i] = e.in[i] ? ldnt(reinterpret_cast<const V*>(e.in[i]) + g) : V{0, 0};
+        lop[u] = has_comp ? __builtin_nontemporal_load(compv + g) : 0u;
+        update_state(u);
+      }
     }
   }
   if (e.red_flags) block_reduce3<kSecThreads>(r0, r1, r2, e.red_flags, L.red, e.red, gridDim.x, blockIdx.x);
