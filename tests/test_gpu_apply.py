@@ -205,3 +205,55 @@ def test_apply_stream_groups(eng, dt, regpass, n, monkeypatch):
     if regpass == "0":
         assert ham.info()["n_passes"][0 if dt == "c64" else 1] == 1
     ham.free()
+
+
+def test_freed_tables_are_not_reused_under_queued_launches(eng):
+    """Table buffers of a freed Hamiltonian go to a pool and are handed out
+    again only once every stream the library launches on has passed the
+    release.  Products queued on one stream keep reading their tables while a
+    Hamiltonian of the same size is built (and uploaded) on another stream
+    right after the free; all of them must match the oracle.  The next
+    Hamiltonian built after the queue has drained may reuse the buffers, and
+    after aqc_trim new ones are allocated; both give the same product."""
+    import dataclasses
+    import torch
+    engine, _ = eng
+    from paper_1311_3938_amd import _lib
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    ca, cb = engine.Context(0, stream=sa), engine.Context(0, stream=sb)
+    inst = I.workload_sk_sin2(n=20, T=5.0, seed=21)
+    inst2 = dataclasses.replace(inst, w=inst.w * 2.0)
+    rng = np.random.default_rng(3)
+    psi = I.random_state(20, rng)
+    t = 1.1
+    want = sqh.apply_h(inst, t, psi)
+    x = to_dev(psi, "c128")
+    outs = [torch.empty_like(x) for _ in range(40)]
+    torch.cuda.synchronize()
+    ham = engine.Hamiltonian(ca, inst)
+    need = _lib.lib().aqc_apply_workspace_bytes(ham.handle, _lib.C128)
+    ws = engine.workspace(ca, need)
+    for o in outs:
+        engine.apply(ca, ham, t, x, out=o, ws=ws)
+    ham.free()                               # the products above are still queued on sa
+    ham2 = engine.Hamiltonian(cb, inst2)     # built and uploaded on sb meanwhile
+    sa.synchronize()
+    for o in outs:
+        assert rel_err(to_host(o), want) < APPLY_TOL["c128"]
+    ws2 = engine.workspace(cb, need)
+    out2 = engine.apply(cb, ham2, t, x, ws=ws2)
+    sb.synchronize()                         # results are read on the default stream
+    assert rel_err(to_host(out2), 2.0 * want) < APPLY_TOL["c128"]
+    ham2.free()
+    for rebuild in ("reused", "after trim"):
+        if rebuild == "after trim":
+            engine.trim(0)
+        h = engine.Hamiltonian(ca, inst)
+        out = engine.apply(ca, h, t, x, ws=ws)
+        sa.synchronize()
+        assert rel_err(to_host(out), want) < APPLY_TOL["c128"], rebuild
+        h.free()
+    sa.synchronize()
+    sb.synchronize()
+    ca.close()
+    cb.close()
