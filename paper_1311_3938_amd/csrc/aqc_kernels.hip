@@ -133,7 +133,8 @@ struct Lds {
   static constexpr int kLB = kLA + 8 * 128;                      // double LB[128]
   static constexpr int kGco = kLB + 8 * 128;                     // R gco[kMaxPassGroups]
   static constexpr int kGxl = kGco + 8 * kMaxPassGroups;         // u32 gxl[kMaxPassGroups]
-  static constexpr int kTm = kGxl + 4 * kMaxPassGroups;          // R tm[kMaxPassTerms]
+  static constexpr int kGfl = kGxl + 4 * kMaxPassGroups;         // u32 gfl[kMaxPassGroups]
+  static constexpr int kTm = kGfl + 4 * kMaxPassGroups;          // R tm[kMaxPassTerms]
   static constexpr int kTmd = kTm + 8 * kMaxPassTerms;           // double tmd[kMaxPassTerms]
   static constexpr int kTile = kTmd + 8 * kMaxPassTerms;         // V tile[2^tb]
 };
@@ -230,6 +231,11 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
   double* LB = reinterpret_cast<double*>(smem + Lds::kLB);
   R* gco = reinterpret_cast<R*>(smem + Lds::kGco);
   uint32_t* gxl = reinterpret_cast<uint32_t*>(smem + Lds::kGxl);
+  // per group: fslot + 1 (0: not a fast group) | li << 8 | lj << 16, so that
+  // the product loop finds a fast group's table without reading its
+  // descriptor from memory (a vector load, whose wait would also wait for
+  // the stores the pass has issued: one counter covers both)
+  uint32_t* gfl = reinterpret_cast<uint32_t*>(smem + Lds::kGfl);
   R* tm = reinterpret_cast<R*>(smem + Lds::kTm);
   V* tile = reinterpret_cast<V*>(smem + Lds::kTile);
 
@@ -338,6 +344,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
     // tile-local flip mask; bit 31 marks a group whose coefficient depends on
     // g, bit 30 one whose partner lies outside the tile (read from memory)
     gxl[tid] = gr.xl | (gr.plain ? 0u : 0x80000000u) | ((gr.x & ~tmask) ? 0x40000000u : 0u);
+    gfl[tid] = (uint32_t)(gr.fslot + 1) | ((uint32_t)gr.lij << 8);
   }
   if (isfast) {
     const int bi = gr.bij & 255, bj = gr.bij >> 8;
@@ -513,16 +520,17 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
           hi[u] += c * v.y;
         }
       } else {
-        const DevGroup gr = a.groups[k];
-        if (gr.fslot >= 0) {
+        const uint32_t fl = gfl[k];
+        if (fl & 255u) {
           // the table entry is 2 (s_i + 2 s_j) for the source's bits s_i, s_j,
           // bits li, lj of the partner's tile index
-          const uint32_t li = (uint32_t)gr.lij & 255u, lj = (uint32_t)gr.lij >> 8;
-          const uint32_t at = tidc ^ (gr.xl & (kThreads - 1u));
-          const R* fc = ftab + 8 * gr.fslot;
+          const uint32_t li = (fl >> 8) & 255u, lj = (fl >> 16) & 255u;
+          const uint32_t xl = gx & 0x3fffffffu;
+          const uint32_t at = tidc ^ (xl & (kThreads - 1u));
+          const R* fc = ftab + 8 * (int)((fl & 255u) - 1u);
 #pragma unroll
           for (int u = 0; u < EB; ++u) {
-            const uint32_t sl = at | ((jc_of(u) ^ (gr.xl >> kTidBits)) << kTidBits);
+            const uint32_t sl = at | ((jc_of(u) ^ (xl >> kTidBits)) << kTidBits);
             const uint32_t q = 2u * (__builtin_amdgcn_ubfe(sl, li, 1) | (__builtin_amdgcn_ubfe(sl, lj, 1) << 1));
             const R cr = fc[q], ci = fc[q + 1];
             const V v = tile[sl];
@@ -531,6 +539,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, const int64_t bid, 
           }
           continue;
         }
+        const DevGroup gr = a.groups[k];   // a group whose terms are summed per element
 #pragma unroll
         for (int u = 0; u < EB; ++u) {
           const uint32_t l = tidc + kThreads * jc_of(u);
