@@ -765,8 +765,10 @@ static aqc_status build_diag_tables(Plan& p, const aqc_ham* h, hipStream_t s) {
 // Pass layout (host only): the last pass tiles the low tbf bits; every other
 // flip pattern goes to a high pass whose tile is [0, lh) plus at most tbh - lh
 // further bits.
+// force_reg >= 0 overrides the register-pass mode (used to weigh the
+// library's choice against a layout without register passes).
 static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& out, int* tbf_out,
-                                bool tiles_only = false) {
+                                bool tiles_only = false, int force_reg = -1) {
   Tiling tl = default_tiling(dtype);
   tl.tbf = env_int(dtype == 0 ? "AQC_TBF_C64" : "AQC_TBF_C128", tl.tbf);
   tl.tbh = env_int(dtype == 0 ? "AQC_TBH_C64" : "AQC_TBH_C128", tl.tbh);
@@ -785,6 +787,7 @@ static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& 
     use_reg = 0;
     use_stream = false;
   }
+  if (force_reg >= 0) use_reg = force_reg;
   const int maxtb = dtype == 0 ? 14 : 13;
   if (tl.tbf < 1 || tl.tbf > maxtb || tl.tbh < 2 || tl.tbh > maxtb || tl.lh < 1 || tl.lh >= tl.tbh)
     return fail(AQC_EINVAL, "tiling parameters out of range");
@@ -923,6 +926,21 @@ static aqc_status layout_passes(const aqc_ham* h, int dtype, std::vector<Pass>& 
   for (Pass& ps : high) out.push_back(ps);
   out.push_back(last);
   *tbf_out = tbf;
+  // the library's choice of register passes: a layout without them wins when
+  // the tile high passes can take the single-qubit flips with fewer passes in
+  // all (each pass streams the state once; with pair flips above the tile,
+  // high passes are needed anyway and often have room for the single flips).
+  // Not with stream groups, which would take the single flips as re-reads.
+  if (use_reg == 1 && !use_stream && !regp.empty()) {
+    std::vector<Pass> alt;
+    int tbf_alt = 0;
+    const std::string err = g_last_error;   // a layout that cannot be built is only not taken
+    if (layout_passes(h, dtype, alt, &tbf_alt, tiles_only, 0) == AQC_OK && alt.size() < out.size()) {
+      out.swap(alt);
+      *tbf_out = tbf_alt;
+    }
+    g_last_error = err;
+  }
   return AQC_OK;
 }
 
