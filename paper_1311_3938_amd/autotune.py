@@ -39,10 +39,10 @@ CANDIDATES = {
 }
 
 BATCH_CANDIDATES = {
-    L.C64: [(tbf, tbh, lh, reg) for tbf in (12, 13) for (tbh, lh) in ((13, 4), (13, 6), (12, 4))
-            for reg in (3, 2)] + [(tbf, 13, 4, 7) for tbf in (12, 13)],
-    L.C128: [(tbf, tbh, lh, reg) for tbf in (11, 12) for (tbh, lh) in ((12, 3), (12, 5), (11, 3))
-             for reg in (3, 2)] + [(tbf, 12, 3, 7) for tbf in (11, 12)],
+    L.C64: [(tbf, tbh, lh, reg) for tbf in (12, 13) for (tbh, lh) in ((13, 4), (13, 5), (13, 6), (12, 4))
+            for reg in (3, 2, 0)] + [(tbf, 13, 4, 7) for tbf in (12, 13)],
+    L.C128: [(tbf, tbh, lh, reg) for tbf in (11, 12) for (tbh, lh) in ((12, 3), (12, 4), (12, 5), (11, 3))
+             for reg in (3, 2, 0)] + [(tbf, 12, 3, 7) for tbf in (11, 12)],
 }
 
 _lock = threading.Lock()
