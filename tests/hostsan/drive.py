@@ -142,10 +142,27 @@ def context_outlived_by_batch():
         ham.free()
 
 
+def plan_choice(ctx):
+    """The default plan keeps register passes for the single-qubit flips above
+    the last tile unless a layout without them needs fewer passes: the 24-qubit
+    SK workload (single flips only: two register passes or two tile high
+    passes, a tie) keeps them; the 24-qubit catalyst workload, whose pair
+    flips straddle the tile, needs 4 passes without them instead of 5."""
+    sk = engine.Hamiltonian(ctx, I.workload_sk_sin2(n=24))
+    assert sk.info()["n_passes"][0] == 3, sk.info()
+    sk.free()
+    cat = engine.Hamiltonian(ctx, I.workload_ec3_catalyst())
+    assert cat.info()["n_passes"][0] == 4, cat.info()
+    cat.set_tiling(torch.complex64, 13, 13, 4, 3)        # wide register passes asked for
+    assert cat.info()["n_passes"][0] == 5, cat.info()
+    cat.free()
+
+
 def main():
     lib().fake_hip_live.restype = C.c_long
     base = lib().fake_hip_live()
     ctx = CpuCtx()
+    plan_choice(ctx)
     insts = [I.workload_sk_sin2(n=12), I.workload_ec3_catalyst(n=14, m=12, n_pairs=10),
              I.workload_ec3_paths(n=13, kind="cbc"), I.workload_ec3_paths(n=13, kind="nonlinear"),
              I.workload_usa(10, 0, "xy"), I.workload_usa(10, 1, "xyz")]
