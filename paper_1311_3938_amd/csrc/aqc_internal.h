@@ -11,7 +11,7 @@ namespace aqc {
 
 constexpr int kMaxSched = 32;       // schedules per Hamiltonian
 constexpr int kMaxDiagSched = kMaxSched;  // schedules with split diagonal tables
-constexpr int kMaxTabSched = 4;     // schedules with a low-bit diagonal table
+constexpr int kMaxTabSched = kMaxSched;  // schedules with a low-bit diagonal table
 constexpr int kMaxPassGroups = 256;
 constexpr int kMaxPassTerms = 512;
 constexpr int kThreads = 512;       // threads per tile workgroup

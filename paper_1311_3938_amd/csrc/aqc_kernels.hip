@@ -207,9 +207,17 @@ __device__ __forceinline__ double diag_value(const PassArgs& a, uint32_t lo, uin
                                              const double* LA, const double* LB, const double* fsh) {
   double d = cprime + LA[lo & 127u] + LB[lo >> 7];
   const int64_t ntile = (int64_t)1 << a.tb;
+  // one table read per schedule: the first few unrolled, the rest (a path
+  // with a schedule per clause) in a loop
+  constexpr int kTabUnrolled = 4;
 #pragma unroll
-  for (int s = 0; s < kMaxTabSched; ++s) {
+  for (int s = 0; s < kTabUnrolled; ++s) {
     if (s < a.dg.ntab) d += fsh[a.dg.tab_sid[s]] * a.dg.TAB64[(int64_t)s * ntile + lo];
+  }
+#pragma unroll 1
+  for (int s = kTabUnrolled; s < a.dg.ntab; ++s) {
+    const double* tab = a.dg.TAB64 + (int64_t)s * ntile;   // uniform
+    d += fsh[a.dg.tab_sid[s]] * tab[lo];
   }
   for (int k = 0; k < a.dg.nres; ++k) {
     const DevTerm t = a.dg.res[k];

@@ -77,6 +77,38 @@ def test_apply_matches_oracle(eng, name, inst, dt):
 
 
 @pytest.mark.parametrize("dt", ["c128", "c64"])
+@pytest.mark.parametrize("exact", [True, False], ids=["quarter_weights", "normal_weights"])
+def test_apply_many_low_bit_diagonal_schedules(eng, dt, exact):
+    """Ten schedules, each with Z pairs and triples inside the last tile's low
+    bits (one diagonal table per schedule, the first four read unrolled and
+    the rest in a loop), beside single and straddling Z terms and flips;
+    weights that are multiples of 1/4 (as in exact-cover clauses) and normal
+    ones."""
+    engine, ctx = eng
+    rng = np.random.default_rng(77 if exact else 78)
+    n, ns = 16, 10
+    t = I.TermList(n)
+    for sid in range(ns):
+        for _ in range(4):
+            k = int(rng.integers(2, 4))
+            qs = rng.choice(10, k, replace=False)
+            w = float(rng.integers(-8, 9)) / 4.0 if exact else float(rng.normal())
+            t.add({int(q) + 1: "Z" for q in qs}, w, sid)
+        t.add({int(rng.integers(0, n)) + 1: "Z", int(rng.integers(12, n)) + 1: "Z"}, 0.5, sid)
+    for q in range(n):
+        t.add({q + 1: "X"}, 0.3 + 0.01 * q, ns)
+    scheds = [I.poly_s([0.1 * (j + 1), 1.0 - 0.15 * j]) for j in range(ns)] + [I.SCHED_ONE_MINUS_S]
+    inst = t.instance(scheds, I.linear_path(2.0))
+    ham = engine.Hamiltonian(ctx, inst)
+    psi = I.random_state(n, np.random.default_rng(6))
+    for tt in (0.4, 1.3):
+        want = sqh.apply_h(inst, tt, psi)
+        got = to_host(engine.apply(ctx, ham, tt, to_dev(psi, dt)))
+        assert rel_err(got, want) < APPLY_TOL[dt], (dt, exact, tt)
+    ham.free()
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64"])
 def test_apply_with_small_tiles_many_passes(eng, dt, monkeypatch):
     """Force tiny tiles so that flip patterns spread over many high passes."""
     engine, ctx = eng
