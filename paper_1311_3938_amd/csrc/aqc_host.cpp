@@ -431,7 +431,6 @@ struct Plan {
   double* dCT = nullptr;
   double* dLT = nullptr;
   double* dTAB64 = nullptr;
-  float* dTAB32 = nullptr;
   DevTerm* dres = nullptr;
 };
 
@@ -485,7 +484,6 @@ static void free_plan(Plan& p, int dev) {
   tab_release(dev, p.dCT);
   tab_release(dev, p.dLT);
   tab_release(dev, p.dTAB64);
-  tab_release(dev, p.dTAB32);
   tab_release(dev, p.dres);
   p = Plan();
 }
@@ -739,13 +737,11 @@ static aqc_status build_diag_tables(Plan& p, const aqc_ham* h, hipStream_t s) {
     for (int64_t lo = 0; lo < ntile; ++lo)
       TAB[(size_t)k * ntile + lo] += (popc((uint64_t)lo & u) & 1) ? -t.w : t.w;
   }
-  std::vector<float> TAB32(TAB.begin(), TAB.end());
   std::vector<DevTerm> dres;
   for (const HTerm& t : res) dres.push_back(DevTerm{t.z, t.w, t.sid, 0});
   STCHK(upload((void**)&p.dCT, CT.data(), CT.size() * sizeof(double), s));
   STCHK(upload((void**)&p.dLT, LT.data(), LT.size() * sizeof(double), s));
   STCHK(upload((void**)&p.dTAB64, TAB.data(), TAB.size() * sizeof(double), s));
-  STCHK(upload((void**)&p.dTAB32, TAB32.data(), TAB32.size() * sizeof(float), s));
   STCHK(upload((void**)&p.dres, dres.data(), dres.size() * sizeof(DevTerm), s));
   DiagDev& d = p.dg;
   d = DiagDev{};
@@ -757,7 +753,6 @@ static aqc_status build_diag_tables(Plan& p, const aqc_ham* h, hipStream_t s) {
   d.CT = p.dCT;
   d.LT = p.dLT;
   d.TAB64 = p.dTAB64;
-  d.TAB32 = p.dTAB32;
   d.res = p.dres;
   return AQC_OK;
 }

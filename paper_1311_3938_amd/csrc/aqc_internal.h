@@ -60,7 +60,6 @@ struct DiagDev {
   const double* CT;             // [nsd][2^(n-tb)]
   const double* LT;             // [nsd][2^(n-tb)][tb]
   const double* TAB64;          // [ntab][2^tb]
-  const float* TAB32;           // [ntab][2^tb]
   const DevTerm* res;           // [nres]
 };
 
