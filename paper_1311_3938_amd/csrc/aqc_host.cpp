@@ -499,6 +499,13 @@ extern "C" aqc_status aqc_ham_free(aqc_ham* h) {
   return AQC_OK;
 }
 
+// owner of a Hamiltonian under construction: an error return releases its
+// device tables with it
+struct HamFree {
+  void operator()(aqc_ham* h) const { aqc_ham_free(h); }
+};
+using HamPtr = std::unique_ptr<aqc_ham, HamFree>;
+
 static int popc(uint64_t v) { return __builtin_popcountll(v); }
 static aqc_status build_plan(aqc_ham* h, int dtype, hipStream_t s);
 
@@ -553,7 +560,7 @@ extern "C" aqc_status aqc_build_hamiltonian(aqc_ctx* ctx, int n, int64_t n_terms
       return fail(AQC_EINVAL, "aqc_build_hamiltonian: sched_id out of range");
     merged[std::make_tuple(xm[l], zm[l], (int)sid[l])] += w[l];
   }
-  std::unique_ptr<aqc_ham> h(new aqc_ham());
+  HamPtr h(new aqc_ham());
   h->n = n;
   h->dim = (int64_t)1 << n;
   h->device = ctx->device;
@@ -1645,7 +1652,7 @@ extern "C" aqc_status aqc_sector_create(aqc_ctx* ctx, const aqc_ham* src, int we
   if (weight < 0 || weight > n) return fail(AQC_EINVAL, "aqc_sector_create: weight outside 0..n");
   for (const GroupH& g : src->groups) STCHK(check_group_keeps_weight(g, (int)src->scheds.size()));
   HIPCHK(hipSetDevice(ctx->device));
-  std::unique_ptr<aqc_ham> h(new aqc_ham());
+  HamPtr h(new aqc_ham());
   h->n = n;
   h->device = src->device;
   h->scheds = src->scheds;

@@ -142,6 +142,39 @@ def context_outlived_by_batch():
         ham.free()
 
 
+def failed_builds_release_tables(ctx):
+    """A sector whose build fails at any of its device allocations returns an
+    error and leaves no device buffer behind (the partly built Hamiltonian
+    releases its tables), and the build then succeeds."""
+    engine.trim(0)
+    ham = engine.Hamiltonian(ctx, I.workload_usa(8, 0, "xy"))
+    engine.trim(0)
+    base = lib().fake_hip_live()
+    lib().fake_hip_fail_malloc_after.argtypes = [C.c_long]
+    failed = 0
+    for k in range(64):
+        lib().fake_hip_fail_malloc_after(k)
+        try:
+            sec = engine.Sector(ctx, ham, 3)
+        except L.AqcError as e:
+            lib().fake_hip_fail_malloc_after(-1)
+            assert e.status == L.AQC_EDEVICE, (k, e)
+            failed += 1
+            engine.trim(0)
+            live = lib().fake_hip_live() - base
+            assert live == 0, f"failed sector build ({k} allocations) left {live} handles"
+            continue
+        lib().fake_hip_fail_malloc_after(-1)
+        sec.free()
+        break
+    else:
+        raise AssertionError("the sector build never succeeded")
+    # the rank, hop, term and mask tables, and the stored diagonal
+    assert failed >= 5, failed
+    ham.free()
+    engine.trim(0)
+
+
 def plan_choice(ctx):
     """The default plan keeps register passes for the single-qubit flips above
     the last tile unless a layout without them needs fewer passes: the 24-qubit
@@ -251,6 +284,7 @@ def main():
     for h in (one, small, sk, big):
         h.free()
     host_error_paths(ctx)
+    failed_builds_release_tables(ctx)
     # the allocation-free energy refuses what its fixed scratch cannot hold
     # and plans that are not built yet
     for n, status in ((23, L.AQC_ENOMEM), (27, L.AQC_EINVAL)):

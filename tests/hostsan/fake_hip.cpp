@@ -113,7 +113,17 @@ hipError_t hipHostFree(void* p) { FAKE_LOCK;
   return hipSuccess;
 }
 hipError_t hipHostMalloc(void** p, size_t n, unsigned) { FAKE_LOCK; *p = calloc(1, n ? n : 1); g_host[*p] = n; return hipSuccess; }
-hipError_t hipMalloc(void** p, size_t n) { FAKE_LOCK; *p = calloc(1, n ? n : 1); g_dev[*p] = n; return hipSuccess; }
+// hipMalloc fails once after this many more successful calls (-1: never)
+static long g_malloc_fail = -1;
+hipError_t hipMalloc(void** p, size_t n) { FAKE_LOCK;
+  if (g_malloc_fail == 0) {
+    g_malloc_fail = -1;
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  if (g_malloc_fail > 0) --g_malloc_fail;
+  *p = calloc(1, n ? n : 1); g_dev[*p] = n; return hipSuccess;
+}
 hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) { FAKE_LOCK; memcpy(d, s, n); return hipSuccess; }
 hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t) { FAKE_LOCK; memcpy(d, s, n); return hipSuccess; }
 hipError_t hipSetDevice(int) { FAKE_LOCK; return hipSuccess; }
@@ -230,6 +240,9 @@ hipError_t launch_scale_copy(void*, const void*, int, int64_t, double, hipStream
 hipError_t launch_basis_transform(void*, int64_t, int64_t, int, int, const double*, int, hipStream_t) { FAKE_LOCK; return hipSuccess; }
 hipError_t launch_random_fill(void*, int, int64_t, uint64_t, hipStream_t) { FAKE_LOCK; return hipSuccess; }
 }  // namespace aqc
+
+// the next hipMalloc after k successful ones fails (k < 0: none fails)
+extern "C" void fake_hip_fail_malloc_after(long k) { FAKE_LOCK; g_malloc_fail = k; }
 
 // handles still alive (allocations, streams, events, graphs)
 extern "C" long fake_hip_live() { FAKE_LOCK;
