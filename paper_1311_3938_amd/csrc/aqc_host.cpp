@@ -340,7 +340,11 @@ extern "C" aqc_status aqc_create(int device, void* stream, aqc_ctx** out) {
   HIPCHK(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(AQC_EINVAL, "aqc_create: bad device index");
   HIPCHK(hipSetDevice(device));
-  std::unique_ptr<aqc_ctx> c(new aqc_ctx());
+  // an error return below destroys the context made so far
+  struct CtxFree {
+    void operator()(aqc_ctx* p) const { aqc_destroy(p); }
+  };
+  std::unique_ptr<aqc_ctx, CtxFree> c(new aqc_ctx());
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(stream);
   tab_stream_add(device, c->stream);

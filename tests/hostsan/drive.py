@@ -173,6 +173,16 @@ def failed_builds_release_tables(ctx):
     assert failed >= 5, failed
     ham.free()
     engine.trim(0)
+    # a context whose buffers cannot all be allocated
+    base = lib().fake_hip_live()
+    for k in range(2):
+        lib().fake_hip_fail_malloc_after(k)
+        out = C.c_void_p()
+        status = lib().aqc_create(0, None, C.byref(out))
+        lib().fake_hip_fail_malloc_after(-1)
+        assert status == L.AQC_EDEVICE and not out.value, (k, status)
+        live = lib().fake_hip_live() - base
+        assert live == 0, f"failed context creation ({k} allocations) left {live} handles"
 
 
 def plan_choice(ctx):
